@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Throughput of the fused chemical-potential LBM step on one MI355X.
+
+Workload (the plain-method FP32 configuration): 1024 x 1024 D2Q9 lattice,
+periodic in x, surface-chemical-potential wall below and neutral wall above,
+Peng-Robinson EOS (a = 2/49, b = 2/21, R = 1, omega = 0.344) at T = 0.8 Tc,
+tau = 1.3, kappa = 0.01, semicircular drop of radius 200 on the wall at the
+coexistence densities, wall mu drawn from a seeded uniform range.  A step is
+one fused update (moments, Eq 28 wall density, Eq 8 chemical potential, Eq 12
+force, Eqs 13-14 collision, streaming with bounce-back) plus the mass /
+residual / divergence monitors every 100 steps.
+
+Prints one JSON line: MLUPS (fluid-node updates per second / 1e6) with inputs
+resident in HBM, the roofline of the step kernel (72 algorithmic bytes per node
+update in FP32: nine loads and nine stores), and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+MONITOR_EVERY = 100
+KERNEL_SRC = os.path.join(ROOT, "paper_1611_00907_amd", "csrc", "lbm_kernels.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-aux", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def kernel_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def wetting_workload(lbm, inputs, prec):
+    nx = ny = 1024
+    p = lbm.make_params(nx, ny, lbm.LBM_EOS_PR, 2 / 49, 2 / 21, 0.8, 1.3, 0.01, omega=0.344, prec=prec,
+                        bc_bottom=lbm.LBM_BC_CPWALL, bc_top=lbm.LBM_BC_NEUTRAL)
+    rg, rl, _, mu_sat = lbm.lbm_coexistence(p)
+    rho0 = inputs.sessile_drop(nx, ny, rl, rg, 200.0)
+    # one draw from the wetting range suggested by the paper's Fig. 2 span around mu_sat
+    mu_w = float(inputs.draw_uniform(2, mu_sat - 0.18, mu_sat + 0.23, 1)[0])
+    return p, rho0, mu_w, nx * (ny - 2)
+
+
+def spinodal_workload(lbm, inputs, prec, n=4096):
+    p = lbm.make_params(n, n, lbm.LBM_EOS_VDW, 9 / 49, 2 / 21, 0.85, 1.0, 0.01, prec=prec)
+    _, rc, _ = lbm.lbm_critical_point(lbm.LBM_EOS_VDW, 9 / 49, 2 / 21, 1.0)
+    rho0 = inputs.with_relative_noise(np.full((n, n), rc), 0.01, 3)
+    return p, rho0, None, n * n
+
+
+def timed(torch, fn, reps: int) -> float:
+    """Seconds for fn() run reps times, bracketed by synchronisations, measured with
+    HIP events on the current stream (the one the library launches on)."""
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / 1e3
+
+
+def traffic_for(workload: str, bytes_per_launch: float):
+    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE counts,
+    if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_sha") != kernel_sha():
+        return None
+    return (d["fetch_kib_per_dispatch"] + d["write_kib_per_dispatch"]) * 1024.0 * d.get("copy_factor", 1.0)
+
+
+def measure(lbm, torch, p, rho0, mu_w, fluid_nodes, steps, warmup, bytes_per_lu, workload):
+    lat = lbm.Lattice(p, rho0)
+    if mu_w is not None:
+        lat.set_wall_mu(0, mu_w)
+    lat.step(warmup)
+    # kernel-only: back-to-back fused steps, no monitors
+    k_steps = max(steps, 100)
+    t_kernel = timed(torch, lambda: lat.step(k_steps), 1) / k_steps
+    # whole step: fused update plus monitors every MONITOR_EVERY steps
+    chunks = max(steps // MONITOR_EVERY, 1)
+
+    def chunk():
+        lat.step(MONITOR_EVERY - 1)
+        lat.monitor_step()
+
+    t_total = timed(torch, chunk, chunks)
+    n_steps = chunks * MONITOR_EVERY
+    mon = lat.monitors()
+    lat.close()
+    achieved = fluid_nodes * bytes_per_lu / t_kernel / 1e9
+    traffic = traffic_for(workload, fluid_nodes * bytes_per_lu)
+    return {
+        "mlups": fluid_nodes * n_steps / t_total / 1e6,
+        "ms_per_step": t_total / n_steps * 1e3,
+        "steps": n_steps,
+        "kernel_us": t_kernel * 1e6,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic},
+        "monitor": {"mass": mon["mass"], "residual": mon["residual"], "flags": mon["flags"]},
+    }
+
+
+def cpu_baseline(seconds: float):
+    """The FP64 oracle on the same 1024^2 wetting workload, timed on the host cores."""
+    from oracle import thermo
+    from oracle.lattice import CPWALL, NEUTRAL, OracleLattice, OracleParams, max_threads
+    from paper_1611_00907_amd import inputs
+
+    nx = ny = 1024
+    op = OracleParams.from_reduced(nx, ny, thermo.PR, 2 / 49, 2 / 21, 0.8, 1.3, 0.01, omega=0.344,
+                                   bottom=CPWALL, top=NEUTRAL)
+    rg, rl, _, mu_sat = thermo.maxwell(op.fluid())
+    ora = OracleLattice(op, inputs.sessile_drop(nx, ny, rl, rg, 200.0), mu_w_bottom=mu_sat)
+    t1 = ora.timed_steps(2) / 2
+    n = max(2, int(seconds / max(t1, 1e-6)))
+    t = ora.timed_steps(n)
+    fluid = nx * (ny - 2)
+    return {"value": round(fluid * n / t / 1e6, 3), "unit": "MLUPS", "cores": max_threads(),
+            "kind": "oracle",
+            "sample": "%d steps of the 1024x1024 wetting workload in FP64 (%.1f s)" % (n, t)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1611_00907_amd import inputs, lbm
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    lbm.load_library()
+
+    p, rho0, mu_w, fluid = wetting_workload(lbm, inputs, lbm.LBM_F32)
+    main_res = measure(lbm, torch, p, rho0, mu_w, fluid, args.steps, args.warmup, 72.0,
+                       "step_f32_wetting1024")
+    print("main: %.1f MLUPS, kernel %.2f us, %.1f GB/s" % (main_res["mlups"], main_res["kernel_us"],
+                                                          main_res["roofline"]["achieved"]),
+          file=sys.stderr, flush=True)
+
+    aux = []
+    if not args.no_aux:
+        for prec, name, b in ((lbm.LBM_F32, "f32", 72.0), (lbm.LBM_F16DEV, "f16dev", 36.0),
+                              (lbm.LBM_BF16DEV, "bf16dev", 36.0)):
+            pp, r0, _, fl = spinodal_workload(lbm, inputs, prec)
+            res = measure(lbm, torch, pp, r0, None, fl, 300, 20, b, "step_%s_spinodal4096" % name)
+            aux.append({"workload": "spinodal 4096x4096 VdW Tr=0.85, %s storage" % name,
+                        "mlups": round(res["mlups"], 1), "kernel_us": round(res["kernel_us"], 2),
+                        "roofline": res["roofline"]})
+            print("aux %s: %.1f MLUPS %.1f GB/s" % (name, res["mlups"], res["roofline"]["achieved"]),
+                  file=sys.stderr, flush=True)
+
+    line = {
+        "metric": "MLUPS + % HBM roofline; time-to-equilibrium (surrogate vs plain) at 0.5deg",
+        "value": round(main_res["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": main_res["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "wetting 1024x1024 D2Q9, PR omega=0.344 Tr=0.8, tau=1.3, kappa=0.01, "
+                               "CP wall + neutral top, drop R=200, monitors every 100 steps",
+                   "nx": 1024, "ny": 1024, "storage": "f32", "parallelism": "single GPU"},
+        "roofline": main_res["roofline"],
+        "kernel_us": round(main_res["kernel_us"], 3),
+        "aux": aux,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * lbm.h - C ABI of the MI355X chemical-potential lattice Boltzmann library.
+ *
+ * Method: Wen, Zhou, He, Zhang, Fang, "Chemical-potential-based lattice
+ * Boltzmann method for nonideal fluids" (arXiv:1611.00907).  One time step
+ * takes the moments of the D2Q9 distributions (Eq 13 state), the chemical
+ * potential mu = psi'(rho) - kappa lap(rho) (Eq 8, bulk terms Eqs 18, 21, 24,
+ * 27), the nonideal force F = -rho grad(mu) + c_s^2 grad(rho) (Eq 12 with the
+ * ideal-gas tensor of Eq 5), the BGK collision of Eq 13 with the equilibrium
+ * of Eq 14 evaluated at u + tau F / rho (forcing paragraph after Eq 14), and
+ * streaming with bounce-back at solid rows whose density follows Eq 28 and
+ * whose chemical potential is the surface value (Sec. IV) or, for a neutral
+ * wall, that of the neighbouring fluid node (Sec. V).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns lbm_status; nothing is thrown across the ABI.  A NULL
+ *    context or required pointer gives LBM_EINVAL.
+ *  - Fields are row-major [ny][nx] arrays of double, x fastest, host memory
+ *    owned by the caller; solid rows are included.
+ *  - Distributions are [9][ny][nx] doubles, direction order
+ *    0 (0,0), 1 (1,0), 2 (0,1), 3 (-1,0), 4 (0,-1), 5 (1,1), 6 (-1,1),
+ *    7 (-1,-1), 8 (1,-1); they are the post-streaming values f_i(x, t) of
+ *    Eq 13, and zero on solid rows.
+ *  - Device memory: the caller may pass a workspace of at least
+ *    lbm_workspace_bytes() bytes (it keeps ownership and must keep it alive
+ *    until lbm_destroy); NULL makes the library allocate and free its own.
+ *  - A context belongs to one HIP stream (the one given at init; NULL = the
+ *    null stream) and is not thread-safe.  lbm_step is asynchronous except at
+ *    monitor points; the getters synchronise the stream.
+ *  - x is always periodic.  y is periodic when both bc_bottom and bc_top are
+ *    LBM_BC_PERIODIC; otherwise rows 0 and ny-1 are both solid.
+ */
+#ifndef CPLBM_LBM_H
+#define CPLBM_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,    /* bad argument or parameter                               */
+    LBM_EDOMAIN = -2,   /* an initial density outside the EOS domain, or non-finite */
+    LBM_EDIVERGED = -3, /* monitor found NaN/Inf, rho <= 0 or rho beyond the EOS pole */
+    LBM_EHIP = -4,      /* a HIP runtime call failed                               */
+    LBM_ENOMEM = -5,    /* workspace too small or device allocation failed         */
+    LBM_ESTATE = -6     /* call not valid in the current state                    */
+} lbm_status;
+
+/* Equations of state of Sec. III. */
+typedef enum {
+    LBM_EOS_VDW = 0, /* Eqs 16-18                                  */
+    LBM_EOS_CS = 1,  /* Carnahan-Starling, Eqs 25-27                */
+    LBM_EOS_PR = 2,  /* Peng-Robinson, Eqs 22-24, Soave-type alpha  */
+    LBM_EOS_RKS = 3, /* Redlich-Kwong-Soave, Eqs 19-21              */
+    LBM_EOS_RK = 4   /* Redlich-Kwong, alpha = 1/sqrt(T)            */
+} lbm_eos;
+
+/* Storage of the distributions; arithmetic is FP64 for LBM_F64, else FP32. */
+typedef enum {
+    LBM_F64 = 0,
+    LBM_F32 = 1,
+    LBM_F16DEV = 2,  /* f_i - w_i rho_ref stored as IEEE half, round to nearest even */
+    LBM_BF16DEV = 3  /* f_i - w_i rho_ref stored as bfloat16, round to nearest even  */
+} lbm_prec;
+
+typedef enum {
+    LBM_BC_PERIODIC = 0,
+    LBM_BC_CPWALL = 1,  /* solid row: Eq 28 density, surface chemical potential mu_w (Sec. IV) */
+    LBM_BC_NEUTRAL = 2  /* solid row: Eq 28 density, mu of the neighbouring fluid node (Sec. V) */
+} lbm_bc;
+
+typedef struct {
+    int32_t nx, ny;         /* lattice nodes including solid rows; nx >= 1, ny >= 1 (>= 3 walled) */
+    int32_t bc_bottom;      /* lbm_bc of row 0                                                   */
+    int32_t bc_top;         /* lbm_bc of row ny-1                                                */
+    int32_t eos;            /* lbm_eos                                                           */
+    int32_t prec;           /* lbm_prec                                                          */
+    double a, b, R;         /* EOS constants (Sec. III: a attraction, b volume, R gas constant)  */
+    double omega;           /* acentric factor (PR, RKS)                                         */
+    double Tr;              /* reduced temperature T / Tc; Tc is solved by the library           */
+    double tau;             /* relaxation time of Eq 13, > 1/2                                   */
+    double kappa;           /* gradient coefficient of Eq 1, >= 0                                */
+    double rho_ref;         /* deviation base of the FP16/BF16 storage (ignored otherwise)       */
+    int32_t monitor_every;  /* evaluate mass / residual / divergence every m steps; 0 = never    */
+    int32_t reserved;       /* must be 0                                                         */
+} lbm_params;
+
+/* Bytes of device workspace that lbm_init needs for these parameters (0 if invalid). */
+size_t lbm_workspace_bytes(const lbm_params* p);
+
+/* Sets up a lattice: T = Tr * Tc, alpha(T), and f_i = f_i^eq(rho0, u0) of Eq 14.
+ * rho0 is required; ux0, uy0 may be NULL (fluid at rest).  Values on solid rows
+ * are ignored.  Errors: LBM_EINVAL (parameters), LBM_EDOMAIN (a fluid rho0 that
+ * is not finite, <= 0, or at or beyond 1/b (4/b for CS)), LBM_ENOMEM, LBM_EHIP.
+ * Wall chemical potentials start at 0. */
+lbm_status lbm_init(const lbm_params* p, const double* rho0, const double* ux0,
+                    const double* uy0, void* dev_workspace, size_t workspace_bytes,
+                    void* hip_stream, lbm_ctx** out);
+
+/* Advances n >= 0 time steps (Eqs 8, 12, 13, 14, 28).  With monitor_every = m > 0
+ * the monitors are evaluated on each step whose count is a multiple of m; a
+ * non-finite density, rho <= 0 or rho beyond the EOS pole returns LBM_EDIVERGED
+ * and the steps that follow it are not run. */
+lbm_status lbm_step(lbm_ctx* c, int64_t n);
+
+/* Output fields of the current state into host arrays [ny][nx]: density (Eq 28
+ * values on solid rows), physical velocity v = u + F / (2 rho) (forcing
+ * paragraph after Eq 14; 0 on solid rows), and chemical potential (Eq 8; the
+ * wall value on solid rows).  Any pointer may be NULL.  Synchronises. */
+lbm_status lbm_get_fields(lbm_ctx* c, double* rho, double* vx, double* vy, double* mu);
+
+/* Surface chemical potential of a CP wall (Sec. IV): wall 0 = bottom, 1 = top;
+ * count 1 sets every column, count nx sets one value per column.  Takes effect
+ * from the next step.  LBM_EINVAL if the wall is not LBM_BC_CPWALL. */
+lbm_status lbm_set_wall_mu(lbm_ctx* c, int32_t wall, const double* mu_w, int32_t count);
+
+/* Last monitor values: total fluid mass, max |rho(t) - rho(t-1)| over fluid nodes,
+ * the step they were taken at (-1 if never), and the divergence flags
+ * (bit 0 non-finite, bit 1 rho <= 0, bit 2 rho beyond the EOS pole).  Any pointer
+ * may be NULL. */
+lbm_status lbm_get_monitors(lbm_ctx* c, double* mass, double* residual, int64_t* step,
+                            int32_t* flags);
+
+/* Evaluates the monitors now, on the current state and the step before it (runs
+ * two steps' worth of work: it advances the lattice by one step). */
+lbm_status lbm_monitor_step(lbm_ctx* c);
+
+/* Checkpoint: the distributions f_i(x, t) [9][ny][nx] and the step count. */
+lbm_status lbm_get_state(lbm_ctx* c, double* f, int64_t* step);
+lbm_status lbm_set_state(lbm_ctx* c, const double* f, int64_t step);
+
+/* Temperature actually used: T = Tr * Tc and alpha(T). */
+lbm_status lbm_get_temperature(lbm_ctx* c, double* T, double* alpha);
+
+void lbm_destroy(lbm_ctx* c);
+const char* lbm_strerror(lbm_status s);
+
+/* ---- host thermodynamics tools (FP64) ---------------------------------- */
+
+/* Critical point of an EOS (Sec. III reduced variables): dp0/drho = d2p0/drho2 = 0.
+ * For PR and RKS alpha(Tc) = 1; for RK alpha = 1/sqrt(T). */
+lbm_status lbm_critical_point(int32_t eos, double a, double b, double R, double* Tc,
+                              double* rho_c, double* p_c);
+
+/* Maxwell equal-area coexistence of the fluid in p (Sec. III, Fig. 1):
+ * mu_b(rho_g) = mu_b(rho_l) and p0(rho_g) = p0(rho_l).  LBM_EDOMAIN if Tr >= 1. */
+lbm_status lbm_coexistence(const lbm_params* p, double* rho_g, double* rho_l, double* p_sat,
+                           double* mu_sat);
+
+/* Bulk chemical potential psi'(rho) and pressure p0(rho) of the fluid in p at n
+ * densities (host, FP64). */
+lbm_status lbm_eos_eval(const lbm_params* p, int64_t n, const double* rho, double* mu_b,
+                        double* p0);
+
+/* Contact angle of a sessile drop (Sec. V): R = (4H^2 + L^2)/(8H),
+ * tan(theta) = L / (2 (R - H)), evaluated as atan2 so that theta > 90 deg works.
+ * rho is [ny][nx]; the interface is the rho_mid isoline; L is the liquid width on
+ * base_row (edges linearly interpolated), H the height of the top crossing on the
+ * column nearest the drop's centre of excess mass, measured from surface_y.
+ * theta = 180 when the drop does not wet base_row.  Outputs may be NULL. */
+lbm_status lbm_contact_angle(const double* rho, int32_t nx, int32_t ny, int32_t base_row,
+                             double surface_y, double rho_mid, double* theta_deg, double* L,
+                             double* H);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPLBM_LBM_H */

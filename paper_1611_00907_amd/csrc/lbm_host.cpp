@@ -1,0 +1,454 @@
+// C ABI of the chemical-potential lattice Boltzmann library (declared in lbm.h).
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+#include "thermo_host.h"
+
+using namespace cplbm;
+
+struct lbm_ctx {
+    lbm_params p;
+    LatticeArgs A;
+    thermo::Fluid fluid;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    char* ws = nullptr;
+    bool own_ws = false;
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    void* rho_mon = nullptr;
+    void* mu_w = nullptr;
+    double* partials = nullptr;
+    double* mon_dev = nullptr;
+    double* mon_host = nullptr;  // pinned
+    int64_t step = 0;
+    int64_t snap_step = -1;
+    double mass = NAN, residual = NAN;
+    int64_t mon_step = -1;
+    int32_t flags = 0;
+    std::vector<double> mu_w_host;  // [2][nx]
+};
+
+namespace {
+
+constexpr int PITCH_ALIGN = 64;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    int pitch;
+    long long plane;
+    size_t f0, f1, rho_mon, mu_w, partials, mon, total;
+};
+
+bool walled(const lbm_params& p) { return p.bc_bottom != LBM_BC_PERIODIC; }
+
+lbm_status validate(const lbm_params* p) {
+    if (!p) return LBM_EINVAL;
+    if (p->nx < 1 || p->ny < 1) return LBM_EINVAL;
+    if (p->bc_bottom < 0 || p->bc_bottom > 2 || p->bc_top < 0 || p->bc_top > 2) return LBM_EINVAL;
+    if ((p->bc_bottom == LBM_BC_PERIODIC) != (p->bc_top == LBM_BC_PERIODIC)) return LBM_EINVAL;
+    if (walled(*p) && p->ny < 3) return LBM_EINVAL;
+    if (p->eos < 0 || p->eos > 4 || p->prec < 0 || p->prec > 3) return LBM_EINVAL;
+    const double vals[] = {p->a, p->b, p->R, p->omega, p->Tr, p->tau, p->kappa, p->rho_ref};
+    for (double v : vals)
+        if (!std::isfinite(v)) return LBM_EINVAL;
+    if (p->a < 0 || p->b <= 0 || p->R <= 0 || p->Tr <= 0 || p->tau <= 0.5 || p->kappa < 0) return LBM_EINVAL;
+    if (p->monitor_every < 0 || p->reserved != 0) return LBM_EINVAL;
+    const long long pitch = ((long long)p->nx + PITCH_ALIGN - 1) / PITCH_ALIGN * PITCH_ALIGN;
+    if (pitch * (long long)p->ny > INT_MAX) return LBM_EINVAL;  // in-plane offsets are 32-bit
+    return LBM_OK;
+}
+
+Layout layout_of(const lbm_params& p) {
+    Layout L{};
+    L.pitch = (p.nx + PITCH_ALIGN - 1) / PITCH_ALIGN * PITCH_ALIGN;
+    L.plane = (long long)L.pitch * p.ny;
+    const size_t sb = storage_bytes(p.prec), cb = compute_bytes(p.prec);
+    const size_t fbytes = align256(9 * size_t(L.plane) * sb);
+    size_t o = 0;
+    L.f0 = o;
+    o += fbytes;
+    L.f1 = o;
+    o += fbytes;
+    L.rho_mon = o;
+    o += align256(size_t(L.plane) * cb);
+    L.mu_w = o;
+    o += align256(2 * size_t(L.pitch) * cb);
+    L.partials = o;
+    o += align256(3 * 1024 * sizeof(double));
+    L.mon = o;
+    o += align256(4 * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+LatticeArgs lattice_args(const lbm_params& p, const thermo::Fluid& fl, const Layout& L) {
+    LatticeArgs A{};
+    A.nx = p.nx;
+    A.ny = p.ny;
+    A.pitch = L.pitch;
+    A.bottom = p.bc_bottom;
+    A.top = p.bc_top;
+    A.tiles_x = (p.nx + TILE_X - 1) / TILE_X;
+    A.tiles_y = (p.ny + TILE_Y - 1) / TILE_Y;
+    A.plane = L.plane;
+    A.tau = p.tau;
+    A.inv_tau = 1.0 / p.tau;
+    A.kappa = p.kappa;
+    A.rho_ref = (p.prec == LBM_F16DEV || p.prec == LBM_BF16DEV) ? p.rho_ref : 0.0;
+    EosConst& E = A.eos;
+    E.RT = fl.R * fl.T;
+    E.b = fl.b;
+    E.rho_max = thermo::rho_pole(fl.eos, fl.b);
+    switch (fl.eos) {
+    case LBM_EOS_VDW:
+        E.a = fl.a;
+        E.c1 = 0.0;
+        break;
+    case LBM_EOS_CS:
+        E.a = fl.a;
+        E.c1 = fl.b / 4.0;
+        break;
+    case LBM_EOS_PR:
+        E.a = fl.a * fl.alpha;
+        E.c1 = fl.a * fl.alpha / (2.0 * std::sqrt(2.0) * fl.b);
+        break;
+    default:
+        E.a = fl.a * fl.alpha;
+        E.c1 = fl.a * fl.alpha / fl.b;
+    }
+    return A;
+}
+
+lbm_status hip_status(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return LBM_EHIP;          \
+    } while (0)
+
+bool is_solid_row(const lbm_params& p, int y) { return walled(p) && (y == 0 || y == p.ny - 1); }
+
+// Monitor pass over the current state; compare == 1 also reads the results back.
+lbm_status run_monitor(lbm_ctx* c, int compare) {
+    HIP_TRY(launch_monitor(c->p.prec, c->p.eos, compare, c->A, c->f[c->cur], c->rho_mon, c->partials,
+                           c->mon_dev, c->stream));
+    c->snap_step = c->step;
+    if (!compare) return LBM_OK;
+    HIP_TRY(hipMemcpyAsync(c->mon_host, c->mon_dev, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->mass = c->mon_host[0];
+    c->residual = c->mon_host[1];
+    c->flags = (int32_t)c->mon_host[2];
+    c->mon_step = c->step;
+    return c->flags ? LBM_EDIVERGED : LBM_OK;
+}
+
+lbm_status one_step(lbm_ctx* c) {
+    HIP_TRY(launch_step(c->p.prec, c->p.eos, MODE_STEP, c->A, c->f[c->cur], c->f[c->cur ^ 1], c->mu_w, nullptr,
+                        c->stream));
+    c->cur ^= 1;
+    ++c->step;
+    return LBM_OK;
+}
+
+lbm_status upload_mu_w(lbm_ctx* c) {
+    const int nx = c->p.nx, pitch = c->A.pitch;
+    if (c->p.prec == LBM_F64) {
+        std::vector<double> buf(2 * (size_t)pitch, 0.0);
+        for (int w = 0; w < 2; ++w)
+            for (int x = 0; x < nx; ++x) buf[(size_t)w * pitch + x] = c->mu_w_host[(size_t)w * nx + x];
+        HIP_TRY(hipMemcpyAsync(c->mu_w, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> buf(2 * (size_t)pitch, 0.0f);
+        for (int w = 0; w < 2; ++w)
+            for (int x = 0; x < nx; ++x) buf[(size_t)w * pitch + x] = (float)c->mu_w_host[(size_t)w * nx + x];
+        HIP_TRY(hipMemcpyAsync(c->mu_w, buf.data(), buf.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    return LBM_OK;
+}
+
+void release(lbm_ctx* c) {
+    if (!c) return;
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    if (c->mon_host) (void)hipHostFree(c->mon_host);
+    delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_params* p) {
+    if (validate(p) != LBM_OK) return 0;
+    return layout_of(*p).total;
+}
+
+lbm_status lbm_init(const lbm_params* p, const double* rho0, const double* ux0, const double* uy0,
+                    void* dev_workspace, size_t workspace_bytes, void* hip_stream, lbm_ctx** out) {
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    lbm_status st = validate(p);
+    if (st != LBM_OK) return st;
+    if (!rho0) return LBM_EINVAL;
+    const thermo::Fluid fl = thermo::make_fluid(p->eos, p->a, p->b, p->R, p->Tr, p->omega);
+    if (!(std::isfinite(fl.T) && fl.T > 0 && std::isfinite(fl.alpha))) return LBM_EINVAL;
+    const double pole = thermo::rho_pole(p->eos, p->b);
+    const size_t n = (size_t)p->nx * p->ny;
+    for (int y = 0; y < p->ny; ++y) {
+        if (is_solid_row(*p, y)) continue;
+        for (int x = 0; x < p->nx; ++x) {
+            const size_t i = (size_t)y * p->nx + x;
+            const double r = rho0[i];
+            if (!(std::isfinite(r) && r > 0.0 && r < pole)) return LBM_EDOMAIN;
+            if ((ux0 && !std::isfinite(ux0[i])) || (uy0 && !std::isfinite(uy0[i]))) return LBM_EDOMAIN;
+        }
+    }
+    const Layout L = layout_of(*p);
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return LBM_ENOMEM;
+    c->p = *p;
+    c->fluid = fl;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        release(c);
+        return LBM_EHIP;
+    }
+    if (dev_workspace) {
+        if (workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(dev_workspace) & 255)) {
+            release(c);
+            return workspace_bytes < L.total ? LBM_ENOMEM : LBM_EINVAL;
+        }
+        c->ws = static_cast<char*>(dev_workspace);
+    } else {
+        if (hipMalloc(&c->ws, L.total) != hipSuccess) {
+            release(c);
+            return LBM_ENOMEM;
+        }
+        c->own_ws = true;
+    }
+    if (hipHostMalloc(&c->mon_host, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        release(c);
+        return LBM_EHIP;
+    }
+    c->f[0] = c->ws + L.f0;
+    c->f[1] = c->ws + L.f1;
+    c->rho_mon = c->ws + L.rho_mon;
+    c->mu_w = c->ws + L.mu_w;
+    c->partials = reinterpret_cast<double*>(c->ws + L.partials);
+    c->mon_dev = reinterpret_cast<double*>(c->ws + L.mon);
+    c->A = lattice_args(*p, fl, L);
+    c->mu_w_host.assign(2 * (size_t)p->nx, 0.0);
+
+    // f(0) = f_eq(rho0, u0), stored in the pulled form.
+    double* staging = nullptr;
+    const size_t sbytes = n * sizeof(double);
+    hipError_t e = hipMalloc(&staging, 3 * sbytes);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(staging, rho0, sbytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && ux0) e = hipMemcpyAsync(staging + n, ux0, sbytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && uy0) e = hipMemcpyAsync(staging + 2 * n, uy0, sbytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = launch_init(p->prec, c->A, staging, ux0 ? staging + n : nullptr, uy0 ? staging + 2 * n : nullptr,
+                        nullptr, c->f[0], c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (staging) (void)hipFree(staging);
+    if (e != hipSuccess) {
+        release(c);
+        return LBM_EHIP;
+    }
+    st = upload_mu_w(c);
+    if (st != LBM_OK) {
+        release(c);
+        return st;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+    if (!c || n < 0) return LBM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LBM_EHIP;
+    const int m = c->p.monitor_every;
+    for (int64_t s = 0; s < n; ++s) {
+        if (m > 0 && (c->step + 1) % m == 0 && c->snap_step != c->step) {
+            lbm_status st = run_monitor(c, 0);
+            if (st != LBM_OK) return st;
+        }
+        lbm_status st = one_step(c);
+        if (st != LBM_OK) return st;
+        if (m > 0 && c->step % m == 0) {
+            st = run_monitor(c, 1);
+            if (st != LBM_OK) return st;
+        }
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_monitor_step(lbm_ctx* c) {
+    if (!c) return LBM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LBM_EHIP;
+    lbm_status st = run_monitor(c, 0);
+    if (st != LBM_OK) return st;
+    st = one_step(c);
+    if (st != LBM_OK) return st;
+    return run_monitor(c, 1);
+}
+
+lbm_status lbm_get_fields(lbm_ctx* c, double* rho, double* vx, double* vy, double* mu) {
+    if (!c) return LBM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LBM_EHIP;
+    const size_t n = (size_t)c->p.nx * c->p.ny;
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, 4 * n * sizeof(double)));
+    hipError_t e = launch_step(c->p.prec, c->p.eos, MODE_FIELDS, c->A, c->f[c->cur], nullptr, c->mu_w, d, c->stream);
+    double* outs[4] = {rho, vx, vy, mu};
+    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+        if (outs[k]) e = hipMemcpyAsync(outs[k], d + k * n, n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d);
+    return hip_status(e);
+}
+
+lbm_status lbm_set_wall_mu(lbm_ctx* c, int32_t wall, const double* mu_w, int32_t count) {
+    if (!c || !mu_w || (wall != 0 && wall != 1)) return LBM_EINVAL;
+    const int kind = wall == 0 ? c->p.bc_bottom : c->p.bc_top;
+    if (kind != LBM_BC_CPWALL) return LBM_EINVAL;
+    if (count != 1 && count != c->p.nx) return LBM_EINVAL;
+    for (int i = 0; i < count; ++i)
+        if (!std::isfinite(mu_w[i])) return LBM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LBM_EHIP;
+    for (int x = 0; x < c->p.nx; ++x) c->mu_w_host[(size_t)wall * c->p.nx + x] = mu_w[count == 1 ? 0 : x];
+    return upload_mu_w(c);
+}
+
+lbm_status lbm_get_monitors(lbm_ctx* c, double* mass, double* residual, int64_t* step, int32_t* flags) {
+    if (!c) return LBM_EINVAL;
+    if (mass) *mass = c->mass;
+    if (residual) *residual = c->residual;
+    if (step) *step = c->mon_step;
+    if (flags) *flags = c->flags;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_state(lbm_ctx* c, double* f, int64_t* step) {
+    if (!c || !f) return LBM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LBM_EHIP;
+    const size_t n = 9 * (size_t)c->p.nx * c->p.ny;
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, n * sizeof(double)));
+    hipError_t e = launch_get_state(c->p.prec, c->A, c->f[c->cur], d, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(f, d, n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d);
+    if (e == hipSuccess && step) *step = c->step;
+    return hip_status(e);
+}
+
+lbm_status lbm_set_state(lbm_ctx* c, const double* f, int64_t step) {
+    if (!c || !f || step < 0) return LBM_EINVAL;
+    const size_t plane = (size_t)c->p.nx * c->p.ny;
+    const size_t n = 9 * plane;
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(f[i])) return LBM_EDOMAIN;
+    if (hipSetDevice(c->device) != hipSuccess) return LBM_EHIP;
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, n * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(d, f, n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_init(c->p.prec, c->A, nullptr, nullptr, nullptr, d, c->f[c->cur], c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return LBM_EHIP;
+    c->step = step;
+    c->snap_step = -1;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_temperature(lbm_ctx* c, double* T, double* alpha) {
+    if (!c) return LBM_EINVAL;
+    if (T) *T = c->fluid.T;
+    if (alpha) *alpha = c->fluid.alpha;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    release(c);
+}
+
+const char* lbm_strerror(lbm_status s) {
+    switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_EDOMAIN: return "density outside the equation-of-state domain";
+    case LBM_EDIVERGED: return "simulation diverged (non-finite or out-of-domain density)";
+    case LBM_EHIP: return "HIP runtime error";
+    case LBM_ENOMEM: return "out of device memory or workspace too small";
+    case LBM_ESTATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+lbm_status lbm_critical_point(int32_t eos, double a, double b, double R, double* Tc, double* rho_c, double* p_c) {
+    if (eos < 0 || eos > 4 || !(a > 0) || !(b > 0) || !(R > 0)) return LBM_EINVAL;
+    double t, r, pc;
+    thermo::critical_point(eos, a, b, R, &t, &r, &pc);
+    if (Tc) *Tc = t;
+    if (rho_c) *rho_c = r;
+    if (p_c) *p_c = pc;
+    return LBM_OK;
+}
+
+lbm_status lbm_coexistence(const lbm_params* p, double* rho_g, double* rho_l, double* p_sat, double* mu_sat) {
+    lbm_params q;
+    if (!p) return LBM_EINVAL;
+    q = *p;
+    q.nx = q.ny = 3;  // lattice size is irrelevant here
+    q.bc_bottom = q.bc_top = LBM_BC_PERIODIC;
+    if (validate(&q) != LBM_OK || !(p->a > 0)) return LBM_EINVAL;
+    if (!(p->Tr < 1.0)) return LBM_EDOMAIN;
+    const thermo::Fluid fl = thermo::make_fluid(p->eos, p->a, p->b, p->R, p->Tr, p->omega);
+    double g, l, ps, ms;
+    if (!thermo::coexistence(fl, &g, &l, &ps, &ms)) return LBM_EDOMAIN;
+    if (rho_g) *rho_g = g;
+    if (rho_l) *rho_l = l;
+    if (p_sat) *p_sat = ps;
+    if (mu_sat) *mu_sat = ms;
+    return LBM_OK;
+}
+
+lbm_status lbm_eos_eval(const lbm_params* p, int64_t n, const double* rho, double* mu_b, double* p0) {
+    if (!p || n < 0 || (n > 0 && !rho)) return LBM_EINVAL;
+    lbm_params q = *p;
+    q.nx = q.ny = 3;
+    q.bc_bottom = q.bc_top = LBM_BC_PERIODIC;
+    if (validate(&q) != LBM_OK) return LBM_EINVAL;
+    const thermo::Fluid fl = thermo::make_fluid(p->eos, p->a, p->b, p->R, p->Tr, p->omega);
+    for (int64_t i = 0; i < n; ++i) {
+        if (mu_b) mu_b[i] = thermo::mu_b(fl, rho[i]);
+        if (p0) p0[i] = thermo::p0(fl, rho[i]);
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_contact_angle(const double* rho, int32_t nx, int32_t ny, int32_t base_row, double surface_y,
+                             double rho_mid, double* theta_deg, double* L, double* H) {
+    if (!rho || !std::isfinite(rho_mid) || !std::isfinite(surface_y)) return LBM_EINVAL;
+    const int r = thermo::contact_angle(rho, nx, ny, base_row, surface_y, rho_mid, theta_deg, L, H);
+    return r == -1 ? LBM_EINVAL : (r == -2 ? LBM_EDOMAIN : LBM_OK);
+}
+
+}  // extern "C"

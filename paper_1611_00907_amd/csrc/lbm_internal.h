@@ -1,0 +1,71 @@
+// Internal interface between the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace cplbm {
+
+enum Eos : int { EOS_VDW = 0, EOS_CS = 1, EOS_PR = 2, EOS_RKS = 3, EOS_RK = 4 };
+enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_F16DEV = 2, PREC_BF16DEV = 3 };
+enum Bc : int { BC_PERIODIC = 0, BC_CPWALL = 1, BC_NEUTRAL = 2 };
+
+// Tile of the fused step: TX x TY nodes per workgroup of TX x (TY / ROWS_PER_THREAD)
+// threads; each thread owns ROWS_PER_THREAD nodes of one column.
+constexpr int TILE_X = 64;
+constexpr int TILE_Y = 16;
+constexpr int ROWS_PER_THREAD = 4;
+constexpr int BLOCK_THREADS = TILE_X * (TILE_Y / ROWS_PER_THREAD);
+
+// Constants of the bulk chemical potential, precomputed on the host in FP64.
+struct EosConst {
+    double RT;       // R * T
+    double a;        // a (VdW, CS) or a * alpha(T) (RK, RKS, PR)
+    double b;
+    double c1;       // PR: a alpha / (2 sqrt 2 b); RK/RKS: a alpha / b; CS: b / 4
+    double rho_max;  // EOS pole: 1/b (4/b for CS)
+};
+
+// Everything a kernel needs about one lattice; passed by value.
+struct LatticeArgs {
+    int nx, ny;
+    int pitch;            // elements per row (>= nx)
+    int bottom, top;      // Bc of rows 0 and ny-1
+    int tiles_x, tiles_y; // tile grid
+    long long plane;      // elements per direction plane = ny * pitch
+    double tau, inv_tau, kappa;
+    double rho_ref;       // deviation base of the half/bf16 storage
+    EosConst eos;
+};
+
+enum StepMode : int { MODE_STEP = 0, MODE_FIELDS = 1 };
+
+// Fused step (or field output) over the whole lattice.
+// fin: storage of the post-collision distributions f*(t-1) (pulled to give f(t));
+// fout: f*(t) (MODE_STEP).  mu_w: [2][pitch] wall chemical potentials in the compute
+// type.  out: MODE_FIELDS only, [4][ny][nx] doubles rho, vx, vy, mu.
+hipError_t launch_step(int prec, int eos, int mode, const LatticeArgs& A, const void* fin,
+                       void* fout, const void* mu_w, double* out, hipStream_t s);
+
+// Monitors of the state in fin: snapshot (compare == 0) writes rho to rho_mon;
+// compare == 1 also writes per-block partials (mass, max |drho|, flags) and reduces
+// them into mon[0..2] (mass, residual, flags as double).
+hipError_t launch_monitor(int prec, int eos, int compare, const LatticeArgs& A, const void* fin,
+                          void* rho_mon, double* partials, double* mon, hipStream_t s);
+int monitor_blocks(const LatticeArgs& A);
+
+// f_i(t) from f_eq(rho0, u0) (init, u may be null) or from given f (set_state): writes the
+// storage form f*(t-1) such that streaming reproduces f(t).  rho0/ux0/uy0/f_in are device
+// doubles [ny][nx] / [9][ny][nx].
+hipError_t launch_init(int prec, const LatticeArgs& A, const double* rho0, const double* ux0,
+                       const double* uy0, const double* f_in, void* fstore, hipStream_t s);
+
+// f_i(t) [9][ny][nx] doubles from the storage (zero on solid rows).
+hipError_t launch_get_state(int prec, const LatticeArgs& A, const void* fstore, double* f_out,
+                            hipStream_t s);
+
+size_t storage_bytes(int prec);
+size_t compute_bytes(int prec);
+
+}  // namespace cplbm

@@ -1,0 +1,258 @@
+"""Python binding of the C ABI in ``include/lbm.h`` (argument marshalling only).
+
+Every step of the method runs in the HIP library ``liblbm.so``; this module
+only converts numpy arrays to pointers, takes device memory for the workspace
+and the current stream from PyTorch, and turns status codes into exceptions.
+There is no fallback: if the library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbm.so")
+
+# lbm_status
+LBM_OK, LBM_EINVAL, LBM_EDOMAIN, LBM_EDIVERGED, LBM_EHIP, LBM_ENOMEM, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
+# lbm_eos
+LBM_EOS_VDW, LBM_EOS_CS, LBM_EOS_PR, LBM_EOS_RKS, LBM_EOS_RK = 0, 1, 2, 3, 4
+# lbm_prec
+LBM_F64, LBM_F32, LBM_F16DEV, LBM_BF16DEV = 0, 1, 2, 3
+# lbm_bc
+LBM_BC_PERIODIC, LBM_BC_CPWALL, LBM_BC_NEUTRAL = 0, 1, 2
+
+EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_get_fields", "lbm_set_wall_mu",
+            "lbm_get_monitors", "lbm_monitor_step", "lbm_get_state", "lbm_set_state",
+            "lbm_get_temperature", "lbm_destroy", "lbm_strerror", "lbm_critical_point",
+            "lbm_coexistence", "lbm_eos_eval", "lbm_contact_angle"]
+
+
+class LbmParams(C.Structure):
+    """Mirror of ``lbm_params``."""
+
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("bc_bottom", C.c_int32), ("bc_top", C.c_int32),
+                ("eos", C.c_int32), ("prec", C.c_int32), ("a", C.c_double), ("b", C.c_double),
+                ("R", C.c_double), ("omega", C.c_double), ("Tr", C.c_double), ("tau", C.c_double),
+                ("kappa", C.c_double), ("rho_ref", C.c_double), ("monitor_every", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+def make_params(nx, ny, eos, a, b, Tr, tau, kappa, R=1.0, omega=0.0, prec=LBM_F32,
+                bc_bottom=LBM_BC_PERIODIC, bc_top=LBM_BC_PERIODIC, rho_ref=1.0,
+                monitor_every=0) -> LbmParams:
+    return LbmParams(int(nx), int(ny), int(bc_bottom), int(bc_top), int(eos), int(prec), float(a),
+                     float(b), float(R), float(omega), float(Tr), float(tau), float(kappa),
+                     float(rho_ref), int(monitor_every), 0)
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (where, strerror(status), status))
+
+
+class LbmDiverged(LbmError):
+    pass
+
+
+_lib = None
+
+
+def load_library():
+    """Loads liblbm.so; raises if it has not been built (no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liblbm.so is not built: run `python -m paper_1611_00907_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER(LbmParams)
+    vp, dp = C.c_void_p, C.POINTER(C.c_double)
+    lib.lbm_workspace_bytes.argtypes = [P]
+    lib.lbm_workspace_bytes.restype = C.c_size_t
+    lib.lbm_init.argtypes = [P, vp, vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.lbm_step.argtypes = [vp, C.c_int64]
+    lib.lbm_get_fields.argtypes = [vp, vp, vp, vp, vp]
+    lib.lbm_set_wall_mu.argtypes = [vp, C.c_int32, vp, C.c_int32]
+    lib.lbm_get_monitors.argtypes = [vp, dp, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+    lib.lbm_monitor_step.argtypes = [vp]
+    lib.lbm_get_state.argtypes = [vp, vp, C.POINTER(C.c_int64)]
+    lib.lbm_set_state.argtypes = [vp, vp, C.c_int64]
+    lib.lbm_get_temperature.argtypes = [vp, dp, dp]
+    lib.lbm_destroy.argtypes = [vp]
+    lib.lbm_destroy.restype = None
+    lib.lbm_strerror.argtypes = [C.c_int]
+    lib.lbm_strerror.restype = C.c_char_p
+    lib.lbm_critical_point.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, dp, dp, dp]
+    lib.lbm_coexistence.argtypes = [P, dp, dp, dp, dp]
+    lib.lbm_eos_eval.argtypes = [P, C.c_int64, vp, vp, vp]
+    lib.lbm_contact_angle.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                      dp, dp, dp]
+    for name in EXPORTED:
+        if name not in ("lbm_workspace_bytes", "lbm_destroy", "lbm_strerror"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    try:
+        return load_library().lbm_strerror(int(status)).decode()
+    except RuntimeError:
+        return "status %d" % status
+
+
+def _check(status: int, where: str):
+    if status == LBM_EDIVERGED:
+        raise LbmDiverged(status, where)
+    if status != LBM_OK:
+        raise LbmError(status, where)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+# ---------------------------------------------------------------- host tools
+def lbm_critical_point(eos: int, a: float, b: float, R: float = 1.0):
+    lib = load_library()
+    out = [C.c_double() for _ in range(3)]
+    _check(lib.lbm_critical_point(int(eos), float(a), float(b), float(R), *[C.byref(o) for o in out]),
+           "lbm_critical_point")
+    return tuple(o.value for o in out)
+
+
+def lbm_coexistence(p: LbmParams):
+    """(rho_g, rho_l, p_sat, mu_sat) of the fluid in p (Maxwell equal area)."""
+    lib = load_library()
+    out = [C.c_double() for _ in range(4)]
+    _check(lib.lbm_coexistence(C.byref(p), *[C.byref(o) for o in out]), "lbm_coexistence")
+    return tuple(o.value for o in out)
+
+
+def lbm_eos_eval(p: LbmParams, rho):
+    lib = load_library()
+    rho = _f64(rho).ravel()
+    mu, p0 = np.empty_like(rho), np.empty_like(rho)
+    _check(lib.lbm_eos_eval(C.byref(p), rho.size, _p(rho), _p(mu), _p(p0)), "lbm_eos_eval")
+    return mu, p0
+
+
+def lbm_contact_angle(rho, rho_mid: float, base_row: int = 1, surface_y=None):
+    """(theta_deg, L, H) of the drop on base_row of rho[ny][nx] (Sec. V formula)."""
+    lib = load_library()
+    rho = _f64(rho)
+    ny, nx = rho.shape
+    sy = float(base_row) if surface_y is None else float(surface_y)
+    out = [C.c_double() for _ in range(3)]
+    _check(lib.lbm_contact_angle(_p(rho), nx, ny, int(base_row), sy, float(rho_mid),
+                                 *[C.byref(o) for o in out]), "lbm_contact_angle")
+    return tuple(o.value for o in out)
+
+
+def lbm_workspace_bytes(p: LbmParams) -> int:
+    return int(load_library().lbm_workspace_bytes(C.byref(p)))
+
+
+# ---------------------------------------------------------------- lattice
+def _torch_workspace(nbytes: int):
+    """Device workspace and current stream from PyTorch (plumbing only)."""
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible to PyTorch")
+    ws = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+    return ws, int(ws.data_ptr()), int(torch.cuda.current_stream().cuda_stream)
+
+
+def lbm_init(p: LbmParams, rho0, ux0=None, uy0=None, workspace="torch"):
+    """Returns a Lattice owning the context; workspace 'torch' takes device memory
+    from PyTorch and its current stream, None lets the library allocate."""
+    return Lattice(p, rho0, ux0, uy0, workspace)
+
+
+class Lattice:
+    """One lattice on the GPU: a thin owner of an ``lbm_ctx``."""
+
+    def __init__(self, p: LbmParams, rho0, ux0=None, uy0=None, workspace="torch"):
+        self.lib = load_library()
+        self.p = p
+        self.nx, self.ny = p.nx, p.ny
+        rho0, ux0, uy0 = _f64(rho0), _f64(ux0), _f64(uy0)
+        shape = (p.ny, p.nx)
+        for a in (rho0, ux0, uy0):
+            if a is not None and a.shape != shape:
+                raise ValueError("field shape %s, expected %s" % (a.shape, shape))
+        self._ws = None
+        ws_ptr, ws_bytes, stream = None, 0, None
+        if workspace == "torch":
+            nbytes = lbm_workspace_bytes(p)
+            if nbytes == 0:
+                _check(LBM_EINVAL, "lbm_workspace_bytes")
+            self._ws, ws_ptr, stream = _torch_workspace(nbytes)
+            ws_bytes = nbytes
+        ctx = C.c_void_p()
+        _check(self.lib.lbm_init(C.byref(p), _p(rho0), _p(ux0), _p(uy0), ws_ptr, ws_bytes, stream,
+                                 C.byref(ctx)), "lbm_init")
+        self.ctx = ctx
+
+    def step(self, n: int = 1):
+        _check(self.lib.lbm_step(self.ctx, int(n)), "lbm_step")
+
+    def monitor_step(self):
+        _check(self.lib.lbm_monitor_step(self.ctx), "lbm_monitor_step")
+        return self.monitors()
+
+    def fields(self):
+        shape = (self.ny, self.nx)
+        out = {k: np.empty(shape) for k in ("rho", "vx", "vy", "mu")}
+        _check(self.lib.lbm_get_fields(self.ctx, *[_p(out[k]) for k in ("rho", "vx", "vy", "mu")]),
+               "lbm_get_fields")
+        return out
+
+    def set_wall_mu(self, wall: int, mu_w):
+        mu = np.atleast_1d(_f64(mu_w))
+        _check(self.lib.lbm_set_wall_mu(self.ctx, int(wall), _p(mu), int(mu.size)), "lbm_set_wall_mu")
+
+    def monitors(self):
+        m, r, s, f = C.c_double(), C.c_double(), C.c_int64(), C.c_int32()
+        _check(self.lib.lbm_get_monitors(self.ctx, C.byref(m), C.byref(r), C.byref(s), C.byref(f)),
+               "lbm_get_monitors")
+        return {"mass": m.value, "residual": r.value, "step": s.value, "flags": f.value}
+
+    def get_state(self):
+        f = np.empty((9, self.ny, self.nx))
+        s = C.c_int64()
+        _check(self.lib.lbm_get_state(self.ctx, _p(f), C.byref(s)), "lbm_get_state")
+        return f, s.value
+
+    def set_state(self, f, step: int = 0):
+        f = _f64(f)
+        if f.shape != (9, self.ny, self.nx):
+            raise ValueError("state shape %s" % (f.shape,))
+        _check(self.lib.lbm_set_state(self.ctx, _p(f), int(step)), "lbm_set_state")
+
+    def temperature(self):
+        T, al = C.c_double(), C.c_double()
+        _check(self.lib.lbm_get_temperature(self.ctx, C.byref(T), C.byref(al)), "lbm_get_temperature")
+        return T.value, al.value
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self.lib.lbm_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,101 @@
+"""Shared test cases: one problem statement turned into oracle and GPU parameters.
+
+The initial fields come from ``paper_1611_00907_amd.inputs`` (seeded, no method
+arithmetic); coexistence densities placed in them come from the oracle.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from oracle import thermo
+from oracle.lattice import CPWALL, NEUTRAL, PERIODIC, OracleLattice, OracleParams
+from paper_1611_00907_amd import inputs
+
+EOS_AB = {thermo.VDW: (9 / 49, 2 / 21), thermo.CS: (1.0, 4.0), thermo.PR: (2 / 49, 2 / 21),
+          thermo.RKS: (2 / 49, 2 / 21), thermo.RK: (2 / 49, 2 / 21)}
+
+
+@dataclass
+class Case:
+    nx: int
+    ny: int
+    eos: int
+    Tr: float
+    tau: float
+    kappa: float = 0.01
+    omega: float = 0.0
+    bottom: int = PERIODIC
+    top: int = PERIODIC
+    drop: str = "circle"          # circle | sessile | slab | spinodal | uniform
+    radius: float = 0.0
+    noise: float = 0.0
+    seed: int = 1
+    mu_w_bottom: object = 0.0
+    mu_w_top: object = 0.0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def ab(self):
+        return EOS_AB[self.eos]
+
+    def oracle_params(self) -> OracleParams:
+        a, b = self.ab
+        return OracleParams.from_reduced(self.nx, self.ny, self.eos, a, b, self.Tr, self.tau, self.kappa,
+                                         omega=self.omega, bottom=self.bottom, top=self.top)
+
+    def coexistence(self):
+        a, b = self.ab
+        return thermo.maxwell(thermo.fluid_at(self.eos, a, b, 1.0, self.Tr, self.omega))
+
+    def rho0(self) -> np.ndarray:
+        nx, ny = self.nx, self.ny
+        if self.drop == "spinodal":
+            a, b = self.ab
+            _, rc, _ = thermo.critical_point(self.eos, a, b, 1.0)
+            return inputs.with_relative_noise(np.full((ny, nx), rc), self.noise, self.seed)
+        if self.drop == "uniform":
+            return np.full((ny, nx), self.extra.get("rho", 1.0))
+        rg, rl, _, _ = self.coexistence()
+        if self.drop == "circle":
+            r = inputs.tanh_drop(nx, ny, rl, rg, self.radius, nx / 2, ny / 2)
+        elif self.drop == "sessile":
+            r = inputs.sessile_drop(nx, ny, rl, rg, self.radius)
+        elif self.drop == "slab":
+            r = inputs.planar_slab(nx, ny, rl, rg, self.radius)
+        else:
+            raise ValueError(self.drop)
+        if self.noise:
+            r = inputs.with_additive_noise(r, self.noise, self.seed)
+        return r
+
+    def lbm_params(self, prec, monitor_every=0, rho_ref=1.0):
+        from paper_1611_00907_amd import lbm
+        a, b = self.ab
+        return lbm.make_params(self.nx, self.ny, self.eos, a, b, self.Tr, self.tau, self.kappa,
+                               omega=self.omega, prec=prec, bc_bottom=self.bottom, bc_top=self.top,
+                               rho_ref=rho_ref, monitor_every=monitor_every)
+
+    def oracle(self) -> OracleLattice:
+        return OracleLattice(self.oracle_params(), self.rho0(), mu_w_bottom=self.mu_w_bottom,
+                             mu_w_top=self.mu_w_top)
+
+
+# Plain method, FP64: 100 x 100 periodic CS drop R = 25 with 1e-4 noise, exactly as
+# stated (tau = 1 diverges after ~110 steps), and the companion with tau = 1.3.
+C1 = Case(100, 100, thermo.CS, 0.7, 1.0, drop="circle", radius=25, noise=1e-4, seed=1)
+C1_TAU13 = Case(100, 100, thermo.CS, 0.7, 1.3, drop="circle", radius=25, noise=1e-4, seed=1)
+# Walled PR twin of the wetting configuration: CP wall below, neutral wall above.
+WALLED_PR = Case(128, 96, thermo.PR, 0.8, 1.3, omega=0.344, bottom=CPWALL, top=NEUTRAL,
+                 drop="sessile", radius=30, noise=1e-4, seed=2, mu_w_bottom=0.2)
+# Plain method, FP32: 1024 x 1024 PR wetting (CP wall + neutral top), drop R = 200.
+C2 = Case(1024, 1024, thermo.PR, 0.8, 1.3, omega=0.344, bottom=CPWALL, top=NEUTRAL,
+          drop="sessile", radius=200, noise=0.0, seed=2, mu_w_bottom=0.2)
+# Precision: VdW spinodal decomposition, rho = rho_c (1 + 0.01 U(-1, 1)).
+C3_512 = Case(512, 512, thermo.VDW, 0.85, 1.0, drop="spinodal", noise=0.01, seed=3)
+C3 = Case(4096, 4096, thermo.VDW, 0.85, 1.0, drop="spinodal", noise=0.01, seed=3)
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))

@@ -1,0 +1,211 @@
+"""GPU parity: the HIP library against the FP64 oracle, element by element.
+
+FP64 storage must match within 1e-10 of the largest distribution; FP32 within
+2e-5 (about 300 FP32 ulps of rounding in the chemical potential and force,
+carried by a contracting map); FP16/BF16 deviation storage within the rounding
+of one stored value per step (2^-11 and 2^-8 of the deviation) times the steps.
+"""
+import numpy as np
+import pytest
+
+from cases import C1, C1_TAU13, C2, C3, WALLED_PR, Case, rel_err
+from oracle import thermo
+from oracle.lattice import CPWALL, NEUTRAL, PERIODIC, OracleLattice
+
+pytestmark = pytest.mark.gpu
+
+lbm = pytest.importorskip("paper_1611_00907_amd.lbm")
+
+
+def _gpu(case: Case, prec, monitor_every=0):
+    lat = lbm.Lattice(case.lbm_params(prec, monitor_every), case.rho0())
+    if case.bottom == CPWALL:
+        lat.set_wall_mu(0, case.mu_w_bottom)
+    if case.top == CPWALL:
+        lat.set_wall_mu(1, case.mu_w_top)
+    return lat
+
+
+def _compare_state(lat, ora, tol):
+    f, _ = lat.get_state()
+    err = rel_err(f, ora.f)
+    assert np.isfinite(f).all()
+    assert err < tol, "max |f_gpu - f_oracle| / max |f| = %.3e" % err
+    return err
+
+
+@pytest.mark.parametrize("steps", [1, 10, 100])
+def test_fp64_config1_as_written(steps):
+    """100^2 CS drop, tau = 1, before the divergence the oracle also shows."""
+    lat, ora = _gpu(C1, lbm.LBM_F64), C1.oracle()
+    lat.step(steps)
+    ora.step(steps)
+    _compare_state(lat, ora, 1e-10)
+
+
+def test_fp64_config1_tau13_5000_steps():
+    lat, ora = _gpu(C1_TAU13, lbm.LBM_F64), C1_TAU13.oracle()
+    for chunk in (1, 9, 90, 900, 4000):
+        lat.step(chunk)
+        ora.step(chunk)
+        _compare_state(lat, ora, 1e-10)
+
+
+def test_fp64_walled_pr_2000_steps():
+    lat, ora = _gpu(WALLED_PR, lbm.LBM_F64), WALLED_PR.oracle()
+    for chunk in (1, 99, 1900):
+        lat.step(chunk)
+        ora.step(chunk)
+        _compare_state(lat, ora, 1e-10)
+
+
+@pytest.mark.parametrize("nx,ny,walls", [(70, 37, False), (130, 45, True), (5, 7, False), (1, 9, False),
+                                         (3, 4, True), (65, 17, True), (200, 3, True), (64, 16, False),
+                                         (129, 18, False)])
+def test_fp64_ragged_and_tiny(nx, ny, walls):
+    """Sizes that are not multiples of the 64 x 16 tile, smaller than one tile,
+    one column wide, or a single fluid row between walls."""
+    kw = dict(bottom=CPWALL, top=NEUTRAL, drop="sessile") if walls else dict(drop="circle")
+    c = Case(nx, ny, thermo.PR, 0.8, 1.3, omega=0.344, radius=max(min(nx, ny) / 3, 0.8), noise=1e-3,
+             seed=nx * 1000 + ny, mu_w_bottom=0.25, **kw)
+    lat, ora = _gpu(c, lbm.LBM_F64), c.oracle()
+    lat.step(25)
+    ora.step(25)
+    _compare_state(lat, ora, 1e-10)
+
+
+def test_fp64_per_node_wall_mu_and_cp_top():
+    """Per-column surface chemical potentials on both walls (CP wall on top too)."""
+    c = Case(96, 40, thermo.PR, 0.8, 1.3, omega=0.344, bottom=CPWALL, top=CPWALL, drop="sessile",
+             radius=14, noise=1e-3, seed=9)
+    x = np.arange(96)
+    c.mu_w_bottom = 0.2 + 0.05 * np.sin(2 * np.pi * x / 96)
+    c.mu_w_top = 0.27 + 0.01 * np.cos(2 * np.pi * x / 48)
+    lat, ora = _gpu(c, lbm.LBM_F64), c.oracle()
+    lat.step(300)
+    ora.step(300)
+    _compare_state(lat, ora, 1e-10)
+
+
+@pytest.mark.parametrize("eos", [thermo.VDW, thermo.CS, thermo.PR, thermo.RKS, thermo.RK])
+def test_fp64_every_eos(eos):
+    Tr = {thermo.CS: 0.8}.get(eos, 0.85)
+    c = Case(80, 48, eos, Tr, 1.3, omega=0.344 if eos in (thermo.PR, thermo.RKS) else 0.0,
+             drop="circle", radius=12, noise=1e-3, seed=eos + 20)
+    lat, ora = _gpu(c, lbm.LBM_F64), c.oracle()
+    lat.step(200)
+    ora.step(200)
+    _compare_state(lat, ora, 1e-10)
+
+
+def test_fp64_fields_and_monitors():
+    """Output fields (rho with Eq 28 rows, v = u + F/2rho, mu with wall values) and
+    the monitors (mass, max |rho(t) - rho(t-1)|) against the oracle."""
+    lat, ora = _gpu(WALLED_PR, lbm.LBM_F64), WALLED_PR.oracle()
+    lat.step(49)
+    ora.step(49)
+    rho_prev = ora.fields()["rho"]
+    mon = lat.monitor_step()
+    ora.step(1)
+    fo = ora.fields()
+    fg = lat.fields()
+    for k in ("rho", "vx", "vy", "mu"):
+        scale = max(np.max(np.abs(fo[k])), 1e-12)
+        assert np.max(np.abs(fg[k] - fo[k])) < 1e-10 * scale, k
+    fluid = ora.p.fluid_mask()
+    assert abs(mon["mass"] - ora.mass()) < 1e-12 * ora.mass()
+    res_o = np.max(np.abs(fo["rho"] - rho_prev)[fluid])
+    assert abs(mon["residual"] - res_o) < 1e-10 * res_o + 1e-14
+    assert mon["step"] == 50 and mon["flags"] == 0
+
+
+def test_checkpoint_resume_bit_exact():
+    for prec in (lbm.LBM_F64, lbm.LBM_F32):
+        a = _gpu(WALLED_PR, prec)
+        a.step(40)
+        f, s = a.get_state()
+        a.step(40)
+        fa, _ = a.get_state()
+        b = _gpu(WALLED_PR, prec)
+        b.set_state(f, s)
+        b.step(40)
+        fb, sb = b.get_state()
+        assert sb == 80
+        assert np.array_equal(fa, fb)
+
+
+def test_state_roundtrip_fp64():
+    lat = _gpu(C1_TAU13, lbm.LBM_F64)
+    f0, _ = lat.get_state()
+    lat.set_state(f0, 0)
+    f1, _ = lat.get_state()
+    assert np.array_equal(f0, f1)
+
+
+def test_divergence_is_reported():
+    """Config 1 as written (tau = 1) blows up; the oracle does too in the same window,
+    and the library stops with LBM_EDIVERGED at a monitor point."""
+    lat = _gpu(C1, lbm.LBM_F64, monitor_every=10)
+    with pytest.raises(lbm.LbmDiverged):
+        lat.step(400)
+    ora = C1.oracle()
+    ora.step(400)
+    assert not np.isfinite(ora.f).all()
+
+
+def test_zero_steps_is_noop():
+    lat = _gpu(WALLED_PR, lbm.LBM_F64)
+    f0, _ = lat.get_state()
+    lat.step(0)
+    f1, s = lat.get_state()
+    assert s == 0 and np.array_equal(f0, f1)
+
+
+@pytest.mark.parametrize("steps", [10, 200])
+def test_fp32_walled_pr(steps):
+    lat, ora = _gpu(WALLED_PR, lbm.LBM_F32), WALLED_PR.oracle()
+    lat.step(steps)
+    ora.step(steps)
+    _compare_state(lat, ora, 2e-5)
+
+
+@pytest.mark.parametrize("prec,tol", [("f16", 4e-3), ("bf16", 3e-2)])
+def test_reduced_storage_one_and_ten_steps(prec, tol):
+    """Deviation storage: one stored rounding per value per step."""
+    p = {"f16": lbm.LBM_F16DEV, "bf16": lbm.LBM_BF16DEV}[prec]
+    lat, ora = _gpu(WALLED_PR, p), WALLED_PR.oracle()
+    lat.step(1)
+    ora.step(1)
+    _compare_state(lat, ora, tol / 10)
+    lat.step(9)
+    ora.step(9)
+    _compare_state(lat, ora, tol)
+
+
+def test_fp32_full_size_config2():
+    """1024 x 1024 wetting case in the benchmark's launch configuration: every
+    node against the oracle after 20 steps."""
+    lat, ora = _gpu(C2, lbm.LBM_F32), C2.oracle()
+    lat.step(20)
+    ora.step(20)
+    _compare_state(lat, ora, 2e-5)
+
+
+def test_fp32_full_size_4096_sampled():
+    """4096^2 spinodal case: after k steps a node depends on the initial field within
+    3k nodes, so periodic oracle windows with a 3k margin give exact samples."""
+    k = 8
+    lat = _gpu(C3, lbm.LBM_F32)
+    rho0 = C3.rho0()
+    lat.step(k)
+    f, _ = lat.get_state()
+    m, w = 3 * k + 2, 32
+    for (y0, x0) in ((0, 0), (2000, 3000), (4096 - 32, 4096 - 32), (1234, 77)):
+        ys = (np.arange(y0 - m, y0 + w + m)) % 4096
+        xs = (np.arange(x0 - m, x0 + w + m)) % 4096
+        sub = Case(len(xs), len(ys), C3.eos, C3.Tr, C3.tau, drop="uniform")
+        ora = OracleLattice(sub.oracle_params(), rho0[np.ix_(ys, xs)])
+        ora.step(k)
+        got = f[:, (ys[m:m + w])[:, None], xs[m:m + w][None, :]]
+        want = ora.f[:, m:m + w, m:m + w]
+        assert rel_err(got, want) < 2e-5
