@@ -141,6 +141,10 @@ lbm_status lbm_get_temperature(lbm_ctx* c, double* T, double* alpha);
 void lbm_destroy(lbm_ctx* c);
 const char* lbm_strerror(lbm_status s);
 
+/* Text of the last HIP failure behind an LBM_EHIP in this thread ("" if none):
+ * the failing call and the HIP error name.  Owned by the library. */
+const char* lbm_last_error(void);
+
 /* ---- host thermodynamics tools (FP64) ---------------------------------- */
 
 /* Critical point of an EOS (Sec. III reduced variables): dp0/drho = d2p0/drho2 = 0.

@@ -3,6 +3,7 @@
 
 #include <climits>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -128,12 +129,25 @@ LatticeArgs lattice_args(const lbm_params& p, const thermo::Fluid& fl, const Lay
     return A;
 }
 
-lbm_status hip_status(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
+thread_local char g_last_error[256] = "";
+
+void note_error(hipError_t e, const char* where) {
+    std::snprintf(g_last_error, sizeof g_last_error, "%s: %s (%d)", where, hipGetErrorName(e), (int)e);
+}
+
+lbm_status hip_status(hipError_t e, const char* where = "hip") {
+    if (e == hipSuccess) return LBM_OK;
+    note_error(e, where);
+    return LBM_EHIP;
+}
 
 #define HIP_TRY(expr)                                   \
     do {                                                \
         hipError_t e_ = (expr);                         \
-        if (e_ != hipSuccess) return LBM_EHIP;          \
+        if (e_ != hipSuccess) {                         \
+            note_error(e_, #expr);                      \
+            return LBM_EHIP;                            \
+        }                                               \
     } while (0)
 
 bool is_solid_row(const lbm_params& p, int y) { return walled(p) && (y == 0 || y == p.ny - 1); }
@@ -221,7 +235,8 @@ lbm_status lbm_init(const lbm_params* p, const double* rho0, const double* ux0, 
     c->p = *p;
     c->fluid = fl;
     c->stream = (hipStream_t)hip_stream;
-    if (hipGetDevice(&c->device) != hipSuccess) {
+    if (hipError_t e0 = hipGetDevice(&c->device); e0 != hipSuccess) {
+        note_error(e0, "hipGetDevice");
         release(c);
         return LBM_EHIP;
     }
@@ -238,7 +253,8 @@ lbm_status lbm_init(const lbm_params* p, const double* rho0, const double* ux0, 
         }
         c->own_ws = true;
     }
-    if (hipHostMalloc(&c->mon_host, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    if (hipError_t e0 = hipHostMalloc(&c->mon_host, 4 * sizeof(double), hipHostMallocDefault); e0 != hipSuccess) {
+        note_error(e0, "hipHostMalloc");
         release(c);
         return LBM_EHIP;
     }
@@ -254,17 +270,20 @@ lbm_status lbm_init(const lbm_params* p, const double* rho0, const double* ux0, 
     // f(0) = f_eq(rho0, u0), stored in the pulled form.
     double* staging = nullptr;
     const size_t sbytes = n * sizeof(double);
+    const char* where = "hipMalloc(staging)";
     hipError_t e = hipMalloc(&staging, 3 * sbytes);
-    if (e == hipSuccess) e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(staging, rho0, sbytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws, 0, L.total, c->stream), where = "hipMemsetAsync(workspace)";
+    if (e == hipSuccess) e = hipMemcpyAsync(staging, rho0, sbytes, hipMemcpyHostToDevice, c->stream), where = "copy rho0";
     if (e == hipSuccess && ux0) e = hipMemcpyAsync(staging + n, ux0, sbytes, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess && uy0) e = hipMemcpyAsync(staging + 2 * n, uy0, sbytes, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
         e = launch_init(p->prec, c->A, staging, ux0 ? staging + n : nullptr, uy0 ? staging + 2 * n : nullptr,
-                        nullptr, c->f[0], c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+                        nullptr, c->f[0], c->stream),
+        where = "init kernel";
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream), where = "hipStreamSynchronize(init)";
     if (staging) (void)hipFree(staging);
     if (e != hipSuccess) {
+        note_error(e, where);
         release(c);
         return LBM_EHIP;
     }
@@ -318,7 +337,7 @@ lbm_status lbm_get_fields(lbm_ctx* c, double* rho, double* vx, double* vy, doubl
         if (outs[k]) e = hipMemcpyAsync(outs[k], d + k * n, n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipFree(d);
-    return hip_status(e);
+    return hip_status(e, "lbm_get_fields");
 }
 
 lbm_status lbm_set_wall_mu(lbm_ctx* c, int32_t wall, const double* mu_w, int32_t count) {
@@ -353,7 +372,7 @@ lbm_status lbm_get_state(lbm_ctx* c, double* f, int64_t* step) {
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipFree(d);
     if (e == hipSuccess && step) *step = c->step;
-    return hip_status(e);
+    return hip_status(e, "lbm_get_state");
 }
 
 lbm_status lbm_set_state(lbm_ctx* c, const double* f, int64_t step) {
@@ -369,7 +388,7 @@ lbm_status lbm_set_state(lbm_ctx* c, const double* f, int64_t step) {
     if (e == hipSuccess) e = launch_init(c->p.prec, c->A, nullptr, nullptr, nullptr, d, c->f[c->cur], c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipFree(d);
-    if (e != hipSuccess) return LBM_EHIP;
+    if (e != hipSuccess) return hip_status(e, "lbm_set_state");
     c->step = step;
     c->snap_step = -1;
     return LBM_OK;
@@ -388,6 +407,8 @@ void lbm_destroy(lbm_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     release(c);
 }
+
+const char* lbm_last_error(void) { return g_last_error; }
 
 const char* lbm_strerror(lbm_status s) {
     switch (s) {

@@ -545,6 +545,7 @@ hipError_t step_eos(int mode, const LatticeArgs& A, const void* fin, void* fout,
                     double* out, hipStream_t s) {
     using CT = typename Codec<ST>::CT;
     const dim3 grid(A.tiles_x * A.tiles_y), block(BLOCK_THREADS);
+    (void)hipGetLastError();  // drop any error left by earlier runtime calls
     if (mode == MODE_STEP)
         hipLaunchKernelGGL((step_kernel<ST, EOS, MODE_STEP>), grid, block, 0, s, A, (const ST*)fin, (ST*)fout,
                            (const CT*)mu_w, out);
@@ -572,6 +573,7 @@ hipError_t monitor_prec(int compare, const LatticeArgs& A, const void* fin, void
                         double* mon, hipStream_t s) {
     using CT = typename Codec<ST>::CT;
     const int nb = monitor_blocks(A);
+    (void)hipGetLastError();
     if (compare) {
         hipLaunchKernelGGL((monitor_kernel<ST, 1>), dim3(nb), dim3(MON_THREADS), 0, s, A, (const ST*)fin,
                            (CT*)rho_mon, partials);
@@ -626,6 +628,7 @@ static hipError_t init_prec(const LatticeArgs& A, const double* rho0, const doub
                             const double* f_in, void* fstore, hipStream_t s) {
     const long long n = (long long)A.nx * A.ny;
     const int blocks = int((n + 255) / 256);
+    (void)hipGetLastError();
     hipLaunchKernelGGL((init_kernel<ST>), dim3(blocks), dim3(256), 0, s, A, rho0, ux0, uy0, f_in, (ST*)fstore);
     return hipGetLastError();
 }
@@ -645,6 +648,7 @@ template <typename ST>
 static hipError_t get_state_prec(const LatticeArgs& A, const void* fstore, double* f_out, hipStream_t s) {
     const long long n = (long long)A.nx * A.ny;
     const int blocks = int((n + 255) / 256);
+    (void)hipGetLastError();
     hipLaunchKernelGGL((get_state_kernel<ST>), dim3(blocks), dim3(256), 0, s, A, (const ST*)fstore, f_out);
     return hipGetLastError();
 }

@@ -27,7 +27,7 @@ LBM_BC_PERIODIC, LBM_BC_CPWALL, LBM_BC_NEUTRAL = 0, 1, 2
 
 EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_get_fields", "lbm_set_wall_mu",
             "lbm_get_monitors", "lbm_monitor_step", "lbm_get_state", "lbm_set_state",
-            "lbm_get_temperature", "lbm_destroy", "lbm_strerror", "lbm_critical_point",
+            "lbm_get_temperature", "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_critical_point",
             "lbm_coexistence", "lbm_eos_eval", "lbm_contact_angle"]
 
 
@@ -52,7 +52,13 @@ def make_params(nx, ny, eos, a, b, Tr, tau, kappa, R=1.0, omega=0.0, prec=LBM_F3
 class LbmError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
-        super().__init__("%s: %s (%d)" % (where, strerror(status), status))
+        detail = ""
+        if status == LBM_EHIP:
+            try:
+                detail = " [" + load_library().lbm_last_error().decode() + "]"
+            except RuntimeError:
+                pass
+        super().__init__("%s: %s (%d)%s" % (where, strerror(status), status, detail))
 
 
 class LbmDiverged(LbmError):
@@ -87,13 +93,15 @@ def load_library():
     lib.lbm_destroy.restype = None
     lib.lbm_strerror.argtypes = [C.c_int]
     lib.lbm_strerror.restype = C.c_char_p
+    lib.lbm_last_error.argtypes = []
+    lib.lbm_last_error.restype = C.c_char_p
     lib.lbm_critical_point.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, dp, dp, dp]
     lib.lbm_coexistence.argtypes = [P, dp, dp, dp, dp]
     lib.lbm_eos_eval.argtypes = [P, C.c_int64, vp, vp, vp]
     lib.lbm_contact_angle.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                       dp, dp, dp]
     for name in EXPORTED:
-        if name not in ("lbm_workspace_bytes", "lbm_destroy", "lbm_strerror"):
+        if name not in ("lbm_workspace_bytes", "lbm_destroy", "lbm_strerror", "lbm_last_error"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
