@@ -68,19 +68,6 @@ def spinodal_workload(lbm, inputs, prec, n=4096):
     return p, rho0, None, n * n
 
 
-def timed(torch, fn, reps: int) -> float:
-    """Seconds for fn() run reps times, bracketed by synchronisations, measured with
-    HIP events on the current stream (the one the library launches on)."""
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        fn()
-    b.record()
-    torch.cuda.synchronize()
-    return a.elapsed_time(b) / 1e3
-
-
 def traffic_for(workload: str, bytes_per_launch: float):
     """HBM bytes per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE counts,
     if they were taken on the current kernel source."""
@@ -93,23 +80,32 @@ def traffic_for(workload: str, bytes_per_launch: float):
     return (d["fetch_kib_per_dispatch"] + d["write_kib_per_dispatch"]) * 1024.0 * d.get("copy_factor", 1.0)
 
 
-def measure(lbm, torch, p, rho0, mu_w, fluid_nodes, steps, warmup, bytes_per_lu, workload):
-    lat = lbm.Lattice(p, rho0)
-    if mu_w is not None:
-        lat.set_wall_mu(0, mu_w)
-    lat.step(warmup)
-    # kernel-only: back-to-back fused steps, no monitors
+def _with_monitor(p, every):
+    q = type(p)()
+    for name, _ in p._fields_:
+        setattr(q, name, getattr(p, name))
+    q.monitor_every = every
+    return q
+
+
+def measure(lbm, p, rho0, mu_w, fluid_nodes, steps, warmup, bytes_per_lu, workload):
+    """Times the step with HIP events on the lattice's own stream (lbm_step_timed)."""
+    def lattice(every):
+        lat = lbm.Lattice(_with_monitor(p, every), rho0)
+        if mu_w is not None:
+            lat.set_wall_mu(0, mu_w)
+        lat.step(warmup)
+        return lat
+
+    # kernel only: back-to-back fused steps, no monitors
+    lat = lattice(0)
     k_steps = max(steps, 100)
-    t_kernel = timed(torch, lambda: lat.step(k_steps), 1) / k_steps
-    # whole step: fused update plus monitors every MONITOR_EVERY steps
-    chunks = max(steps // MONITOR_EVERY, 1)
-
-    def chunk():
-        lat.step(MONITOR_EVERY - 1)
-        lat.monitor_step()
-
-    t_total = timed(torch, chunk, chunks)
-    n_steps = chunks * MONITOR_EVERY
+    t_kernel = lat.step_timed(k_steps) / 1e3 / k_steps
+    lat.close()
+    # whole step: fused update plus the monitors every MONITOR_EVERY steps
+    lat = lattice(MONITOR_EVERY)
+    n_steps = max(steps // MONITOR_EVERY, 1) * MONITOR_EVERY
+    t_total = lat.step_timed(n_steps) / 1e3
     mon = lat.monitors()
     lat.close()
     achieved = fluid_nodes * bytes_per_lu / t_kernel / 1e9
@@ -151,18 +147,12 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
-    import torch
-
     from paper_1611_00907_amd import inputs, lbm
 
-    if not torch.cuda.is_available():
-        print("no GPU visible", file=sys.stderr)
-        sys.exit(1)
-    torch.cuda.set_device(0)
     lbm.load_library()
 
     p, rho0, mu_w, fluid = wetting_workload(lbm, inputs, lbm.LBM_F32)
-    main_res = measure(lbm, torch, p, rho0, mu_w, fluid, args.steps, args.warmup, 72.0,
+    main_res = measure(lbm, p, rho0, mu_w, fluid, args.steps, args.warmup, 72.0,
                        "step_f32_wetting1024")
     print("main: %.1f MLUPS, kernel %.2f us, %.1f GB/s" % (main_res["mlups"], main_res["kernel_us"],
                                                           main_res["roofline"]["achieved"]),
@@ -173,7 +163,7 @@ def main():
         for prec, name, b in ((lbm.LBM_F32, "f32", 72.0), (lbm.LBM_F16DEV, "f16dev", 36.0),
                               (lbm.LBM_BF16DEV, "bf16dev", 36.0)):
             pp, r0, _, fl = spinodal_workload(lbm, inputs, prec)
-            res = measure(lbm, torch, pp, r0, None, fl, 300, 20, b, "step_%s_spinodal4096" % name)
+            res = measure(lbm, pp, r0, None, fl, 300, 20, b, "step_%s_spinodal4096" % name)
             aux.append({"workload": "spinodal 4096x4096 VdW Tr=0.85, %s storage" % name,
                         "mlups": round(res["mlups"], 1), "kernel_us": round(res["kernel_us"], 2),
                         "roofline": res["roofline"]})

@@ -76,7 +76,8 @@ typedef enum {
 } lbm_bc;
 
 typedef struct {
-    int32_t nx, ny;         /* lattice nodes including solid rows; nx >= 1, ny >= 1 (>= 3 walled) */
+    int32_t nx, ny;         /* lattice nodes including solid rows; nx >= 1, ny >= 1 (>= 3 walled); */
+                            /* ny * round_up(nx, 64) * bytes per stored value < 2^32 (one plane)  */
     int32_t bc_bottom;      /* lbm_bc of row 0                                                   */
     int32_t bc_top;         /* lbm_bc of row ny-1                                                */
     int32_t eos;            /* lbm_eos                                                           */
@@ -108,6 +109,11 @@ lbm_status lbm_init(const lbm_params* p, const double* rho0, const double* ux0,
  * non-finite density, rho <= 0 or rho beyond the EOS pole returns LBM_EDIVERGED
  * and the steps that follow it are not run. */
 lbm_status lbm_step(lbm_ctx* c, int64_t n);
+
+/* lbm_step bracketed by HIP events recorded on the context's stream (after a
+ * stream synchronisation): *ms is the elapsed device time of the n steps,
+ * monitors included.  Synchronises. */
+lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* ms);
 
 /* Output fields of the current state into host arrays [ny][nx]: density (Eq 28
  * values on solid rows), physical velocity v = u + F / (2 rho) (forcing

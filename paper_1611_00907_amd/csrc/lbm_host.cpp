@@ -65,6 +65,8 @@ lbm_status validate(const lbm_params* p) {
     if (p->monitor_every < 0 || p->reserved != 0) return LBM_EINVAL;
     const long long pitch = ((long long)p->nx + PITCH_ALIGN - 1) / PITCH_ALIGN * PITCH_ALIGN;
     if (pitch * (long long)p->ny > INT_MAX) return LBM_EINVAL;  // in-plane offsets are 32-bit
+    // kernels address each direction plane with a 32-bit byte offset
+    if (pitch * (long long)p->ny * (long long)storage_bytes(p->prec) >= (1LL << 32)) return LBM_EINVAL;
     return LBM_OK;
 }
 
@@ -313,6 +315,30 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
         }
     }
     return LBM_OK;
+}
+
+lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* ms) {
+    if (!c || n < 0 || !ms) return LBM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LBM_EHIP;
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(hipEventCreate(&a));
+    if (hipError_t e = hipEventCreate(&b); e != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hip_status(e, "hipEventCreate");
+    }
+    lbm_status st = LBM_OK;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipEventRecord(a, c->stream);
+    if (e == hipSuccess) st = lbm_step(c, n);
+    if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_status(e, "lbm_step_timed");
+    *ms = t;
+    return st;
 }
 
 lbm_status lbm_monitor_step(lbm_ctx* c) {

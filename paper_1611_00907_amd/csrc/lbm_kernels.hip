@@ -24,45 +24,62 @@ namespace cplbm {
 namespace {
 
 // ---------------------------------------------------------------- storage codecs
+// Offsets are element indices within one direction plane.  They are turned into
+// 32-bit byte offsets from the plane's (uniform) base, so loads and stores take a
+// scalar base plus one 32-bit vector offset; the host keeps every plane below
+// 4 GiB.
+template <typename T>
+__device__ __forceinline__ const T* at(const T* p, unsigned o) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + (o * unsigned(sizeof(T))));
+}
+template <typename T>
+__device__ __forceinline__ T* at(T* p, unsigned o) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(p) + (o * unsigned(sizeof(T))));
+}
+
 template <typename ST>
 struct Codec;
 
 template <>
 struct Codec<double> {
     using CT = double;
-    static __device__ __forceinline__ double ld(const double* p, int o, double) { return p[o]; }
-    static __device__ __forceinline__ void st(double* p, int o, double v, double) { p[o] = v; }
+    static __device__ __forceinline__ double ld(const double* p, unsigned o, double) { return *at(p, o); }
+    static __device__ __forceinline__ void st(double* p, unsigned o, double v, double) { *at(p, o) = v; }
 };
 template <>
 struct Codec<float> {
     using CT = float;
-    static __device__ __forceinline__ float ld(const float* p, int o, float) { return p[o]; }
-    static __device__ __forceinline__ void st(float* p, int o, float v, float) { p[o] = v; }
+    static __device__ __forceinline__ float ld(const float* p, unsigned o, float) { return *at(p, o); }
+    static __device__ __forceinline__ void st(float* p, unsigned o, float v, float) { *at(p, o) = v; }
 };
 // Deviation storage: h = f - w_i rho_ref, rounded to nearest even on store.
 template <>
 struct Codec<__half> {
     using CT = float;
-    static __device__ __forceinline__ float ld(const __half* p, int o, float base) {
-        return __half2float(p[o]) + base;
+    static __device__ __forceinline__ float ld(const __half* p, unsigned o, float base) {
+        return __half2float(*at(p, o)) + base;
     }
-    static __device__ __forceinline__ void st(__half* p, int o, float v, float base) {
-        p[o] = __float2half_rn(v - base);
+    static __device__ __forceinline__ void st(__half* p, unsigned o, float v, float base) {
+        *at(p, o) = __float2half_rn(v - base);
     }
 };
 template <>
 struct Codec<__hip_bfloat16> {
     using CT = float;
-    static __device__ __forceinline__ float ld(const __hip_bfloat16* p, int o, float base) {
-        return __bfloat162float(p[o]) + base;
+    static __device__ __forceinline__ float ld(const __hip_bfloat16* p, unsigned o, float base) {
+        return __bfloat162float(*at(p, o)) + base;
     }
-    static __device__ __forceinline__ void st(__hip_bfloat16* p, int o, float v, float base) {
-        p[o] = __float2bfloat16(v - base);
+    static __device__ __forceinline__ void st(__hip_bfloat16* p, unsigned o, float v, float base) {
+        *at(p, o) = __float2bfloat16(v - base);
     }
 };
 
-__device__ __forceinline__ float lg(float x) { return logf(x); }
+// FP32 arithmetic uses the hardware log2 and reciprocal (about 1 ulp); FP64 keeps
+// the correctly rounded division and the library logarithm.
+__device__ __forceinline__ float lg(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
 __device__ __forceinline__ double lg(double x) { return log(x); }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 
 // D2Q9 weights (Eq 14 coefficients imply c_s^2 = 1/3): rest, axis, diagonal.
 template <typename CT>
@@ -107,27 +124,28 @@ __device__ __forceinline__ void pull9(const LatticeArgs& A, const Planes<ST>& F,
         sm = ym == 0;
         sp = yp == A.ny - 1;
     }
-    const int rc = gy * A.pitch, rm = ym * A.pitch, rp = yp * A.pitch;
-    f[0] = C::ld(F.p[0], rc + gx, b0);
-    f[1] = C::ld(F.p[1], rc + xm, b1);
-    f[3] = C::ld(F.p[3], rc + xp, b1);
+    const unsigned pitch = unsigned(A.pitch), ux = unsigned(gx), uxm = unsigned(xm), uxp = unsigned(xp);
+    const unsigned rc = unsigned(gy) * pitch, rm = unsigned(ym) * pitch, rp = unsigned(yp) * pitch;
+    f[0] = C::ld(F.p[0], rc + ux, b0);
+    f[1] = C::ld(F.p[1], rc + uxm, b1);
+    f[3] = C::ld(F.p[3], rc + uxp, b1);
     if (sm) {  // links from the wall below return reversed (halfway bounce-back)
-        f[2] = C::ld(F.p[4], rc + gx, b1);
-        f[5] = C::ld(F.p[7], rc + gx, b2);
-        f[6] = C::ld(F.p[8], rc + gx, b2);
+        f[2] = C::ld(F.p[4], rc + ux, b1);
+        f[5] = C::ld(F.p[7], rc + ux, b2);
+        f[6] = C::ld(F.p[8], rc + ux, b2);
     } else {
-        f[2] = C::ld(F.p[2], rm + gx, b1);
-        f[5] = C::ld(F.p[5], rm + xm, b2);
-        f[6] = C::ld(F.p[6], rm + xp, b2);
+        f[2] = C::ld(F.p[2], rm + ux, b1);
+        f[5] = C::ld(F.p[5], rm + uxm, b2);
+        f[6] = C::ld(F.p[6], rm + uxp, b2);
     }
     if (sp) {
-        f[4] = C::ld(F.p[2], rc + gx, b1);
-        f[7] = C::ld(F.p[5], rc + gx, b2);
-        f[8] = C::ld(F.p[6], rc + gx, b2);
+        f[4] = C::ld(F.p[2], rc + ux, b1);
+        f[7] = C::ld(F.p[5], rc + ux, b2);
+        f[8] = C::ld(F.p[6], rc + ux, b2);
     } else {
-        f[4] = C::ld(F.p[4], rp + gx, b1);
-        f[7] = C::ld(F.p[7], rp + xp, b2);
-        f[8] = C::ld(F.p[8], rp + xm, b2);
+        f[4] = C::ld(F.p[4], rp + ux, b1);
+        f[7] = C::ld(F.p[7], rp + uxp, b2);
+        f[8] = C::ld(F.p[8], rp + uxm, b2);
     }
 }
 
@@ -173,18 +191,18 @@ __device__ __forceinline__ CT mu_bulk(const EosConst& E, CT rho) {
     const CT RT = CT(E.RT), a = CT(E.a), b = CT(E.b), c1 = CT(E.c1);
     if constexpr (EOS == EOS_CS) {
         const CT q = c1 * rho, om = CT(1) - q;
-        return RT * ((CT(3) - q) / (om * om * om) + lg(rho) + CT(1)) - CT(2) * a * rho;
+        return RT * ((CT(3) - q) * rcp(om * om * om) + lg(rho) + CT(1)) - CT(2) * a * rho;
     } else {
-        const CT br = b * rho, ib = CT(1) / (CT(1) - br);
+        const CT br = b * rho, ib = rcp(CT(1) - br);
         const CT rep = RT * (lg(rho * ib) + ib);
         if constexpr (EOS == EOS_VDW) {
             return rep - CT(2) * a * rho;
         } else if constexpr (EOS == EOS_PR) {
             const CT s2 = CT(1.4142135623730950488);
-            return rep - c1 * lg((s2 - CT(1) + br) / (s2 + CT(1) - br)) -
-                   a * rho / (CT(1) + CT(2) * br - br * br);
+            return rep - c1 * lg((s2 - CT(1) + br) * rcp(s2 + CT(1) - br)) -
+                   a * rho * rcp(CT(1) + CT(2) * br - br * br);
         } else {  // RK, RKS
-            return rep - c1 * lg(CT(1) + br) - a * rho / (CT(1) + br);
+            return rep - c1 * lg(CT(1) + br) - a * rho * rcp(CT(1) + br);
         }
     }
 }
@@ -201,8 +219,9 @@ __device__ __forceinline__ CT lap9(const CT (*s)[W], int r, int c) {
 template <typename CT, int W>
 __device__ __forceinline__ void grad9(const CT (*s)[W], int r, int c, CT& gx, CT& gy) {
     const CT ne = s[r + 1][c + 1], nw = s[r + 1][c - 1], se = s[r - 1][c + 1], sw = s[r - 1][c - 1];
-    gx = (s[r][c + 1] - s[r][c - 1]) / CT(3) + ((ne - nw) + (se - sw)) / CT(12);
-    gy = (s[r + 1][c] - s[r - 1][c]) / CT(3) + ((ne + nw) - (se + sw)) / CT(12);
+    constexpr CT third = CT(1) / CT(3), twelfth = CT(1) / CT(12);
+    gx = (s[r][c + 1] - s[r][c - 1]) * third + ((ne - nw) + (se - sw)) * twelfth;
+    gy = (s[r + 1][c] - s[r - 1][c]) * third + ((ne + nw) - (se + sw)) * twelfth;
 }
 
 __device__ __forceinline__ int tile_of_block(int b, int nblk) {
@@ -329,16 +348,17 @@ __global__ __launch_bounds__(BLOCK_THREADS) void step_kernel(LatticeArgs A, cons
         CT gmx, gmy, grx, gry;
         grad9<CT, MW>(ms, ry + 1, lx + 1, gmx, gmy);
         grad9<CT, RW>(rs, ry + 2, lx + 2, grx, gry);
-        const CT Fx = -rho * gmx + grx / CT(3);
-        const CT Fy = -rho * gmy + gry / CT(3);
-        const CT inv_rho = CT(1) / rho;
+        constexpr CT third = CT(1) / CT(3);
+        const CT Fx = -rho * gmx + grx * third;
+        const CT Fy = -rho * gmy + gry * third;
+        const CT inv_rho = rcp(rho);
         const CT ux = jx[k] * inv_rho, uy = jy[k] * inv_rho;
         if (MODE == MODE_FIELDS) {
             const long long o = (long long)gy * A.nx + gx_raw;
             const long long P = (long long)A.nx * A.ny;
             out[o] = double(rho);
-            out[P + o] = double(ux + Fx / (CT(2) * rho));
-            out[2 * P + o] = double(uy + Fy / (CT(2) * rho));
+            out[P + o] = double(ux + CT(0.5) * Fx * inv_rho);
+            out[2 * P + o] = double(uy + CT(0.5) * Fy * inv_rho);
             out[3 * P + o] = double(ms[ry + 1][lx + 1]);
             continue;
         }
@@ -359,7 +379,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void step_kernel(LatticeArgs A, cons
             feq[6] = r2 * (CT(1) + CT(3) * d6 + CT(4.5) * d6 * d6 - usq);
             feq[8] = r2 * (CT(1) - CT(3) * d6 + CT(4.5) * d6 * d6 - usq);
         }
-        const int o = gy * A.pitch + gx_raw;
+        const unsigned o = unsigned(gy) * unsigned(A.pitch) + unsigned(gx_raw);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const CT fs = f[k][i] - (f[k][i] - feq[i]) * inv_tau;

@@ -1,15 +1,20 @@
 """Python binding of the C ABI in ``include/lbm.h`` (argument marshalling only).
 
 Every step of the method runs in the HIP library ``liblbm.so``; this module
-only converts numpy arrays to pointers, takes device memory for the workspace
-and the current stream from PyTorch, and turns status codes into exceptions.
+only converts numpy arrays to pointers and turns status codes into exceptions.
 There is no fallback: if the library is missing, loading fails loudly.
+
+Device memory: by default the library allocates its workspace and uses the
+null stream.  ``workspace="torch"`` takes the workspace from PyTorch and runs on
+PyTorch's current stream instead; that needs PyTorch imported *before* this
+library is loaded, so that both use PyTorch's HIP runtime (a process must not
+hold two HIP runtimes, and PyTorch ships its own).
 """
 from __future__ import annotations
 
 import ctypes as C
 import os
-from dataclasses import dataclass
+import sys
 
 import numpy as np
 
@@ -25,7 +30,8 @@ LBM_F64, LBM_F32, LBM_F16DEV, LBM_BF16DEV = 0, 1, 2, 3
 # lbm_bc
 LBM_BC_PERIODIC, LBM_BC_CPWALL, LBM_BC_NEUTRAL = 0, 1, 2
 
-EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_get_fields", "lbm_set_wall_mu",
+EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lbm_get_fields",
+            "lbm_set_wall_mu",
             "lbm_get_monitors", "lbm_monitor_step", "lbm_get_state", "lbm_set_state",
             "lbm_get_temperature", "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_critical_point",
             "lbm_coexistence", "lbm_eos_eval", "lbm_contact_angle"]
@@ -66,13 +72,15 @@ class LbmDiverged(LbmError):
 
 
 _lib = None
+_torch_runtime = False   # True when PyTorch's HIP runtime was in the process first
 
 
 def load_library():
     """Loads liblbm.so; raises if it has not been built (no CPU fallback exists)."""
-    global _lib
+    global _lib, _torch_runtime
     if _lib is not None:
         return _lib
+    _torch_runtime = "torch" in sys.modules
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("liblbm.so is not built: run `python -m paper_1611_00907_amd.build`")
     lib = C.CDLL(LIB_PATH)
@@ -82,6 +90,7 @@ def load_library():
     lib.lbm_workspace_bytes.restype = C.c_size_t
     lib.lbm_init.argtypes = [P, vp, vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.lbm_step.argtypes = [vp, C.c_int64]
+    lib.lbm_step_timed.argtypes = [vp, C.c_int64, dp]
     lib.lbm_get_fields.argtypes = [vp, vp, vp, vp, vp]
     lib.lbm_set_wall_mu.argtypes = [vp, C.c_int32, vp, C.c_int32]
     lib.lbm_get_monitors.argtypes = [vp, dp, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
@@ -173,6 +182,9 @@ def lbm_workspace_bytes(p: LbmParams) -> int:
 # ---------------------------------------------------------------- lattice
 def _torch_workspace(nbytes: int):
     """Device workspace and current stream from PyTorch (plumbing only)."""
+    if not _torch_runtime:
+        raise RuntimeError("workspace='torch' needs `import torch` before liblbm.so is loaded, so that "
+                           "the library binds to PyTorch's HIP runtime")
     import torch
 
     if not torch.cuda.is_available():
@@ -181,16 +193,16 @@ def _torch_workspace(nbytes: int):
     return ws, int(ws.data_ptr()), int(torch.cuda.current_stream().cuda_stream)
 
 
-def lbm_init(p: LbmParams, rho0, ux0=None, uy0=None, workspace="torch"):
-    """Returns a Lattice owning the context; workspace 'torch' takes device memory
-    from PyTorch and its current stream, None lets the library allocate."""
+def lbm_init(p: LbmParams, rho0, ux0=None, uy0=None, workspace=None):
+    """Returns a Lattice owning the context; workspace None lets the library
+    allocate, 'torch' takes device memory and the current stream from PyTorch."""
     return Lattice(p, rho0, ux0, uy0, workspace)
 
 
 class Lattice:
     """One lattice on the GPU: a thin owner of an ``lbm_ctx``."""
 
-    def __init__(self, p: LbmParams, rho0, ux0=None, uy0=None, workspace="torch"):
+    def __init__(self, p: LbmParams, rho0, ux0=None, uy0=None, workspace=None):
         self.lib = load_library()
         self.p = p
         self.nx, self.ny = p.nx, p.ny
@@ -214,6 +226,12 @@ class Lattice:
 
     def step(self, n: int = 1):
         _check(self.lib.lbm_step(self.ctx, int(n)), "lbm_step")
+
+    def step_timed(self, n: int) -> float:
+        """Milliseconds of device time for n steps (HIP events on the lattice's stream)."""
+        ms = C.c_double()
+        _check(self.lib.lbm_step_timed(self.ctx, int(n), C.byref(ms)), "lbm_step_timed")
+        return ms.value
 
     def monitor_step(self):
         _check(self.lib.lbm_monitor_step(self.ctx), "lbm_monitor_step")
