@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-aux", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30,
+                    help="size of the plain copy whose bandwidth is reported beside the roofline")
     return ap.parse_args()
 
 
@@ -66,6 +68,45 @@ def spinodal_workload(lbm, inputs, prec, n=4096):
     _, rc, _ = lbm.lbm_critical_point(lbm.LBM_EOS_VDW, 9 / 49, 2 / 21, 1.0)
     rho0 = inputs.with_relative_noise(np.full((n, n), rc), 0.01, 3)
     return p, rho0, None, n * n
+
+
+def batch_workload(lbm, inputs, n_cases=256, seed=4):
+    """The batching configuration: n droplet-on-wall cases, side ~ U{128..512},
+    CS or PR (50/50), Tr ~ U[0.6, 0.9], drop radius 0.25 side on a CP wall whose
+    mu_w is drawn around the case's coexistence chemical potential."""
+    u = inputs.uniform(seed, 4 * n_cases).reshape(n_cases, 4)
+    params, rhos, muw = [], [], []
+    for k in range(n_cases):
+        side = 128 + int(u[k, 0] * 385)
+        eos = lbm.LBM_EOS_CS if u[k, 1] < 0.5 else lbm.LBM_EOS_PR
+        Tr = 0.6 + 0.3 * u[k, 2]
+        a, b = (1.0, 4.0) if eos == lbm.LBM_EOS_CS else (2 / 49, 2 / 21)
+        om = 0.0 if eos == lbm.LBM_EOS_CS else 0.344
+        p = lbm.make_params(side, side, eos, a, b, Tr, 1.3, 0.01, omega=om, prec=lbm.LBM_F32,
+                            bc_bottom=lbm.LBM_BC_CPWALL, bc_top=lbm.LBM_BC_NEUTRAL)
+        rg, rl, _, mu_sat = lbm.lbm_coexistence(p)
+        span = 0.2 if eos == lbm.LBM_EOS_PR else 0.02
+        params.append(p)
+        rhos.append(inputs.sessile_drop(side, side, rl, rg, 0.25 * side))
+        muw.append(mu_sat + span * (2 * u[k, 3] - 1))
+    return params, rhos, muw
+
+
+def measure_batch(lbm, inputs, steps):
+    params, rhos, muw = batch_workload(lbm, inputs)
+    b = lbm.Batch(params, rhos, mu_w_bottom=muw)
+    nodes = b.fluid_nodes()
+    ty, bpc, ms_tuned = b.tune(trial_steps=10)
+    b.step(20)
+    n = max(steps // 16, 1) * 16
+    t = b.step_timed(n) / 1e3
+    b.close()
+    return {"workload": "batch of 256 droplet-on-wall cases, side 128-512, CS/PR, Tr 0.6-0.9, f32 storage",
+            "fluid_nodes": nodes, "mlups": round(nodes * n / t / 1e6, 1),
+            "ms_per_step": round(t / n * 1e3, 4), "tile_y": ty, "blocks_per_cu": bpc,
+            "roofline": {"bound": "hbm", "achieved": round(nodes * 72.0 * n / t / 1e9, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(nodes * 72.0 * n / t / 1e9 / PEAK_HBM_GBS, 4),
+                         "traffic": None}}
 
 
 def traffic_for(workload: str, bytes_per_launch: float):
@@ -151,6 +192,8 @@ def main():
 
     lbm.load_library()
 
+    copy_gbs = lbm.lbm_copy_bandwidth(args.copy_bytes, 20)
+    print("copy: %.1f GB/s over %d bytes" % (copy_gbs, args.copy_bytes), file=sys.stderr, flush=True)
     p, rho0, mu_w, fluid = wetting_workload(lbm, inputs, lbm.LBM_F32)
     main_res = measure(lbm, p, rho0, mu_w, fluid, args.steps, args.warmup, 72.0,
                        "step_f32_wetting1024")
@@ -169,6 +212,11 @@ def main():
                         "roofline": res["roofline"]})
             print("aux %s: %.1f MLUPS %.1f GB/s" % (name, res["mlups"], res["roofline"]["achieved"]),
                   file=sys.stderr, flush=True)
+        res = measure_batch(lbm, inputs, 320)
+        aux.append(res)
+        print("aux batch: %.1f MLUPS %.1f GB/s (tile %d, %d/CU)" % (res["mlups"], res["roofline"]["achieved"],
+                                                                   res["tile_y"], res["blocks_per_cu"]),
+              file=sys.stderr, flush=True)
 
     line = {
         "metric": "MLUPS + % HBM roofline; time-to-equilibrium (surrogate vs plain) at 0.5deg",
@@ -188,6 +236,8 @@ def main():
                    "nx": 1024, "ny": 1024, "storage": "f32", "parallelism": "single GPU"},
         "roofline": main_res["roofline"],
         "kernel_us": round(main_res["kernel_us"], 3),
+        "copy_kernel": {"bytes": args.copy_bytes, "gbs": round(copy_gbs, 1),
+                        "step_frac_of_copy": round(main_res["roofline"]["achieved"] / copy_gbs, 4)},
         "aux": aux,
     }
     if not args.no_cpu_baseline:

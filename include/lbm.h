@@ -115,6 +115,15 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n);
  * monitors included.  Synchronises. */
 lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* ms);
 
+/* Tile-shape tuner: times trial_steps fused steps for each supported tile height
+ * (8, 16, 32 rows of 64 columns) without changing the state (every trial maps the
+ * current state to the spare buffer), keeps the fastest for this context and
+ * returns it with its time per step in ms.  Synchronises. */
+lbm_status lbm_tune(lbm_ctx* c, int32_t trial_steps, int32_t* tile_y, double* best_ms);
+
+/* Sets the tile height (8, 16 or 32) directly; LBM_EINVAL for other values. */
+lbm_status lbm_set_tile(lbm_ctx* c, int32_t tile_y);
+
 /* Output fields of the current state into host arrays [ny][nx]: density (Eq 28
  * values on solid rows), physical velocity v = u + F / (2 rho) (forcing
  * paragraph after Eq 14; 0 on solid rows), and chemical potential (Eq 8; the
@@ -150,6 +159,66 @@ const char* lbm_strerror(lbm_status s);
 /* Text of the last HIP failure behind an LBM_EHIP in this thread ("" if none):
  * the failing call and the HIP error name.  Owned by the library. */
 const char* lbm_last_error(void);
+
+/* ---- many lattices in one launch ---------------------------------------- */
+
+/* A batch of independent lattices (sizes, EOS, temperature, tau, kappa, walls may
+ * differ; the storage precision must be the same) advanced together: each step is
+ * one persistent launch over the (case, tile) list of the active cases, and runs
+ * of steps are replayed as captured HIP graphs. */
+typedef struct lbm_batch lbm_batch;
+
+/* Device bytes for a batch (0 if any case is invalid or precisions differ). */
+size_t lbm_batch_workspace_bytes(const lbm_params* cases, int32_t n);
+
+/* rho0[i] is the host [ny][nx] initial density of case i (fluid at rest);
+ * mu_w_bottom (may be NULL = 0) gives each case's uniform surface chemical
+ * potential of a CP bottom wall.  Workspace and stream conventions as lbm_init.
+ * Errors as lbm_init, for the first failing case. */
+lbm_status lbm_batch_init(const lbm_params* cases, int32_t n, const double* const* rho0,
+                          const double* mu_w_bottom, void* dev_workspace, size_t workspace_bytes,
+                          void* hip_stream, lbm_batch** out);
+
+/* n steps of every active case (no convergence checks). */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t n);
+
+/* lbm_batch_step bracketed by HIP events on the batch's stream; *ms = device time. */
+lbm_status lbm_batch_step_timed(lbm_batch* b, int64_t n, double* ms);
+
+/* Runs until every case has converged or diverged, or max_steps have passed.  Every
+ * check_every steps each active case's residual max|rho(t) - rho(t - window)| / window
+ * (FP64 over its fluid nodes) is compared with tol: below tol the case converges and
+ * stops; a non-finite or out-of-domain density marks it diverged and stops it.  The
+ * other cases continue.  1 <= window <= check_every. */
+lbm_status lbm_batch_run(lbm_batch* b, int64_t max_steps, int32_t check_every, int32_t window,
+                         double tol, int64_t* steps_run);
+
+/* Per-case arrays of n entries (any may be NULL): state 0 active, 1 converged,
+ * 2 diverged; steps taken; last residual; last mass; last divergence flags. */
+lbm_status lbm_batch_status(lbm_batch* b, int32_t* state, int64_t* steps, double* residual,
+                            double* mass, int32_t* flags);
+
+/* Output fields / distributions of case i, as lbm_get_fields / lbm_get_state. */
+lbm_status lbm_batch_get_fields(lbm_batch* b, int32_t i, double* rho, double* vx, double* vy,
+                                double* mu);
+lbm_status lbm_batch_get_state(lbm_batch* b, int32_t i, double* f);
+
+/* Tunes the tile height and the persistent grid (workgroups per CU) on the active
+ * cases without changing their state; keeps and returns the fastest. */
+lbm_status lbm_batch_tune(lbm_batch* b, int32_t trial_steps, int32_t* tile_y,
+                          int32_t* blocks_per_cu, double* best_ms);
+
+/* Fluid nodes of all cases (active_only != 0: of the active ones); -1 for NULL. */
+int64_t lbm_batch_fluid_nodes(lbm_batch* b, int32_t active_only);
+
+void lbm_batch_destroy(lbm_batch* b);
+
+/* ---- measurement -------------------------------------------------------- */
+
+/* Bandwidth of a plain device-to-device copy of `bytes` (a multiple of 16)
+ * repeated iters times: (read + written bytes) / time in GB/s, timed with HIP
+ * events on a private stream.  Allocates and frees two device buffers. */
+lbm_status lbm_copy_bandwidth(size_t bytes, int32_t iters, double* gbps);
 
 /* ---- host thermodynamics tools (FP64) ---------------------------------- */
 

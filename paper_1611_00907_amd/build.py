@@ -1,5 +1,9 @@
 """Builds the HIP library ``liblbm.so`` in-tree for gfx950 with hipcc.
 
+The kernel file is compiled once per storage type (FP64, FP32, FP16 and BF16
+deviation storage) so the objects build in parallel; the host files and the
+dispatch are separate objects; hipcc links them into one shared library.
+
 Usage: ``python -m paper_1611_00907_amd.build`` (or ``__graft_entry__.build()``).
 """
 from __future__ import annotations
@@ -8,18 +12,23 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
+OBJ = os.path.join(PKG, "_build")
 
-SOURCES = ["lbm_kernels.hip", "lbm_host.cpp", "thermo_host.cpp"]
-HEADERS = ["lbm_internal.h", "thermo_host.h"]
+KERNEL_SOURCE = "lbm_kernels.hip"
+STORAGE = [("double", "f64"), ("float", "f32"), ("__half", "f16dev"), ("__hip_bfloat16", "bf16dev")]
+HOST_SOURCES = ["lbm_dispatch.cpp", "lbm_host.cpp", "lbm_batch.cpp", "thermo_host.cpp"]
+HEADERS = ["lbm_internal.h", "lbm_common.h", "thermo_host.h"]
+SOURCES = [KERNEL_SOURCE] + HOST_SOURCES
 
 ARCH = "gfx950"
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # keep the compiler from forming packed FP32 instructions (v_pk_*_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
@@ -33,19 +42,43 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def command(out: str) -> list:
-    return [hipcc()] + FLAGS + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", out]
+def compile_commands():
+    cmds = []
+    for st, sfx in STORAGE:
+        out = os.path.join(OBJ, "lbm_kernels_%s.o" % sfx)
+        cmds.append((out, [hipcc()] + FLAGS + ["-DCPLBM_ST=%s" % st, "-DCPLBM_SUFFIX=%s" % sfx, "-c",
+                                               os.path.join(CSRC, KERNEL_SOURCE), "-o", out]))
+    for src in HOST_SOURCES:
+        out = os.path.join(OBJ, src.replace(".cpp", ".o"))
+        cmds.append((out, [hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", out]))
+    return cmds
 
 
 def build(verbose: bool = True) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    cmds = compile_commands()
+
+    def run(cmd):
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        return cmd, r
+
+    jobs = max(1, min(len(cmds), os.cpu_count() or 4, 16))
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(lambda c: run(c[1]), cmds))
+    for cmd, r in results:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc failed: %s" % cmd[-3])
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = command(tmp)
+    link = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}"] + [c[0] for c in cmds] + ["-o", tmp]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
+        print(" ".join(link), flush=True)
+    r = subprocess.run(link, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building liblbm.so")
+        raise RuntimeError("hipcc failed linking liblbm.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -5,12 +5,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <vector>
 
-#include "lbm.h"
-#include "lbm_internal.h"
-#include "thermo_host.h"
+#include "lbm_common.h"
 
 using namespace cplbm;
 
@@ -19,7 +18,9 @@ struct lbm_ctx {
     LatticeArgs A;
     thermo::Fluid fluid;
     hipStream_t stream = nullptr;
+    bool own_stream = false;
     int device = 0;
+    hipGraphExec_t graph = nullptr;  // GRAPH_STEPS fused steps from parity 0, captured on demand
     char* ws = nullptr;
     bool own_ws = false;
     void* f[2] = {nullptr, nullptr};
@@ -37,19 +38,20 @@ struct lbm_ctx {
     std::vector<double> mu_w_host;  // [2][nx]
 };
 
-namespace {
+namespace cplbm {
+namespace host {
 
-constexpr int PITCH_ALIGN = 64;
+thread_local char g_last_error[256] = "";
 
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+void note_error(hipError_t e, const char* where) {
+    std::snprintf(g_last_error, sizeof g_last_error, "%s: %s (%d)", where, hipGetErrorName(e), (int)e);
+}
 
-struct Layout {
-    int pitch;
-    long long plane;
-    size_t f0, f1, rho_mon, mu_w, partials, mon, total;
-};
-
-bool walled(const lbm_params& p) { return p.bc_bottom != LBM_BC_PERIODIC; }
+lbm_status hip_status(hipError_t e, const char* where) {
+    if (e == hipSuccess) return LBM_OK;
+    note_error(e, where);
+    return LBM_EHIP;
+}
 
 lbm_status validate(const lbm_params* p) {
     if (!p) return LBM_EINVAL;
@@ -100,8 +102,7 @@ LatticeArgs lattice_args(const lbm_params& p, const thermo::Fluid& fl, const Lay
     A.pitch = L.pitch;
     A.bottom = p.bc_bottom;
     A.top = p.bc_top;
-    A.tiles_x = (p.nx + TILE_X - 1) / TILE_X;
-    A.tiles_y = (p.ny + TILE_Y - 1) / TILE_Y;
+    A.tile_y = TILE_Y_DEFAULT;
     A.plane = L.plane;
     A.tau = p.tau;
     A.inv_tau = 1.0 / p.tau;
@@ -131,28 +132,67 @@ LatticeArgs lattice_args(const lbm_params& p, const thermo::Fluid& fl, const Lay
     return A;
 }
 
-thread_local char g_last_error[256] = "";
-
-void note_error(hipError_t e, const char* where) {
-    std::snprintf(g_last_error, sizeof g_last_error, "%s: %s (%d)", where, hipGetErrorName(e), (int)e);
+lbm_status check_initial(const lbm_params& p, const double* rho0, const double* ux0, const double* uy0) {
+    if (!rho0) return LBM_EINVAL;
+    const double pole = thermo::rho_pole(p.eos, p.b);
+    for (int y = 0; y < p.ny; ++y) {
+        if (is_solid_row(p, y)) continue;
+        for (int x = 0; x < p.nx; ++x) {
+            const size_t i = (size_t)y * p.nx + x;
+            const double r = rho0[i];
+            if (!(std::isfinite(r) && r > 0.0 && r < pole)) return LBM_EDOMAIN;
+            if ((ux0 && !std::isfinite(ux0[i])) || (uy0 && !std::isfinite(uy0[i]))) return LBM_EDOMAIN;
+        }
+    }
+    return LBM_OK;
 }
 
-lbm_status hip_status(hipError_t e, const char* where = "hip") {
-    if (e == hipSuccess) return LBM_OK;
-    note_error(e, where);
-    return LBM_EHIP;
+lbm_status init_state(const lbm_params& p, const LatticeArgs& A, const double* rho0, const double* ux0,
+                      const double* uy0, void* fstore, hipStream_t s) {
+    const size_t n = (size_t)p.nx * p.ny;
+    double* staging = nullptr;
+    const size_t sbytes = n * sizeof(double);
+    const char* where = "hipMalloc(staging)";
+    hipError_t e = hipMalloc(&staging, 3 * sbytes);
+    if (e == hipSuccess) e = hipMemcpyAsync(staging, rho0, sbytes, hipMemcpyHostToDevice, s), where = "copy rho0";
+    if (e == hipSuccess && ux0) e = hipMemcpyAsync(staging + n, ux0, sbytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && uy0) e = hipMemcpyAsync(staging + 2 * n, uy0, sbytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_init(p.prec, A, staging, ux0 ? staging + n : nullptr, uy0 ? staging + 2 * n : nullptr, nullptr,
+                        fstore, s),
+        where = "init kernel";
+    if (e == hipSuccess) e = hipStreamSynchronize(s), where = "hipStreamSynchronize(init)";
+    if (staging) (void)hipFree(staging);
+    return hip_status(e, where);
 }
 
-#define HIP_TRY(expr)                                   \
-    do {                                                \
-        hipError_t e_ = (expr);                         \
-        if (e_ != hipSuccess) {                         \
-            note_error(e_, #expr);                      \
-            return LBM_EHIP;                            \
-        }                                               \
-    } while (0)
+lbm_status upload_mu_w(const lbm_params& p, int pitch, const double* mu_w_host, void* mu_w_dev, hipStream_t s) {
+    const int nx = p.nx;
+    if (p.prec == LBM_F64) {
+        std::vector<double> buf(2 * (size_t)pitch, 0.0);
+        for (int w = 0; w < 2; ++w)
+            for (int x = 0; x < nx; ++x) buf[(size_t)w * pitch + x] = mu_w_host[(size_t)w * nx + x];
+        HIP_TRY(hipMemcpyAsync(mu_w_dev, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    } else {
+        std::vector<float> buf(2 * (size_t)pitch, 0.0f);
+        for (int w = 0; w < 2; ++w)
+            for (int x = 0; x < nx; ++x) buf[(size_t)w * pitch + x] = (float)mu_w_host[(size_t)w * nx + x];
+        HIP_TRY(hipMemcpyAsync(mu_w_dev, buf.data(), buf.size() * sizeof(float), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    return LBM_OK;
+}
 
-bool is_solid_row(const lbm_params& p, int y) { return walled(p) && (y == 0 || y == p.ny - 1); }
+}  // namespace host
+}  // namespace cplbm
+
+using namespace cplbm::host;
+
+namespace {
+
+// Fused steps per captured HIP graph (even, so a replay returns to buffer 0).
+constexpr int GRAPH_STEPS = 32;
 
 // Monitor pass over the current state; compare == 1 also reads the results back.
 lbm_status run_monitor(lbm_ctx* c, int compare) {
@@ -169,6 +209,33 @@ lbm_status run_monitor(lbm_ctx* c, int compare) {
     return c->flags ? LBM_EDIVERGED : LBM_OK;
 }
 
+// Replays (capturing on first use) GRAPH_STEPS fused steps starting from parity 0;
+// GRAPH_STEPS is even, so the state ends in buffer 0 again.
+lbm_status run_graph(lbm_ctx* c) {
+    if (!c->graph) {
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int s = 0; s < GRAPH_STEPS && e == hipSuccess; ++s)
+            e = launch_step(c->p.prec, c->p.eos, MODE_STEP, c->A, c->f[s & 1], c->f[(s & 1) ^ 1], c->mu_w, nullptr,
+                            c->stream);
+        hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_status(e != hipSuccess ? e : e2, "graph capture");
+        }
+        e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->graph = nullptr;
+            return hip_status(e, "hipGraphInstantiate");
+        }
+    }
+    HIP_TRY(hipGraphLaunch(c->graph, c->stream));
+    c->step += GRAPH_STEPS;
+    return LBM_OK;
+}
+
 lbm_status one_step(lbm_ctx* c) {
     HIP_TRY(launch_step(c->p.prec, c->p.eos, MODE_STEP, c->A, c->f[c->cur], c->f[c->cur ^ 1], c->mu_w, nullptr,
                         c->stream));
@@ -178,25 +245,18 @@ lbm_status one_step(lbm_ctx* c) {
 }
 
 lbm_status upload_mu_w(lbm_ctx* c) {
-    const int nx = c->p.nx, pitch = c->A.pitch;
-    if (c->p.prec == LBM_F64) {
-        std::vector<double> buf(2 * (size_t)pitch, 0.0);
-        for (int w = 0; w < 2; ++w)
-            for (int x = 0; x < nx; ++x) buf[(size_t)w * pitch + x] = c->mu_w_host[(size_t)w * nx + x];
-        HIP_TRY(hipMemcpyAsync(c->mu_w, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
-    } else {
-        std::vector<float> buf(2 * (size_t)pitch, 0.0f);
-        for (int w = 0; w < 2; ++w)
-            for (int x = 0; x < nx; ++x) buf[(size_t)w * pitch + x] = (float)c->mu_w_host[(size_t)w * nx + x];
-        HIP_TRY(hipMemcpyAsync(c->mu_w, buf.data(), buf.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
-    }
-    return LBM_OK;
+    return cplbm::host::upload_mu_w(c->p, c->A.pitch, c->mu_w_host.data(), c->mu_w, c->stream);
+}
+
+void drop_graph(lbm_ctx* c) {
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
 }
 
 void release(lbm_ctx* c) {
     if (!c) return;
+    drop_graph(c);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->mon_host) (void)hipHostFree(c->mon_host);
     delete c;
@@ -220,17 +280,8 @@ lbm_status lbm_init(const lbm_params* p, const double* rho0, const double* ux0, 
     if (!rho0) return LBM_EINVAL;
     const thermo::Fluid fl = thermo::make_fluid(p->eos, p->a, p->b, p->R, p->Tr, p->omega);
     if (!(std::isfinite(fl.T) && fl.T > 0 && std::isfinite(fl.alpha))) return LBM_EINVAL;
-    const double pole = thermo::rho_pole(p->eos, p->b);
-    const size_t n = (size_t)p->nx * p->ny;
-    for (int y = 0; y < p->ny; ++y) {
-        if (is_solid_row(*p, y)) continue;
-        for (int x = 0; x < p->nx; ++x) {
-            const size_t i = (size_t)y * p->nx + x;
-            const double r = rho0[i];
-            if (!(std::isfinite(r) && r > 0.0 && r < pole)) return LBM_EDOMAIN;
-            if ((ux0 && !std::isfinite(ux0[i])) || (uy0 && !std::isfinite(uy0[i]))) return LBM_EDOMAIN;
-        }
-    }
+    st = check_initial(*p, rho0, ux0, uy0);
+    if (st != LBM_OK) return st;
     const Layout L = layout_of(*p);
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return LBM_ENOMEM;
@@ -241,6 +292,15 @@ lbm_status lbm_init(const lbm_params* p, const double* rho0, const double* ux0, 
         note_error(e0, "hipGetDevice");
         release(c);
         return LBM_EHIP;
+    }
+    if (!c->stream) {  // a stream of our own (default priority), so that steps can be graph-captured
+        if (hipError_t e0 = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking); e0 != hipSuccess) {
+            note_error(e0, "hipStreamCreateWithFlags");
+            c->stream = nullptr;
+            release(c);
+            return LBM_EHIP;
+        }
+        c->own_stream = true;
     }
     if (dev_workspace) {
         if (workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(dev_workspace) & 255)) {
@@ -270,24 +330,15 @@ lbm_status lbm_init(const lbm_params* p, const double* rho0, const double* ux0, 
     c->mu_w_host.assign(2 * (size_t)p->nx, 0.0);
 
     // f(0) = f_eq(rho0, u0), stored in the pulled form.
-    double* staging = nullptr;
-    const size_t sbytes = n * sizeof(double);
-    const char* where = "hipMalloc(staging)";
-    hipError_t e = hipMalloc(&staging, 3 * sbytes);
-    if (e == hipSuccess) e = hipMemsetAsync(c->ws, 0, L.total, c->stream), where = "hipMemsetAsync(workspace)";
-    if (e == hipSuccess) e = hipMemcpyAsync(staging, rho0, sbytes, hipMemcpyHostToDevice, c->stream), where = "copy rho0";
-    if (e == hipSuccess && ux0) e = hipMemcpyAsync(staging + n, ux0, sbytes, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess && uy0) e = hipMemcpyAsync(staging + 2 * n, uy0, sbytes, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess)
-        e = launch_init(p->prec, c->A, staging, ux0 ? staging + n : nullptr, uy0 ? staging + 2 * n : nullptr,
-                        nullptr, c->f[0], c->stream),
-        where = "init kernel";
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream), where = "hipStreamSynchronize(init)";
-    if (staging) (void)hipFree(staging);
-    if (e != hipSuccess) {
-        note_error(e, where);
+    if (hipError_t e = hipMemsetAsync(c->ws, 0, L.total, c->stream); e != hipSuccess) {
+        note_error(e, "hipMemsetAsync(workspace)");
         release(c);
         return LBM_EHIP;
+    }
+    st = init_state(*p, c->A, rho0, ux0, uy0, c->f[0], c->stream);
+    if (st != LBM_OK) {
+        release(c);
+        return st;
     }
     st = upload_mu_w(c);
     if (st != LBM_OK) {
@@ -302,12 +353,27 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     if (!c || n < 0) return LBM_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return LBM_EHIP;
     const int m = c->p.monitor_every;
-    for (int64_t s = 0; s < n; ++s) {
+    int64_t left = n;
+    while (left > 0) {
         if (m > 0 && (c->step + 1) % m == 0 && c->snap_step != c->step) {
-            lbm_status st = run_monitor(c, 0);
+            lbm_status st = run_monitor(c, 0);  // snapshot one step before a monitor point
             if (st != LBM_OK) return st;
         }
-        lbm_status st = one_step(c);
+        // steps that can run before the next monitor event (snapshot or compare)
+        int64_t run = left;
+        if (m > 0) {
+            int64_t to_event = (m - 1 - c->step % m) % m;
+            if (to_event == 0) to_event = 1;
+            run = std::min(run, to_event);
+        }
+        lbm_status st;
+        if (run >= GRAPH_STEPS && c->cur == 0) {
+            st = run_graph(c);
+            left -= GRAPH_STEPS;
+        } else {
+            st = one_step(c);
+            --left;
+        }
         if (st != LBM_OK) return st;
         if (m > 0 && c->step % m == 0) {
             st = run_monitor(c, 1);
@@ -339,6 +405,63 @@ lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* ms) {
     if (e != hipSuccess) return hip_status(e, "lbm_step_timed");
     *ms = t;
     return st;
+}
+
+lbm_status lbm_tune(lbm_ctx* c, int32_t trial_steps, int32_t* tile_y, double* best_ms) {
+    if (!c || trial_steps < 1) return LBM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LBM_EHIP;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipError_t e = hipEventCreate(&e1); e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_status(e, "hipEventCreate");
+    }
+    double best = 1e300;
+    int best_ty = c->A.tile_y;
+    hipError_t e = hipSuccess;
+    for (int ty : TILE_Y_CHOICES) {
+        LatticeArgs A = c->A;
+        A.tile_y = ty;
+        // trial launches only read the state: each maps f[cur] -> f[cur ^ 1]
+        for (int w = 0; w < 2 && e == hipSuccess; ++w)
+            e = launch_step(c->p.prec, c->p.eos, MODE_STEP, A, c->f[c->cur], c->f[c->cur ^ 1], c->mu_w, nullptr,
+                            c->stream);
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int s = 0; s < trial_steps && e == hipSuccess; ++s)
+            e = launch_step(c->p.prec, c->p.eos, MODE_STEP, A, c->f[c->cur], c->f[c->cur ^ 1], c->mu_w, nullptr,
+                            c->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        if (ms < best) {
+            best = ms;
+            best_ty = ty;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_status(e, "lbm_tune");
+    if (best_ty != c->A.tile_y) {
+        c->A.tile_y = best_ty;
+        drop_graph(c);
+    }
+    if (tile_y) *tile_y = best_ty;
+    if (best_ms) *best_ms = best / trial_steps;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_tile(lbm_ctx* c, int32_t tile_y) {
+    if (!c) return LBM_EINVAL;
+    bool ok = false;
+    for (int ty : TILE_Y_CHOICES) ok = ok || ty == tile_y;
+    if (!ok) return LBM_EINVAL;
+    if (tile_y != c->A.tile_y) {
+        c->A.tile_y = tile_y;
+        drop_graph(c);
+    }
+    return LBM_OK;
 }
 
 lbm_status lbm_monitor_step(lbm_ctx* c) {
@@ -435,6 +558,34 @@ void lbm_destroy(lbm_ctx* c) {
 }
 
 const char* lbm_last_error(void) { return g_last_error; }
+
+lbm_status lbm_copy_bandwidth(size_t bytes, int32_t iters, double* gbps) {
+    if (bytes < 16 || (bytes & 15) || iters < 1 || !gbps) return LBM_EINVAL;
+    void *a = nullptr, *b = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&a, bytes);
+    if (e == hipSuccess) e = hipMalloc(&b, bytes);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMemsetAsync(a, 0, bytes, s);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch_copy(a, b, bytes, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int i = 0; i < iters && e == hipSuccess; ++i) e = launch_copy((i & 1) ? b : a, (i & 1) ? a : b, bytes, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (e != hipSuccess) return hip_status(e, "lbm_copy_bandwidth");
+    *gbps = 2.0 * double(bytes) * iters / (ms * 1e-3) / 1e9;
+    return LBM_OK;
+}
 
 const char* lbm_strerror(lbm_status s) {
     switch (s) {

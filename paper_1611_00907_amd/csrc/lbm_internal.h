@@ -11,12 +11,13 @@ enum Eos : int { EOS_VDW = 0, EOS_CS = 1, EOS_PR = 2, EOS_RKS = 3, EOS_RK = 4 };
 enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_F16DEV = 2, PREC_BF16DEV = 3 };
 enum Bc : int { BC_PERIODIC = 0, BC_CPWALL = 1, BC_NEUTRAL = 2 };
 
-// Tile of the fused step: TX x TY nodes per workgroup of TX x (TY / ROWS_PER_THREAD)
-// threads; each thread owns ROWS_PER_THREAD nodes of one column.
+// Tile of the fused step: TILE_X x tile_y nodes per workgroup of TILE_X * tile_y /
+// ROWS_PER_THREAD threads; each thread owns ROWS_PER_THREAD nodes of one column.
+// tile_y is one of TILE_Y_CHOICES (picked per lattice by the tuner; default 16).
 constexpr int TILE_X = 64;
-constexpr int TILE_Y = 16;
 constexpr int ROWS_PER_THREAD = 4;
-constexpr int BLOCK_THREADS = TILE_X * (TILE_Y / ROWS_PER_THREAD);
+constexpr int TILE_Y_DEFAULT = 16;
+constexpr int TILE_Y_CHOICES[3] = {8, 16, 32};
 
 // Constants of the bulk chemical potential, precomputed on the host in FP64.
 struct EosConst {
@@ -32,7 +33,7 @@ struct LatticeArgs {
     int nx, ny;
     int pitch;            // elements per row (>= nx)
     int bottom, top;      // Bc of rows 0 and ny-1
-    int tiles_x, tiles_y; // tile grid
+    int tile_y;           // rows per tile (one of TILE_Y_CHOICES)
     long long plane;      // elements per direction plane = ny * pitch
     double tau, inv_tau, kappa;
     double rho_ref;       // deviation base of the half/bf16 storage
@@ -40,6 +41,16 @@ struct LatticeArgs {
 };
 
 enum StepMode : int { MODE_STEP = 0, MODE_FIELDS = 1 };
+
+// One lattice of a batch, as the batched kernels see it.
+struct CaseDesc {
+    LatticeArgs A;
+    int eos;
+    int pad_;
+    void* f[2];         // the two distribution buffers (storage type of the batch)
+    const void* mu_w;   // [2][pitch] wall chemical potentials, compute type
+    void* rho_mon;      // density snapshot, compute type
+};
 
 // Fused step (or field output) over the whole lattice.
 // fin: storage of the post-collision distributions f*(t-1) (pulled to give f(t));
@@ -53,7 +64,18 @@ hipError_t launch_step(int prec, int eos, int mode, const LatticeArgs& A, const 
 // them into mon[0..2] (mass, residual, flags as double).
 hipError_t launch_monitor(int prec, int eos, int compare, const LatticeArgs& A, const void* fin,
                           void* rho_mon, double* partials, double* mon, hipStream_t s);
-int monitor_blocks(const LatticeArgs& A);
+
+// All cases of a batch advance one step: tiles is the (case, tile) list of the active
+// cases, grid the number of persistent workgroups, parity selects f[parity] -> f[parity^1].
+hipError_t launch_batch_step(int prec, int tile_y, const CaseDesc* cases, const int2* tiles, int ntiles, int parity,
+                             int grid, hipStream_t s);
+// Batched monitors over the same tile list: partials [3][ntiles]; compare == 1 reduces each
+// case's tile range [case_tile_begin[c], case_tile_begin[c+1]) into case_mon[3 c .. 3 c + 2].
+hipError_t launch_batch_monitor(int prec, int compare, int tile_y, const CaseDesc* cases, const int2* tiles,
+                                int ntiles, int parity, double* partials, const int* case_tile_begin, int ncases,
+                                double* case_mon, hipStream_t s);
+// Resident workgroups per CU of the batched step kernel (for the persistent grid).
+int batch_blocks_per_cu(int prec, int tile_y);
 
 // f_i(t) from f_eq(rho0, u0) (init, u may be null) or from given f (set_state): writes the
 // storage form f*(t-1) such that streaming reproduces f(t).  rho0/ux0/uy0/f_in are device
@@ -64,6 +86,9 @@ hipError_t launch_init(int prec, const LatticeArgs& A, const double* rho0, const
 // f_i(t) [9][ny][nx] doubles from the storage (zero on solid rows).
 hipError_t launch_get_state(int prec, const LatticeArgs& A, const void* fstore, double* f_out,
                             hipStream_t s);
+
+// Plain device copy of bytes (a multiple of 16) from src to dst.
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 size_t storage_bytes(int prec);
 size_t compute_bytes(int prec);

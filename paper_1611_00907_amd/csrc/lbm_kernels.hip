@@ -20,6 +20,10 @@
 
 #include "lbm_internal.h"
 
+#ifndef CPLBM_ST
+#error "compile this file once per storage type: -DCPLBM_ST=float -DCPLBM_SUFFIX=f32, ..."
+#endif
+
 namespace cplbm {
 namespace {
 
@@ -232,25 +236,34 @@ __device__ __forceinline__ int tile_of_block(int b, int nblk) {
 }
 
 // ---------------------------------------------------------------- the fused step
-template <typename ST, int EOS, int MODE>
-__global__ __launch_bounds__(BLOCK_THREADS) void step_kernel(LatticeArgs A, const ST* __restrict__ fin,
-                                                             ST* __restrict__ fout,
-                                                             const typename Codec<ST>::CT* __restrict__ mu_w,
-                                                             double* __restrict__ out) {
+template <typename CT, int TY>
+struct TileLds {
+    CT rs[TY + 4][TILE_X + 4];  // density, tile + 2-node ring
+    CT ms[TY + 2][TILE_X + 2];  // chemical potential, tile + 1-node ring
+};
+
+// One TILE_X x TY tile of the step (MODE_STEP) or of the field output (MODE_FIELDS),
+// run by a workgroup of TILE_X * TY / ROWS_PER_THREAD threads.
+template <typename ST, int EOS, int MODE, int TY>
+__device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __restrict__ fin,
+                                          ST* __restrict__ fout,
+                                          const typename Codec<ST>::CT* __restrict__ mu_w,
+                                          double* __restrict__ out, int x0, int y0,
+                                          TileLds<typename Codec<ST>::CT, TY>& L) {
     using CT = typename Codec<ST>::CT;
     using C = Codec<ST>;
     constexpr int RW = TILE_X + 4, MW = TILE_X + 2;
-    __shared__ CT rs[TILE_Y + 4][RW];  // density, tile + 2-node ring
-    __shared__ CT ms[TILE_Y + 2][MW];  // chemical potential, tile + 1-node ring
+    constexpr int NT = TILE_X * TY / ROWS_PER_THREAD;  // threads
+    constexpr int RS = TY / ROWS_PER_THREAD;           // row stride between a thread's nodes
+    auto& rs = L.rs;
+    auto& ms = L.ms;
 
     Planes<ST> F;
 #pragma unroll
     for (int i = 0; i < 9; ++i) F.p[i] = fin + (long long)i * A.plane;
 
-    const int t = tile_of_block(blockIdx.x, gridDim.x);
-    const int x0 = (t % A.tiles_x) * TILE_X, y0 = (t / A.tiles_x) * TILE_Y;
     const int lx = threadIdx.x % TILE_X, ly = threadIdx.x / TILE_X;
-    const bool small_x = A.nx < TILE_X + 2, small_y = A.ny < TILE_Y + 2;
+    const bool small_x = A.nx < TILE_X + 2, small_y = A.ny < TY + 2;
 
     // 1. own nodes: pull, keep f, density into LDS
     CT f[ROWS_PER_THREAD][9];
@@ -259,7 +272,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void step_kernel(LatticeArgs A, cons
     const int gxw = wrap_fast(gx_raw, A.nx, small_x);
 #pragma unroll
     for (int k = 0; k < ROWS_PER_THREAD; ++k) {
-        const int gy = y0 + ly + k * (TILE_Y / ROWS_PER_THREAD);
+        const int gy = y0 + ly + k * RS;
         const bool own = gx_raw < A.nx && gy < A.ny && !solid_row(A, gy);
         CT r;
         if (own) {
@@ -270,25 +283,25 @@ __global__ __launch_bounds__(BLOCK_THREADS) void step_kernel(LatticeArgs A, cons
         } else {
             r = node_rho<ST, CT>(A, F, gxw, gy, small_y);
         }
-        rs[ly + k * (TILE_Y / ROWS_PER_THREAD) + 2][lx + 2] = r;
+        rs[ly + k * RS + 2][lx + 2] = r;
     }
 
     // 2. the two-node ring of densities around the tile
-    constexpr int RING = 2 * RW * 2 + 2 * TILE_Y * 2;
-    for (int q = threadIdx.x; q < RING; q += BLOCK_THREADS) {
+    constexpr int RING = 2 * RW * 2 + 2 * TY * 2;
+    for (int q = threadIdx.x; q < RING; q += NT) {
         int r, c;
         if (q < 2 * RW) {
             r = q / RW;
             c = q % RW;
         } else if (q < 4 * RW) {
-            r = TILE_Y + 2 + (q - 2 * RW) / RW;
+            r = TY + 2 + (q - 2 * RW) / RW;
             c = (q - 2 * RW) % RW;
-        } else if (q < 4 * RW + 2 * TILE_Y) {
+        } else if (q < 4 * RW + 2 * TY) {
             r = 2 + (q - 4 * RW) / 2;
             c = (q - 4 * RW) % 2;
         } else {
-            r = 2 + (q - 4 * RW - 2 * TILE_Y) / 2;
-            c = TILE_X + 2 + (q - 4 * RW - 2 * TILE_Y) % 2;
+            r = 2 + (q - 4 * RW - 2 * TY) / 2;
+            c = TILE_X + 2 + (q - 4 * RW - 2 * TY) % 2;
         }
         rs[r][c] = node_rho<ST, CT>(A, F, wrap_fast(x0 - 2 + c, A.nx, small_x), y0 - 2 + r, small_y);
     }
@@ -296,7 +309,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void step_kernel(LatticeArgs A, cons
 
     // 3. chemical potential, Eq 8, on the tile and a one-node ring
     const CT kappa = CT(A.kappa);
-    for (int q = threadIdx.x; q < (TILE_Y + 2) * MW; q += BLOCK_THREADS) {
+    for (int q = threadIdx.x; q < (TY + 2) * MW; q += NT) {
         const int r = q / MW, c = q % MW;
         const int y = y0 - 1 + r;
         CT m;
@@ -327,7 +340,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void step_kernel(LatticeArgs A, cons
              b2 = CT(A.rho_ref) * Wt<CT>::w2;
 #pragma unroll
     for (int k = 0; k < ROWS_PER_THREAD; ++k) {
-        const int ry = ly + k * (TILE_Y / ROWS_PER_THREAD);
+        const int ry = ly + k * RS;
         const int gy = y0 + ry;
         if (gx_raw >= A.nx || gy >= A.ny) continue;
         const bool solid = solid_row(A, gy);
@@ -389,9 +402,54 @@ __global__ __launch_bounds__(BLOCK_THREADS) void step_kernel(LatticeArgs A, cons
     }
 }
 
+// One lattice: one workgroup per tile.
+template <typename ST, int EOS, int MODE, int TY>
+__global__ __launch_bounds__(TILE_X * TY / ROWS_PER_THREAD) void step_kernel(
+    LatticeArgs A, const ST* __restrict__ fin, ST* __restrict__ fout,
+    const typename Codec<ST>::CT* __restrict__ mu_w, double* __restrict__ out) {
+    __shared__ TileLds<typename Codec<ST>::CT, TY> L;
+    const int t = tile_of_block(blockIdx.x, gridDim.x);
+    const int tiles_x = (A.nx + TILE_X - 1) / TILE_X;
+    step_tile<ST, EOS, MODE, TY>(A, fin, fout, mu_w, out, (t % tiles_x) * TILE_X, (t / tiles_x) * TY, L);
+}
+
+// Many lattices in one persistent launch: each workgroup walks a contiguous range
+// of the (case, tile) list; the ranges of the workgroups on one XCD are adjacent.
+template <typename ST, int TY>
+__global__ __launch_bounds__(TILE_X * TY / ROWS_PER_THREAD) void batch_step_kernel(
+    const CaseDesc* __restrict__ cases, const int2* __restrict__ tiles, int ntiles, int parity) {
+    using CT = typename Codec<ST>::CT;
+    __shared__ TileLds<CT, TY> L;
+    const int chunk = tile_of_block(blockIdx.x, gridDim.x);
+    const int begin = int((long long)ntiles * chunk / gridDim.x);
+    const int end = int((long long)ntiles * (chunk + 1) / gridDim.x);
+    for (int t = begin; t < end; ++t) {
+        const int2 w = tiles[t];
+        const CaseDesc& C = cases[w.x];
+        const int tiles_x = (C.A.nx + TILE_X - 1) / TILE_X;
+        const int x0 = (w.y % tiles_x) * TILE_X, y0 = (w.y / tiles_x) * TY;
+        const ST* fin = static_cast<const ST*>(C.f[parity]);
+        ST* fout = static_cast<ST*>(C.f[parity ^ 1]);
+        const CT* mw = static_cast<const CT*>(C.mu_w);
+        switch (C.eos) {
+        case EOS_VDW: step_tile<ST, EOS_VDW, MODE_STEP, TY>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
+        case EOS_CS: step_tile<ST, EOS_CS, MODE_STEP, TY>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
+        case EOS_PR: step_tile<ST, EOS_PR, MODE_STEP, TY>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
+        default: step_tile<ST, EOS_RK, MODE_STEP, TY>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
+        }
+        __syncthreads();  // the next tile reuses the LDS
+    }
+}
+
 // ---------------------------------------------------------------- monitors
 constexpr int MON_THREADS = 256;
 constexpr int MON_BLOCKS_MAX = 1024;
+
+int mon_blocks(const LatticeArgs& A) {
+    const long long n = (long long)A.nx * A.ny;
+    const long long nb = (n + MON_THREADS - 1) / MON_THREADS;
+    return int(nb < MON_BLOCKS_MAX ? (nb < 1 ? 1 : nb) : MON_BLOCKS_MAX);
+}
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -489,6 +547,92 @@ __global__ __launch_bounds__(64) void monitor_reduce(const double* __restrict__ 
     }
 }
 
+// Monitors of many lattices: one workgroup per (case, tile); per-tile partials, then
+// one workgroup per case reduces its contiguous tile range in a fixed order.
+template <typename ST, int COMPARE, int TY>
+__global__ __launch_bounds__(MON_THREADS) void batch_monitor_kernel(const CaseDesc* __restrict__ cases,
+                                                                    const int2* __restrict__ tiles, int parity,
+                                                                    double* __restrict__ partials) {
+    using CT = typename Codec<ST>::CT;
+    const int2 w = tiles[blockIdx.x];
+    const CaseDesc& C = cases[w.x];
+    const LatticeArgs& A = C.A;
+    Planes<ST> F;
+    const ST* fin = static_cast<const ST*>(C.f[parity]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) F.p[i] = fin + (long long)i * A.plane;
+    CT* rho_mon = static_cast<CT*>(C.rho_mon);
+    const int tiles_x = (A.nx + TILE_X - 1) / TILE_X;
+    const int x0 = (w.y % tiles_x) * TILE_X, y0 = (w.y / tiles_x) * TY;
+    double mass = 0.0, res = 0.0;
+    int flags = 0;
+    for (int i = threadIdx.x; i < TILE_X * TY; i += MON_THREADS) {
+        const int x = x0 + i % TILE_X, y = y0 + i / TILE_X;
+        if (x >= A.nx || y >= A.ny || solid_row(A, y)) continue;
+        const CT r = fluid_rho<ST, CT>(A, F, x, y);
+        const unsigned o = unsigned(y) * unsigned(A.pitch) + unsigned(x);
+        if (COMPARE) {
+            const double rd = double(r);
+            mass += rd;
+            const double d = fabs(rd - double(rho_mon[o]));
+            res = d > res ? d : res;
+            if (!(rd == rd) || isinf(rd)) flags |= 1;
+            else if (rd <= 0.0) flags |= 2;
+            else if (rd >= A.eos.rho_max) flags |= 4;
+            if (!(d == d)) res = d;
+        }
+        rho_mon[o] = r;
+    }
+    if (!COMPARE) return;
+    __shared__ double s_mass[MON_THREADS / 64], s_res[MON_THREADS / 64];
+    __shared__ int s_flags[MON_THREADS / 64];
+    mass = wave_sum(mass);
+    res = wave_max(res);
+    flags = wave_or(flags);
+    const int wv = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        s_mass[wv] = mass;
+        s_res[wv] = res;
+        s_flags[wv] = flags;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0, rr = 0.0;
+        int fl = 0;
+        for (int i = 0; i < MON_THREADS / 64; ++i) {
+            m += s_mass[i];
+            rr = fmax(rr, s_res[i]);
+            fl |= s_flags[i];
+        }
+        partials[3 * blockIdx.x] = m;
+        partials[3 * blockIdx.x + 1] = rr;
+        partials[3 * blockIdx.x + 2] = double(fl);
+    }
+}
+
+__global__ __launch_bounds__(64) void batch_monitor_reduce(const double* __restrict__ partials,
+                                                           const int* __restrict__ case_tile_begin,
+                                                           double* __restrict__ case_mon) {
+    const int c = blockIdx.x;
+    const int b0 = case_tile_begin[c], b1 = case_tile_begin[c + 1];
+    if (b0 == b1) return;  // inactive case: keep its last values
+    double m = 0.0, r = 0.0;
+    int fl = 0;
+    for (int b = b0 + int(threadIdx.x); b < b1; b += 64) {
+        m += partials[3 * b];
+        r = fmax(r, partials[3 * b + 1]);
+        fl |= int(partials[3 * b + 2]);
+    }
+    m = wave_sum(m);
+    r = wave_max(r);
+    fl = wave_or(fl);
+    if (threadIdx.x == 0) {
+        case_mon[3 * c] = m;
+        case_mon[3 * c + 1] = r;
+        case_mon[3 * c + 2] = double(fl);
+    }
+}
+
 // ---------------------------------------------------------------- state conversion
 __device__ __forceinline__ double feq_d(int i, double rho, double ux, double uy) {
     constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -557,33 +701,46 @@ __global__ void get_state_kernel(LatticeArgs A, const ST* __restrict__ fstore, d
     for (int i = 0; i < 9; ++i) f_out[(long long)i * n + c] = double(f[i]);
 }
 
-template <typename ST>
-struct PrecOf;
-
-template <typename ST, int EOS>
-hipError_t step_eos(int mode, const LatticeArgs& A, const void* fin, void* fout, const void* mu_w,
-                    double* out, hipStream_t s) {
+template <typename ST, int EOS, int MODE>
+hipError_t step_ty(int tile_y, const LatticeArgs& A, const void* fin, void* fout, const void* mu_w, double* out,
+                   hipStream_t s) {
     using CT = typename Codec<ST>::CT;
-    const dim3 grid(A.tiles_x * A.tiles_y), block(BLOCK_THREADS);
+    const int tiles = ((A.nx + TILE_X - 1) / TILE_X) * ((A.ny + tile_y - 1) / tile_y);
     (void)hipGetLastError();  // drop any error left by earlier runtime calls
-    if (mode == MODE_STEP)
-        hipLaunchKernelGGL((step_kernel<ST, EOS, MODE_STEP>), grid, block, 0, s, A, (const ST*)fin, (ST*)fout,
-                           (const CT*)mu_w, out);
-    else
-        hipLaunchKernelGGL((step_kernel<ST, EOS, MODE_FIELDS>), grid, block, 0, s, A, (const ST*)fin,
-                           (ST*)fout, (const CT*)mu_w, out);
+    switch (tile_y) {
+    case 8:
+        hipLaunchKernelGGL((step_kernel<ST, EOS, MODE, 8>), dim3(tiles), dim3(TILE_X * 8 / ROWS_PER_THREAD), 0, s, A,
+                           (const ST*)fin, (ST*)fout, (const CT*)mu_w, out);
+        break;
+    case 16:
+        hipLaunchKernelGGL((step_kernel<ST, EOS, MODE, 16>), dim3(tiles), dim3(TILE_X * 16 / ROWS_PER_THREAD), 0, s,
+                           A, (const ST*)fin, (ST*)fout, (const CT*)mu_w, out);
+        break;
+    case 32:
+        hipLaunchKernelGGL((step_kernel<ST, EOS, MODE, 32>), dim3(tiles), dim3(TILE_X * 32 / ROWS_PER_THREAD), 0, s,
+                           A, (const ST*)fin, (ST*)fout, (const CT*)mu_w, out);
+        break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
+template <typename ST, int EOS>
+hipError_t step_eos(int mode, int tile_y, const LatticeArgs& A, const void* fin, void* fout, const void* mu_w,
+                    double* out, hipStream_t s) {
+    if (mode == MODE_STEP) return step_ty<ST, EOS, MODE_STEP>(tile_y, A, fin, fout, mu_w, out, s);
+    return step_ty<ST, EOS, MODE_FIELDS>(16, A, fin, fout, mu_w, out, s);  // output uses one shape
+}
+
 template <typename ST>
-hipError_t step_prec(int eos, int mode, const LatticeArgs& A, const void* fin, void* fout, const void* mu_w,
-                     double* out, hipStream_t s) {
+hipError_t step_prec(int eos, int mode, int tile_y, const LatticeArgs& A, const void* fin, void* fout,
+                     const void* mu_w, double* out, hipStream_t s) {
     switch (eos) {
-    case EOS_VDW: return step_eos<ST, EOS_VDW>(mode, A, fin, fout, mu_w, out, s);
-    case EOS_CS: return step_eos<ST, EOS_CS>(mode, A, fin, fout, mu_w, out, s);
-    case EOS_PR: return step_eos<ST, EOS_PR>(mode, A, fin, fout, mu_w, out, s);
+    case EOS_VDW: return step_eos<ST, EOS_VDW>(mode, tile_y, A, fin, fout, mu_w, out, s);
+    case EOS_CS: return step_eos<ST, EOS_CS>(mode, tile_y, A, fin, fout, mu_w, out, s);
+    case EOS_PR: return step_eos<ST, EOS_PR>(mode, tile_y, A, fin, fout, mu_w, out, s);
     case EOS_RKS:
-    case EOS_RK: return step_eos<ST, EOS_RK>(mode, A, fin, fout, mu_w, out, s);
+    case EOS_RK: return step_eos<ST, EOS_RK>(mode, tile_y, A, fin, fout, mu_w, out, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -592,7 +749,7 @@ template <typename ST>
 hipError_t monitor_prec(int compare, const LatticeArgs& A, const void* fin, void* rho_mon, double* partials,
                         double* mon, hipStream_t s) {
     using CT = typename Codec<ST>::CT;
-    const int nb = monitor_blocks(A);
+    const int nb = mon_blocks(A);
     (void)hipGetLastError();
     if (compare) {
         hipLaunchKernelGGL((monitor_kernel<ST, 1>), dim3(nb), dim3(MON_THREADS), 0, s, A, (const ST*)fin,
@@ -607,44 +764,74 @@ hipError_t monitor_prec(int compare, const LatticeArgs& A, const void* fin, void
     return hipGetLastError();
 }
 
-}  // namespace
-
-int monitor_blocks(const LatticeArgs& A) {
-    const long long n = (long long)A.nx * A.ny;
-    long long nb = (n + MON_THREADS - 1) / MON_THREADS;
-    return int(nb < MON_BLOCKS_MAX ? (nb < 1 ? 1 : nb) : MON_BLOCKS_MAX);
-}
-
-size_t storage_bytes(int prec) {
-    return prec == PREC_F64 ? 8 : (prec == PREC_F32 ? 4 : 2);
-}
-size_t compute_bytes(int prec) { return prec == PREC_F64 ? 8 : 4; }
-
-hipError_t launch_step(int prec, int eos, int mode, const LatticeArgs& A, const void* fin, void* fout,
-                       const void* mu_w, double* out, hipStream_t s) {
-    switch (prec) {
-    case PREC_F64: return step_prec<double>(eos, mode, A, fin, fout, mu_w, out, s);
-    case PREC_F32: return step_prec<float>(eos, mode, A, fin, fout, mu_w, out, s);
-    case PREC_F16DEV: return step_prec<__half>(eos, mode, A, fin, fout, mu_w, out, s);
-    case PREC_BF16DEV: return step_prec<__hip_bfloat16>(eos, mode, A, fin, fout, mu_w, out, s);
+template <typename ST>
+hipError_t batch_step_prec(int tile_y, const CaseDesc* cases, const int2* tiles, int ntiles, int parity, int grid,
+                           hipStream_t s) {
+    (void)hipGetLastError();
+    switch (tile_y) {
+    case 8:
+        hipLaunchKernelGGL((batch_step_kernel<ST, 8>), dim3(grid), dim3(TILE_X * 8 / ROWS_PER_THREAD), 0, s, cases,
+                           tiles, ntiles, parity);
+        break;
+    case 16:
+        hipLaunchKernelGGL((batch_step_kernel<ST, 16>), dim3(grid), dim3(TILE_X * 16 / ROWS_PER_THREAD), 0, s,
+                           cases, tiles, ntiles, parity);
+        break;
+    case 32:
+        hipLaunchKernelGGL((batch_step_kernel<ST, 32>), dim3(grid), dim3(TILE_X * 32 / ROWS_PER_THREAD), 0, s,
+                           cases, tiles, ntiles, parity);
+        break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
 }
 
-hipError_t launch_monitor(int prec, int eos, int compare, const LatticeArgs& A, const void* fin, void* rho_mon,
-                          double* partials, double* mon, hipStream_t s) {
-    (void)eos;
-    switch (prec) {
-    case PREC_F64: return monitor_prec<double>(compare, A, fin, rho_mon, partials, mon, s);
-    case PREC_F32: return monitor_prec<float>(compare, A, fin, rho_mon, partials, mon, s);
-    case PREC_F16DEV: return monitor_prec<__half>(compare, A, fin, rho_mon, partials, mon, s);
-    case PREC_BF16DEV: return monitor_prec<__hip_bfloat16>(compare, A, fin, rho_mon, partials, mon, s);
+template <typename ST, int COMPARE>
+hipError_t batch_monitor_ty(int tile_y, const CaseDesc* cases, const int2* tiles, int ntiles, int parity,
+                            double* partials, hipStream_t s) {
+    switch (tile_y) {
+    case 8:
+        hipLaunchKernelGGL((batch_monitor_kernel<ST, COMPARE, 8>), dim3(ntiles), dim3(MON_THREADS), 0, s, cases,
+                           tiles, parity, partials);
+        break;
+    case 16:
+        hipLaunchKernelGGL((batch_monitor_kernel<ST, COMPARE, 16>), dim3(ntiles), dim3(MON_THREADS), 0, s, cases,
+                           tiles, parity, partials);
+        break;
+    case 32:
+        hipLaunchKernelGGL((batch_monitor_kernel<ST, COMPARE, 32>), dim3(ntiles), dim3(MON_THREADS), 0, s, cases,
+                           tiles, parity, partials);
+        break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
 }
 
 template <typename ST>
-static hipError_t init_prec(const LatticeArgs& A, const double* rho0, const double* ux0, const double* uy0,
+hipError_t batch_monitor_prec(int compare, int tile_y, const CaseDesc* cases, const int2* tiles, int ntiles,
+                              int parity, double* partials, const int* case_tile_begin, int ncases,
+                              double* case_mon, hipStream_t s) {
+    (void)hipGetLastError();
+    if (ntiles == 0) return hipSuccess;
+    hipError_t e = compare ? batch_monitor_ty<ST, 1>(tile_y, cases, tiles, ntiles, parity, partials, s)
+                           : batch_monitor_ty<ST, 0>(tile_y, cases, tiles, ntiles, parity, partials, s);
+    if (e != hipSuccess || !compare) return e;
+    hipLaunchKernelGGL(batch_monitor_reduce, dim3(ncases), dim3(64), 0, s, partials, case_tile_begin, case_mon);
+    return hipGetLastError();
+}
+
+template <typename ST>
+int batch_occupancy(int tile_y) {
+    int n = 0;
+    const int threads = TILE_X * tile_y / ROWS_PER_THREAD;
+    const void* k = tile_y == 8 ? (const void*)batch_step_kernel<ST, 8>
+                  : (tile_y == 16 ? (const void*)batch_step_kernel<ST, 16> : (const void*)batch_step_kernel<ST, 32>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, 0) != hipSuccess || n < 1) n = 1;
+    return n;
+}
+
+template <typename ST>
+hipError_t init_prec(const LatticeArgs& A, const double* rho0, const double* ux0, const double* uy0,
                             const double* f_in, void* fstore, hipStream_t s) {
     const long long n = (long long)A.nx * A.ny;
     const int blocks = int((n + 255) / 256);
@@ -653,19 +840,8 @@ static hipError_t init_prec(const LatticeArgs& A, const double* rho0, const doub
     return hipGetLastError();
 }
 
-hipError_t launch_init(int prec, const LatticeArgs& A, const double* rho0, const double* ux0, const double* uy0,
-                       const double* f_in, void* fstore, hipStream_t s) {
-    switch (prec) {
-    case PREC_F64: return init_prec<double>(A, rho0, ux0, uy0, f_in, fstore, s);
-    case PREC_F32: return init_prec<float>(A, rho0, ux0, uy0, f_in, fstore, s);
-    case PREC_F16DEV: return init_prec<__half>(A, rho0, ux0, uy0, f_in, fstore, s);
-    case PREC_BF16DEV: return init_prec<__hip_bfloat16>(A, rho0, ux0, uy0, f_in, fstore, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
 template <typename ST>
-static hipError_t get_state_prec(const LatticeArgs& A, const void* fstore, double* f_out, hipStream_t s) {
+hipError_t get_state_prec(const LatticeArgs& A, const void* fstore, double* f_out, hipStream_t s) {
     const long long n = (long long)A.nx * A.ny;
     const int blocks = int((n + 255) / 256);
     (void)hipGetLastError();
@@ -673,14 +849,46 @@ static hipError_t get_state_prec(const LatticeArgs& A, const void* fstore, doubl
     return hipGetLastError();
 }
 
-hipError_t launch_get_state(int prec, const LatticeArgs& A, const void* fstore, double* f_out, hipStream_t s) {
-    switch (prec) {
-    case PREC_F64: return get_state_prec<double>(A, fstore, f_out, s);
-    case PREC_F32: return get_state_prec<float>(A, fstore, f_out, s);
-    case PREC_F16DEV: return get_state_prec<__half>(A, fstore, f_out, s);
-    case PREC_BF16DEV: return get_state_prec<__hip_bfloat16>(A, fstore, f_out, s);
-    default: return hipErrorInvalidValue;
-    }
+}  // namespace
+
+// Entry points of this translation unit, for one storage type (CPLBM_ST); the
+// dispatch over storage types is in lbm_dispatch.cpp.
+#define CPLBM_CAT2(a, b) a##_##b
+#define CPLBM_CAT(a, b) CPLBM_CAT2(a, b)
+#define CPLBM_FN(name) CPLBM_CAT(name, CPLBM_SUFFIX)
+
+hipError_t CPLBM_FN(launch_step)(int eos, int mode, const LatticeArgs& A, const void* fin, void* fout,
+                                 const void* mu_w, double* out, hipStream_t s) {
+    return step_prec<CPLBM_ST>(eos, mode, A.tile_y, A, fin, fout, mu_w, out, s);
+}
+
+hipError_t CPLBM_FN(launch_monitor)(int compare, const LatticeArgs& A, const void* fin, void* rho_mon,
+                                    double* partials, double* mon, hipStream_t s) {
+    return monitor_prec<CPLBM_ST>(compare, A, fin, rho_mon, partials, mon, s);
+}
+
+hipError_t CPLBM_FN(launch_batch_step)(int tile_y, const CaseDesc* cases, const int2* tiles, int ntiles,
+                                       int parity, int grid, hipStream_t s) {
+    if (ntiles == 0) return hipSuccess;
+    return batch_step_prec<CPLBM_ST>(tile_y, cases, tiles, ntiles, parity, grid, s);
+}
+
+hipError_t CPLBM_FN(launch_batch_monitor)(int compare, int tile_y, const CaseDesc* cases, const int2* tiles,
+                                          int ntiles, int parity, double* partials, const int* case_tile_begin,
+                                          int ncases, double* case_mon, hipStream_t s) {
+    return batch_monitor_prec<CPLBM_ST>(compare, tile_y, cases, tiles, ntiles, parity, partials, case_tile_begin,
+                                        ncases, case_mon, s);
+}
+
+int CPLBM_FN(batch_blocks_per_cu)(int tile_y) { return batch_occupancy<CPLBM_ST>(tile_y); }
+
+hipError_t CPLBM_FN(launch_init)(const LatticeArgs& A, const double* rho0, const double* ux0, const double* uy0,
+                                 const double* f_in, void* fstore, hipStream_t s) {
+    return init_prec<CPLBM_ST>(A, rho0, ux0, uy0, f_in, fstore, s);
+}
+
+hipError_t CPLBM_FN(launch_get_state)(const LatticeArgs& A, const void* fstore, double* f_out, hipStream_t s) {
+    return get_state_prec<CPLBM_ST>(A, fstore, f_out, s);
 }
 
 }  // namespace cplbm

@@ -31,7 +31,10 @@ LBM_F64, LBM_F32, LBM_F16DEV, LBM_BF16DEV = 0, 1, 2, 3
 LBM_BC_PERIODIC, LBM_BC_CPWALL, LBM_BC_NEUTRAL = 0, 1, 2
 
 EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lbm_get_fields",
-            "lbm_set_wall_mu",
+            "lbm_set_wall_mu", "lbm_tune", "lbm_set_tile",
+            "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_step_timed",
+            "lbm_batch_run", "lbm_batch_status", "lbm_batch_get_fields", "lbm_batch_get_state",
+            "lbm_batch_tune", "lbm_batch_fluid_nodes", "lbm_batch_destroy", "lbm_copy_bandwidth",
             "lbm_get_monitors", "lbm_monitor_step", "lbm_get_state", "lbm_set_state",
             "lbm_get_temperature", "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_critical_point",
             "lbm_coexistence", "lbm_eos_eval", "lbm_contact_angle"]
@@ -104,13 +107,31 @@ def load_library():
     lib.lbm_strerror.restype = C.c_char_p
     lib.lbm_last_error.argtypes = []
     lib.lbm_last_error.restype = C.c_char_p
+    lib.lbm_tune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), dp]
+    lib.lbm_set_tile.argtypes = [vp, C.c_int32]
+    lib.lbm_batch_workspace_bytes.argtypes = [P, C.c_int32]
+    lib.lbm_batch_workspace_bytes.restype = C.c_size_t
+    lib.lbm_batch_init.argtypes = [P, C.c_int32, vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.lbm_batch_step.argtypes = [vp, C.c_int64]
+    lib.lbm_batch_step_timed.argtypes = [vp, C.c_int64, dp]
+    lib.lbm_batch_run.argtypes = [vp, C.c_int64, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.c_int64)]
+    lib.lbm_batch_status.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.lbm_batch_get_fields.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
+    lib.lbm_batch_get_state.argtypes = [vp, C.c_int32, vp]
+    lib.lbm_batch_tune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp]
+    lib.lbm_batch_fluid_nodes.argtypes = [vp, C.c_int32]
+    lib.lbm_batch_fluid_nodes.restype = C.c_int64
+    lib.lbm_batch_destroy.argtypes = [vp]
+    lib.lbm_batch_destroy.restype = None
+    lib.lbm_copy_bandwidth.argtypes = [C.c_size_t, C.c_int32, dp]
     lib.lbm_critical_point.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, dp, dp, dp]
     lib.lbm_coexistence.argtypes = [P, dp, dp, dp, dp]
     lib.lbm_eos_eval.argtypes = [P, C.c_int64, vp, vp, vp]
     lib.lbm_contact_angle.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                       dp, dp, dp]
     for name in EXPORTED:
-        if name not in ("lbm_workspace_bytes", "lbm_destroy", "lbm_strerror", "lbm_last_error"):
+        if name not in ("lbm_workspace_bytes", "lbm_destroy", "lbm_strerror", "lbm_last_error",
+                        "lbm_batch_workspace_bytes", "lbm_batch_fluid_nodes", "lbm_batch_destroy"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -175,6 +196,13 @@ def lbm_contact_angle(rho, rho_mid: float, base_row: int = 1, surface_y=None):
     return tuple(o.value for o in out)
 
 
+def lbm_copy_bandwidth(nbytes: int, iters: int = 20) -> float:
+    """GB/s of a plain device copy (read + write bytes over time)."""
+    g = C.c_double()
+    _check(load_library().lbm_copy_bandwidth(int(nbytes), int(iters), C.byref(g)), "lbm_copy_bandwidth")
+    return g.value
+
+
 def lbm_workspace_bytes(p: LbmParams) -> int:
     return int(load_library().lbm_workspace_bytes(C.byref(p)))
 
@@ -233,6 +261,15 @@ class Lattice:
         _check(self.lib.lbm_step_timed(self.ctx, int(n), C.byref(ms)), "lbm_step_timed")
         return ms.value
 
+    def tune(self, trial_steps: int = 50):
+        """Picks the fastest tile height for this lattice; returns (tile_y, ms per step)."""
+        ty, ms = C.c_int32(), C.c_double()
+        _check(self.lib.lbm_tune(self.ctx, int(trial_steps), C.byref(ty), C.byref(ms)), "lbm_tune")
+        return ty.value, ms.value
+
+    def set_tile(self, tile_y: int):
+        _check(self.lib.lbm_set_tile(self.ctx, int(tile_y)), "lbm_set_tile")
+
     def monitor_step(self):
         _check(self.lib.lbm_monitor_step(self.ctx), "lbm_monitor_step")
         return self.monitors()
@@ -276,6 +313,90 @@ class Lattice:
             self.lib.lbm_destroy(self.ctx)
             self.ctx = C.c_void_p()
         self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- batches
+def lbm_batch_workspace_bytes(cases) -> int:
+    arr = (LbmParams * len(cases))(*cases)
+    return int(load_library().lbm_batch_workspace_bytes(arr, len(cases)))
+
+
+class Batch:
+    """Many lattices advanced by one persistent launch per step (``lbm_batch``)."""
+
+    ACTIVE, CONVERGED, DIVERGED = 0, 1, 2
+
+    def __init__(self, cases, rho0s, mu_w_bottom=None):
+        self.lib = load_library()
+        self.n = len(cases)
+        self.cases = list(cases)
+        self._arr = (LbmParams * self.n)(*cases)
+        self._rho = [_f64(r) for r in rho0s]
+        for p, r in zip(self.cases, self._rho):
+            if r.shape != (p.ny, p.nx):
+                raise ValueError("rho0 shape %s, expected %s" % (r.shape, (p.ny, p.nx)))
+        ptrs = (C.c_void_p * self.n)(*[r.ctypes.data for r in self._rho])
+        mw = None if mu_w_bottom is None else _f64(np.asarray(mu_w_bottom, dtype=np.float64).ravel())
+        ctx = C.c_void_p()
+        _check(self.lib.lbm_batch_init(self._arr, self.n, ptrs, _p(mw), None, 0, None, C.byref(ctx)),
+               "lbm_batch_init")
+        self.ctx = ctx
+
+    def step(self, n: int):
+        _check(self.lib.lbm_batch_step(self.ctx, int(n)), "lbm_batch_step")
+
+    def step_timed(self, n: int) -> float:
+        ms = C.c_double()
+        _check(self.lib.lbm_batch_step_timed(self.ctx, int(n), C.byref(ms)), "lbm_batch_step_timed")
+        return ms.value
+
+    def run(self, max_steps: int, check_every: int = 100, window: int = 1, tol: float = 1e-9) -> int:
+        s = C.c_int64()
+        _check(self.lib.lbm_batch_run(self.ctx, int(max_steps), int(check_every), int(window), float(tol),
+                                      C.byref(s)), "lbm_batch_run")
+        return s.value
+
+    def status(self):
+        st = np.zeros(self.n, np.int32)
+        steps = np.zeros(self.n, np.int64)
+        res, mass = np.zeros(self.n), np.zeros(self.n)
+        fl = np.zeros(self.n, np.int32)
+        _check(self.lib.lbm_batch_status(self.ctx, _p(st), _p(steps), _p(res), _p(mass), _p(fl)),
+               "lbm_batch_status")
+        return {"state": st, "steps": steps, "residual": res, "mass": mass, "flags": fl}
+
+    def fields(self, i: int):
+        p = self.cases[i]
+        out = {k: np.empty((p.ny, p.nx)) for k in ("rho", "vx", "vy", "mu")}
+        _check(self.lib.lbm_batch_get_fields(self.ctx, int(i), *[_p(out[k]) for k in ("rho", "vx", "vy", "mu")]),
+               "lbm_batch_get_fields")
+        return out
+
+    def get_state(self, i: int):
+        p = self.cases[i]
+        f = np.empty((9, p.ny, p.nx))
+        _check(self.lib.lbm_batch_get_state(self.ctx, int(i), _p(f)), "lbm_batch_get_state")
+        return f
+
+    def tune(self, trial_steps: int = 20):
+        ty, bpc, ms = C.c_int32(), C.c_int32(), C.c_double()
+        _check(self.lib.lbm_batch_tune(self.ctx, int(trial_steps), C.byref(ty), C.byref(bpc), C.byref(ms)),
+               "lbm_batch_tune")
+        return ty.value, bpc.value, ms.value
+
+    def fluid_nodes(self, active_only: bool = False) -> int:
+        return int(self.lib.lbm_batch_fluid_nodes(self.ctx, 1 if active_only else 0))
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self.lib.lbm_batch_destroy(self.ctx)
+            self.ctx = C.c_void_p()
 
     def __del__(self):
         try:
