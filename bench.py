@@ -110,15 +110,17 @@ def measure_batch(lbm, inputs, steps):
 
 
 def traffic_for(workload: str, bytes_per_launch: float):
-    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE counts,
-    if they were taken on the current kernel source."""
+    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE counts, each
+    scaled by what the counter reads for a plain copy of known size, if they were
+    taken on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("kernel_sha") != kernel_sha():
         return None
-    return (d["fetch_kib_per_dispatch"] + d["write_kib_per_dispatch"]) * 1024.0 * d.get("copy_factor", 1.0)
+    return round((d["fetch_kib_per_dispatch"] * d["fetch_factor"] +
+                  d["write_kib_per_dispatch"] * d["write_factor"]) * 1024.0, 0)
 
 
 def _with_monitor(p, every):

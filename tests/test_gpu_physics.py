@@ -1,0 +1,132 @@
+"""GPU physics: reduced-precision statistics against the FP64 oracle, and the
+contact angle's dependence on the surface chemical potential (Sec. V).
+
+These compare statistics that survive the chaotic divergence of two runs
+(spinodal decomposition) or equilibrium quantities (contact angles), not nodes.
+"""
+import numpy as np
+import pytest
+
+from cases import C3_512, Case
+from oracle import thermo
+from oracle.contact import contact_angle
+from oracle.lattice import CPWALL, NEUTRAL
+
+pytestmark = pytest.mark.gpu
+
+lbm = pytest.importorskip("paper_1611_00907_amd.lbm")
+
+
+def bulk_densities(rho):
+    """Liquid and vapour bulk densities of a phase-separated field: medians of the
+    nodes whose whole 3x3 neighbourhood is on one side of the mid density."""
+    mid = 0.5 * (rho.max() + rho.min())
+    hi = rho > mid
+    nb_all_hi = np.ones_like(hi)
+    nb_all_lo = np.ones_like(hi)
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            s = np.roll(np.roll(hi, dy, 0), dx, 1)
+            nb_all_hi &= s
+            nb_all_lo &= ~s
+    return float(np.median(rho[nb_all_lo])), float(np.median(rho[nb_all_hi]))
+
+
+@pytest.fixture(scope="module")
+def spinodal_runs():
+    """512^2 VdW spinodal decomposition (Tr = 0.85, rho = rho_c (1 + 0.01 U)), 3000 steps,
+    in FP64 on the CPU oracle and in every GPU storage precision."""
+    steps = 3000
+    rho0 = C3_512.rho0()
+    ora = C3_512.oracle()
+    m0 = ora.mass()
+    ora.step(steps)
+    out = {"oracle": (ora.fields()["rho"], ora.mass() / m0 - 1)}
+    for name, prec in (("f64", lbm.LBM_F64), ("f32", lbm.LBM_F32), ("f16", lbm.LBM_F16DEV),
+                       ("bf16", lbm.LBM_BF16DEV)):
+        lat = lbm.Lattice(C3_512.lbm_params(prec, monitor_every=1000), rho0)
+        lat.step(steps)
+        mon = lat.monitors()
+        out[name] = (lat.fields()["rho"], mon["mass"] / m0 - 1)
+    return out
+
+
+def test_spinodal_fp64_gpu_statistics(spinodal_runs):
+    g, l = bulk_densities(spinodal_runs["oracle"][0])
+    g2, l2 = bulk_densities(spinodal_runs["f64"][0])
+    assert abs(g2 / g - 1) < 1e-6 and abs(l2 / l - 1) < 1e-6
+
+
+@pytest.mark.parametrize("name,tol", [("f32", 2e-3), ("f16", 1e-2), ("bf16", 5e-2)])
+def test_reduced_precision_coexistence(spinodal_runs, name, tol):
+    """Bulk densities of the phase-separated field in reduced precision against the
+    FP64 oracle, and against the Maxwell values (the discrete equilibrium sits a
+    few percent off, as for the planar interface)."""
+    g, l = bulk_densities(spinodal_runs["oracle"][0])
+    gp, lp = bulk_densities(spinodal_runs[name][0])
+    assert abs(gp / g - 1) < tol and abs(lp / l - 1) < tol, (name, gp, g, lp, l)
+    rg, rl, _, _ = thermo.maxwell(thermo.fluid_at(thermo.VDW, 9 / 49, 2 / 21, 1.0, 0.85))
+    assert abs(lp / rl - 1) < 0.03 and abs(gp / rg - 1) < 0.08
+
+
+@pytest.mark.parametrize("name,tol", [("oracle", 1e-12), ("f64", 1e-12), ("f32", 1e-5), ("f16", 1e-2),
+                                      ("bf16", 5e-2)])
+def test_mass_drift(spinodal_runs, name, tol):
+    assert abs(spinodal_runs[name][1]) < tol
+
+
+def _wetting_batch(eos, a, b, omega, Tr, nx, ny, R, mus, steps):
+    cases, rhos = [], []
+    for mu in mus:
+        p = lbm.make_params(nx, ny, eos, a, b, Tr, 1.3, 0.01, omega=omega, prec=lbm.LBM_F32,
+                            bc_bottom=lbm.LBM_BC_CPWALL, bc_top=lbm.LBM_BC_NEUTRAL)
+        rg, rl, _, _ = lbm.lbm_coexistence(p)
+        cases.append(p)
+        from paper_1611_00907_amd import inputs
+        rhos.append(inputs.sessile_drop(nx, ny, rl, rg, R))
+    bt = lbm.Batch(cases, rhos, mu_w_bottom=list(mus))
+    bt.step(steps)
+    thetas = []
+    for i in range(len(mus)):
+        rho = bt.fields(i)["rho"]
+        rg, rl = np.median(rho[-10:-2]), np.max(rho)
+        thetas.append(lbm.lbm_contact_angle(rho, 0.5 * (rg + rl), base_row=1)[0])
+    bt.close()
+    return np.array(thetas)
+
+
+def test_contact_angle_monotone_near_linear_pr():
+    """Sec. V, Fig. 3: the contact angle grows smoothly and almost linearly with the
+    surface chemical potential (PR water, Tr = 0.8, tau = 1.3, kappa = 0.01)."""
+    p = lbm.make_params(8, 8, lbm.LBM_EOS_PR, 2 / 49, 2 / 21, 0.8, 1.3, 0.01, omega=0.344)
+    mu_sat = lbm.lbm_coexistence(p)[3]
+    mus = mu_sat + np.linspace(-0.15, 0.15, 7)
+    th = _wetting_batch(lbm.LBM_EOS_PR, 2 / 49, 2 / 21, 0.344, 0.8, 320, 160, 48, mus, 30000)
+    assert np.all(np.diff(th) > 0), th
+    sel = (th > 30) & (th < 150)
+    assert sel.sum() >= 4, th
+    A = np.vstack([mus[sel], np.ones(sel.sum())]).T
+    coef, res, _, _ = np.linalg.lstsq(A, th[sel], rcond=None)
+    r2 = 1 - res[0] / ((th[sel] - th[sel].mean()) ** 2).sum()
+    assert r2 > 0.98, (th, r2)
+
+
+def test_fig2_rks_contact_angles():
+    """The paper's only printed numbers (Fig. 2 caption, tests/golden/fig2_rks.json):
+    RKS, 500 x 200, Tr = 0.8, drop radius 50, tau = 1.3, kappa = 0.01.  The printed
+    angles are multiples of 5 degrees (so +-2.5 degrees of rounding) and the angle
+    tool is pinned to 0.5 degrees on synthetic caps: the four wetting-to-moderately
+    hydrophobic pairs must agree within 3 degrees.  Near detachment (CP 0.15, 0.18:
+    160 and 180 degrees) the cap is a sliver on a 1-node base, so only
+    theta >= 150 is required there."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fig2_rks.json")))
+    cps = np.array([p[0] for p in g["pairs_cp_theta_deg"]])
+    want = np.array([p[1] for p in g["pairs_cp_theta_deg"]], dtype=float)
+    th = _wetting_batch(lbm.LBM_EOS_RKS, g["a"], g["b"], 0.344, g["Tr"], g["nx"], g["ny"], g["drop_radius"],
+                        cps, 40000)
+    print("Fig. 2 reproduction:", dict(zip(cps.tolist(), np.round(th, 1).tolist())))
+    assert np.all(np.diff(th) >= 0), th
+    assert np.max(np.abs(th[:4] - want[:4])) < 3.0, th
+    assert np.all(th[4:] >= 150.0), th
