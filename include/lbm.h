@@ -213,6 +213,46 @@ int64_t lbm_batch_fluid_nodes(lbm_batch* b, int32_t active_only);
 
 void lbm_batch_destroy(lbm_batch* b);
 
+/* ---- learned warm start: convolutional surrogate ------------------------ */
+
+/* An encoder-decoder of 3x3 convolutions (4 levels of 32, 64, 96, 128 channels,
+ * two ReLU convolutions per level, 2x2 average pooling down, nearest-neighbour
+ * upsampling and skip concatenation up, one final 3x3 convolution to one
+ * channel) mapping 4 input channels (solid mask, initial density, T/Tc, wall
+ * chemical potential; the caller chooses their scaling) to one output channel
+ * (the equilibrium density, same scaling).  Weights and activations are BF16,
+ * products accumulate in FP32 on the matrix cores; the master weights, their
+ * gradients and the Adam moments are FP32.  Not part of the paper's method: a
+ * warm start for it (the lattice Boltzmann solver still relaxes the prediction).
+ *
+ * Parameter exchange layout (FP32, sur_param_count values): for each layer in the
+ * order e0a e0b e1a e1b e2a e2b e3a e3b d2a d2b d1a d1b d0a d0b out, the weights
+ * w[co][ci][3][3] then the bias b[co]; the first layer takes ci = 16 input
+ * channels (inputs 4..15 are zero), the last gives co = 1.  Images are FP32
+ * NCHW: inputs [n][4][size][size], outputs and targets [n][size][size]. */
+typedef struct sur_net sur_net;
+
+/* size: image side, a multiple of 8; max_batch: images per device pass.
+ * Allocates all device buffers; parameters start at zero (set them). */
+lbm_status sur_create(int32_t size, int32_t max_batch, sur_net** out);
+int64_t sur_param_count(const sur_net* n);
+/* Sets the FP32 master parameters (exchange layout), resets Adam. */
+lbm_status sur_set_params(sur_net* n, const float* params);
+lbm_status sur_get_params(sur_net* n, float* params);
+/* Prediction for count images (host buffers), in passes of max_batch. */
+lbm_status sur_forward(sur_net* n, const float* inputs, int32_t count, float* outputs);
+/* Mean-squared-error loss of count <= max_batch images against targets and the
+ * gradient of every parameter (exchange layout; grads may be NULL). */
+lbm_status sur_gradients(sur_net* n, const float* inputs, const float* targets, int32_t count,
+                         float* grads, double* loss);
+/* Copies a training set to the device (replacing any previous one). */
+lbm_status sur_set_dataset(sur_net* n, const float* inputs, const float* targets, int32_t count);
+/* steps Adam updates (lr; beta 0.9, 0.999; eps 1e-8) on minibatches of `batch`
+ * images drawn with replacement from the dataset by SplitMix64 from seed; losses
+ * (may be NULL) receives the loss of each step. */
+lbm_status sur_train(sur_net* n, int32_t steps, int32_t batch, float lr, uint64_t seed, float* losses);
+void sur_destroy(sur_net* n);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* Bandwidth of a plain device-to-device copy of `bytes` (a multiple of 16)

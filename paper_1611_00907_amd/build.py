@@ -22,8 +22,9 @@ OBJ = os.path.join(PKG, "_build")
 
 KERNEL_SOURCE = "lbm_kernels.hip"
 STORAGE = [("double", "f64"), ("float", "f32"), ("__half", "f16dev"), ("__hip_bfloat16", "bf16dev")]
-HOST_SOURCES = ["lbm_dispatch.cpp", "lbm_host.cpp", "lbm_batch.cpp", "thermo_host.cpp"]
-HEADERS = ["lbm_internal.h", "lbm_common.h", "thermo_host.h"]
+HOST_SOURCES = ["lbm_dispatch.cpp", "lbm_host.cpp", "lbm_batch.cpp", "thermo_host.cpp", "sur_kernels.hip",
+                "sur_host.cpp"]
+HEADERS = ["lbm_internal.h", "lbm_common.h", "thermo_host.h", "sur_internal.h"]
 SOURCES = [KERNEL_SOURCE] + HOST_SOURCES
 
 ARCH = "gfx950"
@@ -49,7 +50,7 @@ def compile_commands():
         cmds.append((out, [hipcc()] + FLAGS + ["-DCPLBM_ST=%s" % st, "-DCPLBM_SUFFIX=%s" % sfx, "-c",
                                                os.path.join(CSRC, KERNEL_SOURCE), "-o", out]))
     for src in HOST_SOURCES:
-        out = os.path.join(OBJ, src.replace(".cpp", ".o"))
+        out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
         cmds.append((out, [hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", out]))
     return cmds
 

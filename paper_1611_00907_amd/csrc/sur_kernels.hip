@@ -1,0 +1,468 @@
+// HIP kernels of the convolutional surrogate (encoder-decoder of 3x3 convolutions)
+// for CDNA4: BF16 activations and weights, FP32 accumulation on the matrix cores
+// (v_mfma_f32_16x16x32_bf16), FP32 master weights and Adam.
+//
+// Activations are NHWC with a channel stride and offset per tensor view, so a
+// convolution can read from or write into a slice of a concatenation buffer.
+// Weights are [9][Cout_p][Cin_p] (tap-major, input channels contiguous, both
+// padded with zeros: Cin_p to a multiple of 32, Cout_p to a multiple of 16).
+//
+// MFMA 16x16x32 operand layout: lane l supplies A[l % 16][8 (l / 16) + j] and
+// B[8 (l / 16) + j][l % 16], j = 0..7, and receives D[4 (l / 16) + i][l % 16],
+// i = 0..3.  A convolution is the GEMM out[pixel][co] = sum_k in_col[pixel][k] W[k][co]
+// with k = (tap, ci): A rows are pixels, B columns output channels.
+#include <hip/hip_runtime.h>
+
+#include "sur_internal.h"
+
+namespace cplbm {
+namespace sur {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+// float -> bfloat16 bits, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40);
+    return uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// ---------------------------------------------------------------- convolution
+// One wave computes WM x 16 pixels by WN x 16 output channels.
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int co_tiles = a.cout_p / (16 * WN);
+    const long long npx = (long long)a.N * a.H * a.W;
+    const int co_tile = wave % co_tiles;
+    const long long px0 = (long long)(wave / co_tiles) * (16 * WM);
+    if (px0 >= npx) return;
+
+    f32x4 acc[WM][WN];
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+        for (int n = 0; n < WN; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // the pixel each lane feeds into A rows of block m
+    int py[WM], pxx[WM];
+    long long pn[WM];
+    bool pvalid[WM];
+#pragma unroll
+    for (int m = 0; m < WM; ++m) {
+        const long long p = px0 + 16 * m + r;
+        pvalid[m] = p < npx;
+        const long long q = pvalid[m] ? p : 0;
+        pxx[m] = int(q % a.W);
+        const long long t = q / a.W;
+        py[m] = int(t % a.H);
+        pn[m] = t / a.H;
+    }
+    const int co_base = co_tile * 16 * WN;
+    for (int tap = 0; tap < 9; ++tap) {
+        const int du = tap / 3 - 1, dv = tap % 3 - 1;
+        long long src[WM];
+        bool sval[WM];
+#pragma unroll
+        for (int m = 0; m < WM; ++m) {
+            const int yy = py[m] + du, xx = pxx[m] + dv;
+            sval[m] = pvalid[m] && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+            src[m] = ((pn[m] * a.H + yy) * a.W + xx) * a.in.cs + a.in.co;
+        }
+        for (int ci0 = 0; ci0 < a.cin_p; ci0 += 32) {
+            const int ci = ci0 + 8 * g;
+            const bool cin_ok = ci < a.cin;
+            bf16x8 av[WM], bv[WN];
+#pragma unroll
+            for (int m = 0; m < WM; ++m) {
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (sval[m] && cin_ok) v = *reinterpret_cast<const uint4*>(a.in.p + src[m] + ci);
+                av[m] = as_bf16x8(v);
+            }
+#pragma unroll
+            for (int n = 0; n < WN; ++n) {
+                const int co = co_base + 16 * n + r;
+                const uint4 v = *reinterpret_cast<const uint4*>(a.w + ((size_t)(tap * a.cout_p + co) * a.cin_p + ci));
+                bv[n] = as_bf16x8(v);
+            }
+#pragma unroll
+            for (int m = 0; m < WM; ++m)
+#pragma unroll
+                for (int n = 0; n < WN; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv[n], acc[m][n], 0, 0, 0);
+        }
+    }
+
+    // epilogue: lane holds pixels px0 + 16 m + 4 g + i, channel co_base + 16 n + r
+#pragma unroll
+    for (int n = 0; n < WN; ++n) {
+        const int co = co_base + 16 * n + r;
+        if (co >= a.cout) continue;
+        const float b = (a.bias != nullptr) ? a.bias[co] : 0.0f;
+#pragma unroll
+        for (int m = 0; m < WM; ++m) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long long p = px0 + 16 * m + 4 * g + i;
+                if (p >= npx) continue;
+                float v = acc[m][n][i] + b;
+                switch (a.epi) {
+                case EPI_RELU_BF16:
+                    a.out.p[p * a.out.cs + a.out.co + co] = f2bf(v > 0.f ? v : 0.f);
+                    break;
+                case EPI_MASK_BF16: {
+                    const float mk = bf2f(a.mask.p[p * a.mask.cs + a.mask.co + co]);
+                    a.out.p[p * a.out.cs + a.out.co + co] = f2bf(mk > 0.f ? v : 0.f);
+                    break;
+                }
+                case EPI_BF16:
+                    a.out.p[p * a.out.cs + a.out.co + co] = f2bf(v);
+                    break;
+                default:  // EPI_F32
+                    a.out_f32[p * a.out_f32_cs + co] = v;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- weight gradient
+// dW[tap][co][ci] += sum_p dZ[p][co] X[p shifted by tap][ci]: GEMM with the pixels as
+// the reduction axis.  A = dZ^T (rows co), B = shifted X (columns ci); the operands
+// are gathered 8 pixels at a time.  Each wave owns one tap, a 16 x 16 (co, ci) tile
+// and a chunk of pixels, and adds its partial tile to dW atomically.
+__global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(WgradArgs a) {
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int co_tiles = a.cout_p / 16, ci_tiles = (a.cin + 15) / 16;
+    const int tiles = 9 * co_tiles * ci_tiles;
+    const int tile = wave % tiles;
+    const int chunk = wave / tiles;
+    const long long npx = (long long)a.N * a.H * a.W;
+    const long long p_begin = (long long)chunk * a.chunk_px;
+    if (p_begin >= npx) return;
+    const long long p_end = p_begin + a.chunk_px < npx ? p_begin + a.chunk_px : npx;
+    const int tap = tile % 9;
+    const int co_t = (tile / 9) % co_tiles, ci_t = tile / 9 / co_tiles;
+    const int du = tap / 3 - 1, dv = tap % 3 - 1;
+    const int co_a = co_t * 16 + r;  // A row of this lane
+    const int ci_b = ci_t * 16 + r;  // B column of this lane
+    const bool co_ok = co_a < a.cout, ci_ok = ci_b < a.cin;
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (long long pk = p_begin; pk < p_end; pk += 32) {
+        uint16_t ah[8], bh[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const long long p = pk + 8 * g + j;
+            ah[j] = 0;
+            bh[j] = 0;
+            if (p < p_end) {
+                if (co_ok) ah[j] = a.dz.p[p * a.dz.cs + a.dz.co + co_a];
+                const int x = int(p % a.W);
+                const long long t = p / a.W;
+                const int y = int(t % a.H);
+                const long long n = t / a.H;
+                const int yy = y + du, xx = x + dv;
+                if (ci_ok && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                    bh[j] = a.x.p[((n * a.H + yy) * a.W + xx) * a.x.cs + a.x.co + ci_b];
+            }
+        }
+        uint4 av, bv;
+        av.x = ah[0] | (uint32_t(ah[1]) << 16);
+        av.y = ah[2] | (uint32_t(ah[3]) << 16);
+        av.z = ah[4] | (uint32_t(ah[5]) << 16);
+        av.w = ah[6] | (uint32_t(ah[7]) << 16);
+        bv.x = bh[0] | (uint32_t(bh[1]) << 16);
+        bv.y = bh[2] | (uint32_t(bh[3]) << 16);
+        bv.z = bh[4] | (uint32_t(bh[5]) << 16);
+        bv.w = bh[6] | (uint32_t(bh[7]) << 16);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), as_bf16x8(bv), acc, 0, 0, 0);
+    }
+    // lane holds D[4 g + i][r]: co = co_t*16 + 4g + i, ci = ci_t*16 + r
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int co = co_t * 16 + 4 * g + i, ci = ci_t * 16 + r;
+        if (co < a.cout && ci < a.cin) atomicAdd(&a.dw[((size_t)tap * a.cout_p + co) * a.cin_p + ci], acc[i]);
+    }
+}
+
+// db[co] += sum_p dZ[p][co] over a chunk of pixels.
+__global__ __launch_bounds__(256) void bias_grad_kernel(TView dz, long long npx, int cout, long long chunk,
+                                                        float* __restrict__ db) {
+    const int co = threadIdx.x % 64 + 64 * (blockIdx.y);
+    const long long p0 = (long long)blockIdx.x * chunk;
+    if (co >= cout) return;
+    float s = 0.f;
+    for (long long p = p0 + threadIdx.x / 64; p < p0 + chunk && p < npx; p += 4) s += bf2f(dz.p[p * dz.cs + dz.co + co]);
+    atomicAdd(&db[co], s);
+}
+
+// ---------------------------------------------------------------- elementwise
+__global__ void avgpool2_kernel(TView in, TView out, int N, int H, int W, int C) {
+    const int Ho = H / 2, Wo = W / 2;
+    const long long total = (long long)N * Ho * Wo * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = int(i % C);
+        const long long q = i / C;
+        const int x = int(q % Wo);
+        const long long t = q / Wo;
+        const int y = int(t % Ho);
+        const long long n = t / Ho;
+        float s = 0.f;
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx)
+                s += bf2f(in.p[((n * H + 2 * y + dy) * W + 2 * x + dx) * in.cs + in.co + c]);
+        out.p[q * out.cs + out.co + c] = f2bf(0.25f * s);
+    }
+}
+
+// out (H, W) = in (H/2, W/2) repeated 2 x 2.
+__global__ void upsample2_kernel(TView in, TView out, int N, int H, int W, int C) {
+    const long long total = (long long)N * H * W * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = int(i % C);
+        const long long q = i / C;
+        const int x = int(q % W);
+        const long long t = q / W;
+        const int y = int(t % H);
+        const long long n = t / H;
+        out.p[q * out.cs + out.co + c] = in.p[((n * (H / 2) + y / 2) * (W / 2) + x / 2) * in.cs + in.co + c];
+    }
+}
+
+// Gradient of an upsampled tensor (sum of its 2 x 2 children in the FP32 concat
+// gradient), times the ReLU mask of the activation it came from.
+__global__ void upsample2_grad_kernel(const float* __restrict__ dcat, int dcs, int dco, TView act, TView dz, int N,
+                                      int Ho, int Wo, int C) {
+    const long long total = (long long)N * Ho * Wo * C;
+    const int H = 2 * Ho, W = 2 * Wo;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = int(i % C);
+        const long long q = i / C;
+        const int x = int(q % Wo);
+        const long long t = q / Wo;
+        const int y = int(t % Ho);
+        const long long n = t / Ho;
+        float s = 0.f;
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) s += dcat[((n * H + 2 * y + dy) * W + 2 * x + dx) * dcs + dco + c];
+        const float mk = bf2f(act.p[q * act.cs + act.co + c]);
+        dz.p[q * dz.cs + dz.co + c] = f2bf(mk > 0.f ? s : 0.f);
+    }
+}
+
+// Gradient of a skip tensor: its share of the FP32 concat gradient plus the
+// average-pooling gradient dpool / 4 of its parent pixel, times its ReLU mask.
+__global__ void skip_grad_kernel(const float* __restrict__ dcat, int dcs, int dco, const float* __restrict__ dpool,
+                                 int pcs, TView act, TView dz, int N, int H, int W, int C) {
+    const long long total = (long long)N * H * W * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = int(i % C);
+        const long long q = i / C;
+        const int x = int(q % W);
+        const long long t = q / W;
+        const int y = int(t % H);
+        const long long n = t / H;
+        const float gp = dpool[((n * (H / 2) + y / 2) * (W / 2) + x / 2) * pcs + c];
+        const float s = dcat[q * dcs + dco + c] + 0.25f * gp;
+        const float mk = bf2f(act.p[q * act.cs + act.co + c]);
+        dz.p[q * dz.cs + dz.co + c] = f2bf(mk > 0.f ? s : 0.f);
+    }
+}
+
+// NCHW FP32 input with 4 channels -> NHWC BF16 with 16 channels (12 zero).
+__global__ void pack_input_kernel(const float* __restrict__ in, int N, int H, int W, TView out) {
+    const long long total = (long long)N * H * W;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const long long n = q / ((long long)H * W), hw = q % ((long long)H * W);
+        for (int c = 0; c < 16; ++c)
+            out.p[q * out.cs + out.co + c] = c < 4 ? f2bf(in[(n * 4 + c) * H * W + hw]) : 0;
+    }
+}
+
+// MSE: dY = 2 (y - t) / count as the BF16 gradient of channel 0 (others 0), and the
+// per-block partial sums of (y - t)^2.
+__global__ __launch_bounds__(256) void mse_kernel(const float* __restrict__ y, const float* __restrict__ t,
+                                                  long long count, TView dz, double* __restrict__ partial) {
+    double s = 0.0;
+    for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < count; q += (long long)gridDim.x * 256) {
+        const float d = y[q] - t[q];
+        s += double(d) * d;
+        for (int c = 0; c < 16; ++c) dz.p[q * dz.cs + dz.co + c] = c == 0 ? f2bf(2.0f * d / float(count)) : 0;
+    }
+    __shared__ double sh[256];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// Adam on the FP32 master copy, then the BF16 working copy.
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, uint16_t* __restrict__ p_bf16, long long n, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        p[i] = pi;
+        if (p_bf16) p_bf16[i] = f2bf(pi);
+    }
+}
+
+// FP32 -> BF16 copy.
+__global__ void to_bf16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = f2bf(src[i]);
+}
+
+// Weights for the input gradient: Wt[t'][ci][co] = W[8 - t'][co][ci] (flip the 3 x 3
+// window, swap the channel roles), padded as [9][cin_p16][cout_p32].
+__global__ void flip_weights_kernel(const uint16_t* __restrict__ w, int cout_p, int cin_p, int cin, int cout,
+                                    uint16_t* __restrict__ wt, int t_cout_p, int t_cin_p) {
+    const long long total = 9LL * t_cout_p * t_cin_p;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int k = int(i % t_cin_p);        // original output channel
+        const int c = int((i / t_cin_p) % t_cout_p);  // original input channel
+        const int tp = int(i / t_cin_p / t_cout_p);
+        uint16_t v = 0;
+        if (c < cin && k < cout) v = w[((size_t)(8 - tp) * cout_p + k) * cin_p + c];
+        wt[i] = v;
+    }
+}
+
+// Gathers minibatch rows of a resident dataset: dst[b] = src[idx[b]] (float rows of len).
+__global__ void gather_rows_kernel(const float* __restrict__ src, const int* __restrict__ idx, long long len, int nb,
+                                   float* __restrict__ dst) {
+    const long long total = len * nb;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int b = int(i / len);
+        dst[i] = src[(long long)idx[b] * len + i % len];
+    }
+}
+
+int grid_for(long long n) {
+    long long g = (n + 255) / 256;
+    return int(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+
+}  // namespace
+
+hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
+    const long long npx = (long long)a.N * a.H * a.W;
+    (void)hipGetLastError();
+    if (a.cout_p % 32 == 0) {
+        const long long waves = ((npx + 63) / 64) * (a.cout_p / 32);
+        hipLaunchKernelGGL((conv3x3_kernel<4, 2>), dim3(int((waves + 3) / 4)), dim3(256), 0, s, a);
+    } else {
+        const long long waves = ((npx + 63) / 64) * (a.cout_p / 16);
+        hipLaunchKernelGGL((conv3x3_kernel<4, 1>), dim3(int((waves + 3) / 4)), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t conv3x3_wgrad(const WgradArgs& a, hipStream_t s) {
+    const long long npx = (long long)a.N * a.H * a.W;
+    const long long chunks = (npx + a.chunk_px - 1) / a.chunk_px;
+    const long long tiles = 9LL * (a.cout_p / 16) * ((a.cin + 15) / 16);
+    const long long waves = chunks * tiles;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3(int((waves + 3) / 4)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t bias_grad(TView dz, long long npx, int cout, float* db, hipStream_t s) {
+    const long long chunk = 4096;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(bias_grad_kernel, dim3(int((npx + chunk - 1) / chunk), (cout + 63) / 64), dim3(256), 0, s, dz,
+                       npx, cout, chunk, db);
+    return hipGetLastError();
+}
+
+hipError_t avgpool2(TView in, TView out, int N, int H, int W, int C, hipStream_t s) {
+    hipLaunchKernelGGL(avgpool2_kernel, dim3(grid_for((long long)N * H * W * C / 4)), dim3(256), 0, s, in, out, N, H,
+                       W, C);
+    return hipGetLastError();
+}
+
+hipError_t upsample2(TView in, TView out, int N, int H, int W, int C, hipStream_t s) {
+    hipLaunchKernelGGL(upsample2_kernel, dim3(grid_for((long long)N * H * W * C)), dim3(256), 0, s, in, out, N, H, W,
+                       C);
+    return hipGetLastError();
+}
+
+hipError_t upsample2_grad(const float* dcat, int dcs, int dco, TView act, TView dz, int N, int Ho, int Wo, int C,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(upsample2_grad_kernel, dim3(grid_for((long long)N * Ho * Wo * C)), dim3(256), 0, s, dcat, dcs,
+                       dco, act, dz, N, Ho, Wo, C);
+    return hipGetLastError();
+}
+
+hipError_t skip_grad(const float* dcat, int dcs, int dco, const float* dpool, int pcs, TView act, TView dz, int N,
+                     int H, int W, int C, hipStream_t s) {
+    hipLaunchKernelGGL(skip_grad_kernel, dim3(grid_for((long long)N * H * W * C)), dim3(256), 0, s, dcat, dcs, dco,
+                       dpool, pcs, act, dz, N, H, W, C);
+    return hipGetLastError();
+}
+
+hipError_t pack_input(const float* in, int N, int H, int W, TView out, hipStream_t s) {
+    hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for((long long)N * H * W)), dim3(256), 0, s, in, N, H, W, out);
+    return hipGetLastError();
+}
+
+hipError_t mse(const float* y, const float* t, long long count, TView dz, double* partial, int blocks,
+               hipStream_t s) {
+    hipLaunchKernelGGL(mse_kernel, dim3(blocks), dim3(256), 0, s, y, t, count, dz, partial);
+    return hipGetLastError();
+}
+
+hipError_t adam(float* p, const float* g, float* m, float* v, uint16_t* p_bf16, long long n, float lr, int step,
+                hipStream_t s) {
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - powf(b1, float(step)), c2 = 1.f - powf(b2, float(step));
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, g, m, v, p_bf16, n, lr, b1, b2, 1e-8f, c1,
+                       c2);
+    return hipGetLastError();
+}
+
+hipError_t to_bf16(const float* src, uint16_t* dst, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t flip_weights(const uint16_t* w, int cout_p, int cin_p, int cin, int cout, uint16_t* wt, int t_cout_p,
+                        int t_cin_p, hipStream_t s) {
+    hipLaunchKernelGGL(flip_weights_kernel, dim3(grid_for(9LL * t_cout_p * t_cin_p)), dim3(256), 0, s, w, cout_p,
+                       cin_p, cin, cout, wt, t_cout_p, t_cin_p);
+    return hipGetLastError();
+}
+
+hipError_t gather_rows(const float* src, const int* idx, long long len, int nb, float* dst, hipStream_t s) {
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_for(len * nb)), dim3(256), 0, s, src, idx, len, nb, dst);
+    return hipGetLastError();
+}
+
+}  // namespace sur
+}  // namespace cplbm

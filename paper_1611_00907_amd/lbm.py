@@ -35,6 +35,8 @@ EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lb
             "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_step_timed",
             "lbm_batch_run", "lbm_batch_status", "lbm_batch_get_fields", "lbm_batch_get_state",
             "lbm_batch_tune", "lbm_batch_fluid_nodes", "lbm_batch_destroy", "lbm_copy_bandwidth",
+            "sur_create", "sur_param_count", "sur_set_params", "sur_get_params", "sur_forward", "sur_gradients",
+            "sur_set_dataset", "sur_train", "sur_destroy",
             "lbm_get_monitors", "lbm_monitor_step", "lbm_get_state", "lbm_set_state",
             "lbm_get_temperature", "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_critical_point",
             "lbm_coexistence", "lbm_eos_eval", "lbm_contact_angle"]
@@ -124,6 +126,17 @@ def load_library():
     lib.lbm_batch_destroy.argtypes = [vp]
     lib.lbm_batch_destroy.restype = None
     lib.lbm_copy_bandwidth.argtypes = [C.c_size_t, C.c_int32, dp]
+    lib.sur_create.argtypes = [C.c_int32, C.c_int32, C.POINTER(vp)]
+    lib.sur_param_count.argtypes = [vp]
+    lib.sur_param_count.restype = C.c_int64
+    lib.sur_set_params.argtypes = [vp, vp]
+    lib.sur_get_params.argtypes = [vp, vp]
+    lib.sur_forward.argtypes = [vp, vp, C.c_int32, vp]
+    lib.sur_gradients.argtypes = [vp, vp, vp, C.c_int32, vp, dp]
+    lib.sur_set_dataset.argtypes = [vp, vp, vp, C.c_int32]
+    lib.sur_train.argtypes = [vp, C.c_int32, C.c_int32, C.c_float, C.c_uint64, vp]
+    lib.sur_destroy.argtypes = [vp]
+    lib.sur_destroy.restype = None
     lib.lbm_critical_point.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, dp, dp, dp]
     lib.lbm_coexistence.argtypes = [P, dp, dp, dp, dp]
     lib.lbm_eos_eval.argtypes = [P, C.c_int64, vp, vp, vp]
@@ -131,7 +144,8 @@ def load_library():
                                       dp, dp, dp]
     for name in EXPORTED:
         if name not in ("lbm_workspace_bytes", "lbm_destroy", "lbm_strerror", "lbm_last_error",
-                        "lbm_batch_workspace_bytes", "lbm_batch_fluid_nodes", "lbm_batch_destroy"):
+                        "lbm_batch_workspace_bytes", "lbm_batch_fluid_nodes", "lbm_batch_destroy",
+                        "sur_param_count", "sur_destroy"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -396,6 +410,88 @@ class Batch:
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:
             self.lib.lbm_batch_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- surrogate
+class Surrogate:
+    """The convolutional warm-start network (``sur_*``): BF16 MFMA kernels on the GPU.
+
+    Parameters use the exchange layout of ``lbm.h`` (per layer w[co][ci][3][3], b[co])."""
+
+    LAYERS = [("e0a", 16, 32), ("e0b", 32, 32), ("e1a", 32, 64), ("e1b", 64, 64), ("e2a", 64, 96),
+              ("e2b", 96, 96), ("e3a", 96, 128), ("e3b", 128, 128), ("d2a", 224, 96), ("d2b", 96, 96),
+              ("d1a", 160, 64), ("d1b", 64, 64), ("d0a", 96, 32), ("d0b", 32, 32), ("out", 32, 1)]
+
+    def __init__(self, size: int, max_batch: int):
+        self.lib = load_library()
+        self.size, self.max_batch = int(size), int(max_batch)
+        ctx = C.c_void_p()
+        _check(self.lib.sur_create(self.size, self.max_batch, C.byref(ctx)), "sur_create")
+        self.ctx = ctx
+        self.n_params = int(self.lib.sur_param_count(self.ctx))
+
+    @classmethod
+    def unflatten(cls, flat):
+        """Exchange-layout vector -> {name: (w [co,ci,3,3], b [co])}."""
+        out, o = {}, 0
+        for name, ci, co in cls.LAYERS:
+            w = flat[o:o + co * ci * 9].reshape(co, ci, 3, 3)
+            o += co * ci * 9
+            out[name] = (w, flat[o:o + co])
+            o += co
+        return out
+
+    @classmethod
+    def flatten(cls, params):
+        return np.concatenate([np.concatenate([np.asarray(params[n][0], np.float64).ravel(),
+                                               np.asarray(params[n][1], np.float64).ravel()])
+                               for n, _, _ in cls.LAYERS]).astype(np.float32)
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        assert flat.size == self.n_params
+        _check(self.lib.sur_set_params(self.ctx, _p(flat)), "sur_set_params")
+
+    def get_params(self):
+        flat = np.empty(self.n_params, np.float32)
+        _check(self.lib.sur_get_params(self.ctx, _p(flat)), "sur_get_params")
+        return flat
+
+    def forward(self, inputs):
+        x = np.ascontiguousarray(inputs, dtype=np.float32)
+        n = x.shape[0]
+        out = np.empty((n, self.size, self.size), np.float32)
+        _check(self.lib.sur_forward(self.ctx, _p(x), n, _p(out)), "sur_forward")
+        return out
+
+    def gradients(self, inputs, targets):
+        x = np.ascontiguousarray(inputs, dtype=np.float32)
+        t = np.ascontiguousarray(targets, dtype=np.float32)
+        g = np.empty(self.n_params, np.float32)
+        loss = C.c_double()
+        _check(self.lib.sur_gradients(self.ctx, _p(x), _p(t), x.shape[0], _p(g), C.byref(loss)), "sur_gradients")
+        return g, loss.value
+
+    def set_dataset(self, inputs, targets):
+        self._ds = (np.ascontiguousarray(inputs, dtype=np.float32), np.ascontiguousarray(targets, dtype=np.float32))
+        _check(self.lib.sur_set_dataset(self.ctx, _p(self._ds[0]), _p(self._ds[1]), self._ds[0].shape[0]),
+               "sur_set_dataset")
+
+    def train(self, steps: int, batch: int, lr: float, seed: int = 0):
+        losses = np.empty(int(steps), np.float32)
+        _check(self.lib.sur_train(self.ctx, int(steps), int(batch), float(lr), int(seed), _p(losses)), "sur_train")
+        return losses
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self.lib.sur_destroy(self.ctx)
             self.ctx = C.c_void_p()
 
     def __del__(self):

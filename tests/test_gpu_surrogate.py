@@ -1,0 +1,106 @@
+"""GPU: the surrogate's BF16 MFMA kernels against the FP64 oracle.
+
+Bounds come from BF16 arithmetic: every weight and activation is rounded to 8
+significant bits (unit roundoff u = 2^-8 ~ 0.4 %), once per layer, with FP32
+accumulation; through 15 layers the relative L2 error of the output stays near
+sqrt(15) u ~ 1.5 %, so the forward bound is 3 %.  Gradients pass the forward
+error and the backward roundings (about twice the layers, and the first layer's
+gradient sits at the end of the whole chain): cosine similarity >= 0.99 and norm
+within 5 % per layer."""
+import numpy as np
+import pytest
+
+from oracle import surrogate as S
+
+pytestmark = pytest.mark.gpu
+
+lbm = pytest.importorskip("paper_1611_00907_amd.lbm")
+
+
+def _setup(size=32, n=2, seed=3):
+    r = np.random.default_rng(seed)
+    params = S.init_params(11)
+    params = {k: (w, r.normal(0, 0.05, b.shape)) for k, (w, b) in params.items()}
+    x = r.normal(size=(n, S.IN_CHANNELS, size, size))
+    t = r.normal(size=(n, size, size))
+    net = lbm.Surrogate(size, max_batch=4)
+    flat = lbm.Surrogate.flatten(params)
+    net.set_params(flat)
+    # the oracle sees the same (FP32-rounded) parameters the GPU holds as its master copy
+    p32 = lbm.Surrogate.unflatten(flat.astype(np.float64))
+    return net, p32, x, t
+
+
+def _oracle_input(x):
+    xp = np.zeros((x.shape[0], S.IN_PADDED) + x.shape[2:])
+    xp[:, :S.IN_CHANNELS] = x
+    return xp
+
+
+def test_param_roundtrip():
+    net, p32, x, t = _setup()
+    back = net.get_params()
+    assert np.array_equal(back, lbm.Surrogate.flatten(p32))
+
+
+def test_forward_matches_oracle():
+    net, p32, x, t = _setup()
+    y = net.forward(x.astype(np.float32))
+    yo, _ = S.forward(p32, _oracle_input(x))
+    yo = yo[:, 0]
+    err = np.linalg.norm(y - yo) / np.linalg.norm(yo)
+    assert err < 0.03, err
+
+
+@pytest.mark.parametrize("size", [16, 64])
+def test_forward_other_sizes(size):
+    net, p32, x, t = _setup(size=size, n=3, seed=size)
+    y = net.forward(x.astype(np.float32))
+    yo = S.forward(p32, _oracle_input(x))[0][:, 0]
+    assert np.linalg.norm(y - yo) / np.linalg.norm(yo) < 0.03
+
+
+def test_gradients_match_oracle():
+    net, p32, x, t = _setup()
+    g, loss = net.gradients(x.astype(np.float32), t.astype(np.float32))
+    yo, cache = S.forward(p32, _oracle_input(x))
+    lo, dy = S.mse(yo, t[:, None])
+    go = S.backward(p32, cache, dy)
+    assert abs(loss - lo) < 0.03 * lo
+    gg = lbm.Surrogate.unflatten(g.astype(np.float64))
+    rows = []
+    for name, _, _ in lbm.Surrogate.LAYERS:
+        for k in (0, 1):
+            a, b = gg[name][k].ravel(), go[name][k].ravel()
+            cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30))
+            ratio = float(np.linalg.norm(a) / (np.linalg.norm(b) + 1e-30))
+            rows.append((name, "wb"[k], round(cos, 5), round(ratio, 4)))
+    print("gradient agreement (layer, w/b, cosine, norm ratio):", rows)
+    for name, k, cos, ratio in rows:
+        assert cos > 0.99 and abs(ratio - 1) < 0.05, (name, k, cos, ratio)
+
+
+def test_first_adam_step():
+    """One training step on a one-image dataset: the first Adam step moves every
+    parameter by -lr * g / (|g| + eps) with the gradient of that image."""
+    net, p32, x, t = _setup(n=1)
+    x32, t32 = x.astype(np.float32), t.astype(np.float32)
+    p0 = net.get_params()
+    g, _ = net.gradients(x32, t32)
+    net.set_dataset(x32, t32)
+    lr = 1e-3
+    net.train(1, 1, lr, seed=5)
+    p1 = net.get_params()
+    want = p0 - lr * g / (np.abs(g) + 1e-8)
+    big = np.abs(g) > 1e-4 * np.abs(g).max()   # away from the eps-dominated entries
+    assert np.max(np.abs(p1 - want)[big]) < 2e-6
+    assert np.max(np.abs(p1 - p0)) <= lr * 1.0001
+
+
+def test_training_reduces_loss():
+    net, p32, x, t = _setup(size=32, n=4)
+    tt = np.tanh(x[:, 1]) * 0.5                    # a learnable target: a pointwise map of one input
+    net.set_dataset(x.astype(np.float32), tt.astype(np.float32))
+    losses = net.train(150, 4, 2e-3, seed=1)
+    assert np.isfinite(losses).all()
+    assert losses[-10:].mean() < 0.3 * losses[:5].mean(), (losses[:5], losses[-10:])
