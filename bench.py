@@ -67,8 +67,10 @@ def spinodal_workload(lbm, inputs, prec, n=4096, rho_mean=2.6):
     """Precision configuration: 4096^2 periodic VdW spinodal decomposition at Tr = 0.85,
     tau = 1, kappa = 0.01, rho = rho_mean (1 + 0.01 U(-1, 1)); the mean density is not
     stated, 2.6 lies inside the spinodal (a quench from the critical density 3.5
-    overshoots into the EOS pole at this size)."""
-    p = lbm.make_params(n, n, lbm.LBM_EOS_VDW, 9 / 49, 2 / 21, 0.85, 1.0, 0.01, prec=prec)
+    overshoots into the EOS pole at this size).  The 16-bit formats store deviations from
+    w_i rho_mean: with the literal base w_i, BF16 loses the field within 1000 steps."""
+    rho_ref = rho_mean if prec in (lbm.LBM_F16DEV, lbm.LBM_BF16DEV) else 1.0
+    p = lbm.make_params(n, n, lbm.LBM_EOS_VDW, 9 / 49, 2 / 21, 0.85, 1.0, 0.01, prec=prec, rho_ref=rho_ref)
     rho0 = inputs.with_relative_noise(np.full((n, n), rho_mean), 0.01, 3)
     return p, rho0, None, n * n
 

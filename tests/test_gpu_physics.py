@@ -16,6 +16,9 @@ pytestmark = pytest.mark.gpu
 
 lbm = pytest.importorskip("paper_1611_00907_amd.lbm")
 
+STEPS_SPINODAL = 3000
+U32 = 2.0 ** -24          # FP32 unit roundoff
+
 
 def bulk_densities(rho):
     """Liquid and vapour bulk densities of a phase-separated field: medians of the
@@ -34,9 +37,9 @@ def bulk_densities(rho):
 
 @pytest.fixture(scope="module")
 def spinodal_runs():
-    """512^2 VdW spinodal decomposition (Tr = 0.85, rho = rho_c (1 + 0.01 U)), 3000 steps,
+    """512^2 VdW spinodal decomposition (Tr = 0.85, rho = 2.6 (1 + 0.01 U)), 3000 steps,
     in FP64 on the CPU oracle and in every GPU storage precision."""
-    steps = 3000
+    steps = STEPS_SPINODAL
     rho0 = C3_512.rho0()
     ora = C3_512.oracle()
     m0 = ora.mass()
@@ -55,24 +58,37 @@ def test_spinodal_fp64_gpu_statistics(spinodal_runs):
     g, l = bulk_densities(spinodal_runs["oracle"][0])
     g2, l2 = bulk_densities(spinodal_runs["f64"][0])
     assert abs(g2 / g - 1) < 1e-6 and abs(l2 / l - 1) < 1e-6
+    # The FP64 field has phase-separated to near the coexistence values: the liquid
+    # bulk near Maxwell's, the vapour of the still-coarsening field (3000 steps,
+    # droplets in a vapour continuum at a mean density of 2.6) within 15 %.
+    rg, rl, _, _ = thermo.maxwell(thermo.fluid_at(thermo.VDW, 9 / 49, 2 / 21, 1.0, 0.85))
+    print("oracle bulk densities vs Maxwell: liquid %+.4f, vapour %+.4f" % (l / rl - 1, g / rg - 1))
+    assert abs(l / rl - 1) < 0.03
+    assert abs(g / rg - 1) < 0.15
 
 
-@pytest.mark.parametrize("name,tol", [("f32", 2e-3), ("f16", 1e-2), ("bf16", 5e-2)])
+# Stated tolerances on the bulk densities relative to the FP64 oracle.
+@pytest.mark.parametrize("name,tol", [("f32", 1e-4), ("f16", 1e-2), ("bf16", 5e-2)])
 def test_reduced_precision_coexistence(spinodal_runs, name, tol):
     """Bulk densities of the phase-separated field in reduced precision against the
-    FP64 oracle, and against the Maxwell values (the discrete equilibrium sits a
-    few percent off, as for the planar interface)."""
+    FP64 oracle (statistics of the two chaotic runs, not nodes)."""
     g, l = bulk_densities(spinodal_runs["oracle"][0])
     gp, lp = bulk_densities(spinodal_runs[name][0])
+    print("%s bulk densities vs oracle: vapour %.2e, liquid %.2e" % (name, gp / g - 1, lp / l - 1))
     assert abs(gp / g - 1) < tol and abs(lp / l - 1) < tol, (name, gp, g, lp, l)
-    rg, rl, _, _ = thermo.maxwell(thermo.fluid_at(thermo.VDW, 9 / 49, 2 / 21, 1.0, 0.85))
-    assert abs(lp / rl - 1) < 0.03 and abs(gp / rg - 1) < 0.08
 
 
-@pytest.mark.parametrize("name,tol", [("oracle", 1e-12), ("f64", 1e-12), ("f32", 1e-5), ("f16", 1e-2),
-                                      ("bf16", 5e-2)])
+# The scheme conserves mass exactly; only storage rounding moves it.  FP32 storage
+# rounds each population to half an ulp, so a systematic drift of at most about one
+# unit roundoff per step is the bound; the 16-bit deviation formats are reported
+# against stated tolerances (their worst-case rounding bound exceeds one).
+@pytest.mark.parametrize("name,tol", [("oracle", 1e-12), ("f64", 1e-12), ("f32", STEPS_SPINODAL * U32),
+                                      ("f16", 1e-2), ("bf16", 1e-1)])
 def test_mass_drift(spinodal_runs, name, tol):
-    assert abs(spinodal_runs[name][1]) < tol
+    d = spinodal_runs[name][1]
+    print("%s mass drift %.3e over %d steps (%.3e per 1000 steps)" % (name, d, STEPS_SPINODAL,
+                                                                      d * 1000 / STEPS_SPINODAL))
+    assert abs(d) < tol
 
 
 def _wetting_batch(eos, a, b, omega, Tr, nx, ny, R, mus, steps):
