@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-bytes", type=int, default=1 << 30,
                     help="size of the plain copy whose bandwidth is reported beside the roofline")
+    ap.add_argument("--workload", choices=("wetting1024", "spinodal4096"), default="wetting1024",
+                    help="main measurement: the 1024^2 FP32 wetting configuration (default) or the "
+                         "4096^2 FP32 spinodal lattice (for profiling the HBM-bound size)")
     return ap.parse_args()
 
 
@@ -114,15 +117,15 @@ def measure_batch(lbm, inputs, steps):
                          "traffic": None}}
 
 
-def traffic_for(workload: str, bytes_per_launch: float):
+def traffic_for(workload: str, shape: int):
     """HBM bytes per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE counts, each
     scaled by what the counter reads for a plain copy of known size, if they were
-    taken on the current kernel source (else None)."""
+    taken on the current kernel source and launch shape (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("kernel_sha") != kernel_sha():
+    if d.get("kernel_sha") != kernel_sha() or d.get("shape") != shape:
         return None
     return round((d["fetch_kib_per_dispatch"] * d["fetch_factor"] +
                   d["write_kib_per_dispatch"] * d["write_factor"]) * 1024.0, 0)
@@ -138,31 +141,38 @@ def _with_monitor(p, every):
 
 def measure(lbm, p, rho0, mu_w, fluid_nodes, steps, warmup, bytes_per_lu, workload):
     """Times the step with HIP events on the lattice's own stream (lbm_step_timed)."""
-    def lattice(every):
+    def lattice(every, shape=None):
         lat = lbm.Lattice(_with_monitor(p, every), rho0)
         if mu_w is not None:
             lat.set_wall_mu(0, mu_w)
+        if shape is not None:
+            lat.set_tile(shape)
         lat.step(warmup)
         return lat
 
-    # kernel only: back-to-back fused steps, no monitors
+    # launch shape from the library's tuner (tiles of several widths, column marching)
     lat = lattice(0)
+    shape, _ = lat.tune(trial_steps=20)
+    lat.close()
+    # kernel only: back-to-back fused steps, no monitors
+    lat = lattice(0, shape)
     k_steps = max(steps, 100)
     t_kernel = lat.step_timed(k_steps) / 1e3 / k_steps
     lat.close()
     # whole step: fused update plus the monitors every MONITOR_EVERY steps
-    lat = lattice(MONITOR_EVERY)
+    lat = lattice(MONITOR_EVERY, shape)
     n_steps = max(steps // MONITOR_EVERY, 1) * MONITOR_EVERY
     t_total = lat.step_timed(n_steps) / 1e3
     mon = lat.monitors()
     lat.close()
     achieved = fluid_nodes * bytes_per_lu / t_kernel / 1e9
-    traffic = traffic_for(workload, fluid_nodes * bytes_per_lu)
+    traffic = traffic_for(workload, shape)
     return {
         "mlups": fluid_nodes * n_steps / t_total / 1e6,
         "ms_per_step": t_total / n_steps * 1e3,
         "steps": n_steps,
         "kernel_us": t_kernel * 1e6,
+        "shape": shape,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic},
         "monitor": {"mass": mon["mass"], "residual": mon["residual"], "flags": mon["flags"]},
@@ -201,9 +211,18 @@ def main():
 
     copy_gbs = lbm.lbm_copy_bandwidth(args.copy_bytes, 20)
     print("copy: %.1f GB/s over %d bytes" % (copy_gbs, args.copy_bytes), file=sys.stderr, flush=True)
-    p, rho0, mu_w, fluid = wetting_workload(lbm, inputs, lbm.LBM_F32)
+    if args.workload == "wetting1024":
+        p, rho0, mu_w, fluid = wetting_workload(lbm, inputs, lbm.LBM_F32)
+        config = {"workload": "wetting 1024x1024 D2Q9, PR omega=0.344 Tr=0.8, tau=1.3, kappa=0.01, "
+                              "CP wall + neutral top, drop R=200, monitors every 100 steps",
+                  "nx": 1024, "ny": 1024, "storage": "f32", "parallelism": "single GPU"}
+    else:
+        p, rho0, mu_w, fluid = spinodal_workload(lbm, inputs, lbm.LBM_F32)
+        config = {"workload": "spinodal 4096x4096 D2Q9, VdW Tr=0.85, tau=1, kappa=0.01, periodic, "
+                              "rho = 2.6 (1 + 0.01 U), monitors every 100 steps",
+                  "nx": 4096, "ny": 4096, "storage": "f32", "parallelism": "single GPU"}
     main_res = measure(lbm, p, rho0, mu_w, fluid, args.steps, args.warmup, 72.0,
-                       "step_f32_wetting1024")
+                       "step_f32_" + args.workload)
     print("main: %.1f MLUPS, kernel %.2f us, %.1f GB/s" % (main_res["mlups"], main_res["kernel_us"],
                                                           main_res["roofline"]["achieved"]),
           file=sys.stderr, flush=True)
@@ -216,7 +235,7 @@ def main():
             res = measure(lbm, pp, r0, None, fl, 300, 20, b, "step_%s_spinodal4096" % name)
             aux.append({"workload": "spinodal 4096x4096 VdW Tr=0.85, %s storage" % name,
                         "mlups": round(res["mlups"], 1), "kernel_us": round(res["kernel_us"], 2),
-                        "roofline": res["roofline"]})
+                        "shape": res["shape"], "roofline": res["roofline"]})
             print("aux %s: %.1f MLUPS %.1f GB/s" % (name, res["mlups"], res["roofline"]["achieved"]),
                   file=sys.stderr, flush=True)
         res = measure_batch(lbm, inputs, 320)
@@ -238,11 +257,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "wetting 1024x1024 D2Q9, PR omega=0.344 Tr=0.8, tau=1.3, kappa=0.01, "
-                               "CP wall + neutral top, drop R=200, monitors every 100 steps",
-                   "nx": 1024, "ny": 1024, "storage": "f32", "parallelism": "single GPU"},
+        "config": config,
         "roofline": main_res["roofline"],
         "kernel_us": round(main_res["kernel_us"], 3),
+        "shape": main_res["shape"],
         "copy_kernel": {"bytes": args.copy_bytes, "gbs": round(copy_gbs, 1),
                         "step_frac_of_copy": round(main_res["roofline"]["achieved"] / copy_gbs, 4)},
         "aux": aux,

@@ -115,13 +115,27 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n);
  * monitors included.  Synchronises. */
 lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* ms);
 
-/* Tile-shape tuner: times trial_steps fused steps for each supported tile height
- * (8, 16, 32 rows of 64 columns) without changing the state (every trial maps the
- * current state to the spare buffer), keeps the fastest for this context and
- * returns it with its time per step in ms.  Synchronises. */
+/* Launch shapes of the fused step, as a shape code:
+ *   8, 16, 32         tiles of 64 columns and that many rows, one per workgroup
+ *                     (the default is 16);
+ *   12816, 12832, 25608, 25616
+ *                     wider tiles, 100 * columns + rows (128 x 16, 128 x 32,
+ *                     256 x 8, 256 x 16), 512 threads each;
+ *   -1 .. -8          column marching: a workgroup owns a strip of at most 252
+ *                     columns and marches up a segment of rows, keeping the
+ *                     neighbouring rows' densities and chemical potentials on
+ *                     chip; -k splits the rows into as many segments as fill k
+ *                     workgroups per compute unit.  Offered when one
+ *                     distribution buffer (nine planes) stays below 2 GiB.
+ * Every shape computes the same step.
+ *
+ * Shape tuner: times trial_steps fused steps for each shape offered on this
+ * lattice without changing the state (every trial maps the current state to the
+ * spare buffer), keeps the fastest for this context and returns its code with its
+ * time per step in ms.  Synchronises. */
 lbm_status lbm_tune(lbm_ctx* c, int32_t trial_steps, int32_t* tile_y, double* best_ms);
 
-/* Sets the tile height (8, 16 or 32) directly; LBM_EINVAL for other values. */
+/* Sets the shape code directly; LBM_EINVAL for a code not offered on this lattice. */
 lbm_status lbm_set_tile(lbm_ctx* c, int32_t tile_y);
 
 /* Output fields of the current state into host arrays [ny][nx]: density (Eq 28

@@ -102,7 +102,9 @@ LatticeArgs lattice_args(const lbm_params& p, const thermo::Fluid& fl, const Lay
     A.pitch = L.pitch;
     A.bottom = p.bc_bottom;
     A.top = p.bc_top;
-    A.tile_y = TILE_Y_DEFAULT;
+    // 128 x 16 tiles where a lattice is at least that wide: the fastest tile at the
+    // sizes measured, before any tuning
+    A.tile_y = p.nx >= 128 ? 12816 : TILE_Y_DEFAULT;
     A.plane = L.plane;
     A.tau = p.tau;
     A.inv_tau = 1.0 / p.tau;
@@ -419,7 +421,13 @@ lbm_status lbm_tune(lbm_ctx* c, int32_t trial_steps, int32_t* tile_y, double* be
     double best = 1e300;
     int best_ty = c->A.tile_y;
     hipError_t e = hipSuccess;
-    for (int ty : TILE_Y_CHOICES) {
+    int shapes[7 + MARCH_K_MAX], nshapes = 0;
+    for (int ty : TILE_Y_CHOICES) shapes[nshapes++] = ty;
+    for (int code : WIDE_TILE_CODES) shapes[nshapes++] = code;
+    if (march_allowed(c->A, c->p.prec))
+        for (int k = 1; k <= MARCH_K_MAX; ++k) shapes[nshapes++] = -k;
+    for (int k = 0; k < nshapes; ++k) {
+        const int ty = shapes[k];
         LatticeArgs A = c->A;
         A.tile_y = ty;
         // trial launches only read the state: each maps f[cur] -> f[cur ^ 1]
@@ -456,6 +464,9 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t tile_y) {
     if (!c) return LBM_EINVAL;
     bool ok = false;
     for (int ty : TILE_Y_CHOICES) ok = ok || ty == tile_y;
+    for (int code : WIDE_TILE_CODES) ok = ok || code == tile_y;
+    if (march_allowed(c->A, c->p.prec))
+        ok = ok || (tile_y < 0 && -tile_y <= MARCH_K_MAX);
     if (!ok) return LBM_EINVAL;
     if (tile_y != c->A.tile_y) {
         c->A.tile_y = tile_y;

@@ -18,6 +18,22 @@ constexpr int TILE_X = 64;
 constexpr int ROWS_PER_THREAD = 4;
 constexpr int TILE_Y_DEFAULT = 16;
 constexpr int TILE_Y_CHOICES[3] = {8, 16, 32};
+// Wider tiles of the single-lattice step, as shape codes 100 * width + height:
+// 128 x 16 and 256 x 8 (4 rows per thread), 128 x 32 and 256 x 16 (8 rows per
+// thread), each run by 512 threads.  A wider tile pulls a smaller fraction of
+// redundant ring nodes.
+constexpr int WIDE_TILE_CODES[4] = {12816, 12832, 25608, 25616};
+
+// Column-marching shape: a workgroup of MARCH_NT lanes owns a strip of at most
+// MARCH_OWN columns (two halo lanes per side) and marches up a segment of rows.  A
+// lattice's shape code (LatticeArgs::tile_y) is the tile height for tiles, or -k
+// for marching with k resident workgroups per CU (1 <= k <= MARCH_K_MAX): the rows
+// are split into as many segments as fill that many workgroups per CU.  Marching
+// needs the nine planes of one buffer below 2 GiB (32-bit buffer offsets).
+constexpr int MARCH_NT = 256;
+constexpr int MARCH_OWN = MARCH_NT - 4;
+constexpr int MARCH_K_MAX = 8;
+constexpr long long MARCH_MAX_BYTES = (1LL << 31) - 1;
 
 // Constants of the bulk chemical potential, precomputed on the host in FP64.
 struct EosConst {
@@ -33,7 +49,7 @@ struct LatticeArgs {
     int nx, ny;
     int pitch;            // elements per row (>= nx)
     int bottom, top;      // Bc of rows 0 and ny-1
-    int tile_y;           // rows per tile (one of TILE_Y_CHOICES)
+    int tile_y;           // shape code: tile height (64-wide tiles), a wide-tile code, or -k (marching)
     long long plane;      // elements per direction plane = ny * pitch
     double tau, inv_tau, kappa;
     double rho_ref;       // deviation base of the half/bf16 storage
@@ -92,5 +108,10 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 size_t storage_bytes(int prec);
 size_t compute_bytes(int prec);
+
+// Whether the column-marching shapes may run on this lattice and storage type.
+inline bool march_allowed(const LatticeArgs& A, int prec) {
+    return 9 * A.plane * (long long)storage_bytes(prec) <= MARCH_MAX_BYTES;
+}
 
 }  // namespace cplbm

@@ -14,6 +14,8 @@
 // 14 with u + tau F / rho) and writes the tile.  Wall rows get their density from
 // Eq 28 and their chemical potential from the surface value (Sec. IV) or from the
 // neighbouring fluid node (Sec. V).
+#include <algorithm>
+
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -228,6 +230,45 @@ __device__ __forceinline__ void grad9(const CT (*s)[W], int r, int c, CT& gx, CT
     gy = (s[r + 1][c] - s[r - 1][c]) * third + ((ne + nw) - (se + sw)) * twelfth;
 }
 
+// Momentum sum_i f_i e_i of one node.
+template <typename CT>
+__device__ __forceinline__ void momentum(const CT f[9], CT& jx, CT& jy) {
+    jx = ((f[1] - f[3]) + (f[5] - f[6])) + (f[8] - f[7]);
+    jy = ((f[2] - f[4]) + (f[5] + f[6])) - (f[7] + f[8]);
+}
+
+// Force of Eq 12 from the chemical-potential and density gradients, then the BGK
+// collision of Eqs 13 and 14 with the equilibrium velocity u + tau F / rho:
+// fs[i] = f_i - (f_i - f_i^eq) / tau.
+template <typename CT>
+__device__ __forceinline__ void collide(const CT f[9], CT rho, CT jx, CT jy, CT gmx, CT gmy, CT grx, CT gry,
+                                        CT tau, CT inv_tau, CT fs[9]) {
+    constexpr CT third = CT(1) / CT(3);
+    const CT Fx = -rho * gmx + grx * third;
+    const CT Fy = -rho * gmy + gry * third;
+    const CT inv_rho = rcp(rho);
+    const CT ux = jx * inv_rho, uy = jy * inv_rho;
+    const CT uex = ux + tau * Fx * inv_rho, uey = uy + tau * Fy * inv_rho;
+    const CT usq = CT(1.5) * (uex * uex + uey * uey);
+    const CT r0 = Wt<CT>::w0 * rho, r1 = Wt<CT>::w1 * rho, r2 = Wt<CT>::w2 * rho;
+    CT feq[9];
+    feq[0] = r0 * (CT(1) - usq);
+    {
+        const CT e1 = uex, e2 = uey;
+        feq[1] = r1 * (CT(1) + CT(3) * e1 + CT(4.5) * e1 * e1 - usq);
+        feq[3] = r1 * (CT(1) - CT(3) * e1 + CT(4.5) * e1 * e1 - usq);
+        feq[2] = r1 * (CT(1) + CT(3) * e2 + CT(4.5) * e2 * e2 - usq);
+        feq[4] = r1 * (CT(1) - CT(3) * e2 + CT(4.5) * e2 * e2 - usq);
+        const CT d5 = uex + uey, d6 = uey - uex;
+        feq[5] = r2 * (CT(1) + CT(3) * d5 + CT(4.5) * d5 * d5 - usq);
+        feq[7] = r2 * (CT(1) - CT(3) * d5 + CT(4.5) * d5 * d5 - usq);
+        feq[6] = r2 * (CT(1) + CT(3) * d6 + CT(4.5) * d6 * d6 - usq);
+        feq[8] = r2 * (CT(1) - CT(3) * d6 + CT(4.5) * d6 * d6 - usq);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fs[i] = f[i] - (f[i] - feq[i]) * inv_tau;
+}
+
 __device__ __forceinline__ int tile_of_block(int b, int nblk) {
     // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
     // band of tiles so that halos shared by neighbouring tiles stay in its L2.
@@ -236,25 +277,25 @@ __device__ __forceinline__ int tile_of_block(int b, int nblk) {
 }
 
 // ---------------------------------------------------------------- the fused step
-template <typename CT, int TY>
+template <typename CT, int TY, int TX = TILE_X>
 struct TileLds {
-    CT rs[TY + 4][TILE_X + 4];  // density, tile + 2-node ring
-    CT ms[TY + 2][TILE_X + 2];  // chemical potential, tile + 1-node ring
+    CT rs[TY + 4][TX + 4];  // density, tile + 2-node ring
+    CT ms[TY + 2][TX + 2];  // chemical potential, tile + 1-node ring
 };
 
-// One TILE_X x TY tile of the step (MODE_STEP) or of the field output (MODE_FIELDS),
-// run by a workgroup of TILE_X * TY / ROWS_PER_THREAD threads.
-template <typename ST, int EOS, int MODE, int TY>
+// One TX x TY tile of the step (MODE_STEP) or of the field output (MODE_FIELDS),
+// run by a workgroup of TX * TY / RPT threads, RPT nodes of one column per thread.
+template <typename ST, int EOS, int MODE, int TY, int TX = TILE_X, int RPT = ROWS_PER_THREAD>
 __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __restrict__ fin,
                                           ST* __restrict__ fout,
                                           const typename Codec<ST>::CT* __restrict__ mu_w,
                                           double* __restrict__ out, int x0, int y0,
-                                          TileLds<typename Codec<ST>::CT, TY>& L) {
+                                          TileLds<typename Codec<ST>::CT, TY, TX>& L) {
     using CT = typename Codec<ST>::CT;
     using C = Codec<ST>;
-    constexpr int RW = TILE_X + 4, MW = TILE_X + 2;
-    constexpr int NT = TILE_X * TY / ROWS_PER_THREAD;  // threads
-    constexpr int RS = TY / ROWS_PER_THREAD;           // row stride between a thread's nodes
+    constexpr int RW = TX + 4, MW = TX + 2;
+    constexpr int NT = TX * TY / RPT;  // threads
+    constexpr int RS = TY / RPT;       // row stride between a thread's nodes
     auto& rs = L.rs;
     auto& ms = L.ms;
 
@@ -262,24 +303,23 @@ __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __rest
 #pragma unroll
     for (int i = 0; i < 9; ++i) F.p[i] = fin + (long long)i * A.plane;
 
-    const int lx = threadIdx.x % TILE_X, ly = threadIdx.x / TILE_X;
-    const bool small_x = A.nx < TILE_X + 2, small_y = A.ny < TY + 2;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const bool small_x = A.nx < TX + 2, small_y = A.ny < TY + 2;
 
     // 1. own nodes: pull, keep f, density into LDS
-    CT f[ROWS_PER_THREAD][9];
-    CT jx[ROWS_PER_THREAD], jy[ROWS_PER_THREAD];
+    CT f[RPT][9];
+    CT jx[RPT], jy[RPT];
     const int gx_raw = x0 + lx;
     const int gxw = wrap_fast(gx_raw, A.nx, small_x);
 #pragma unroll
-    for (int k = 0; k < ROWS_PER_THREAD; ++k) {
+    for (int k = 0; k < RPT; ++k) {
         const int gy = y0 + ly + k * RS;
         const bool own = gx_raw < A.nx && gy < A.ny && !solid_row(A, gy);
         CT r;
         if (own) {
             pull9<ST, CT>(A, F, gxw, gy, f[k]);
             r = sum9(f[k]);
-            jx[k] = ((f[k][1] - f[k][3]) + (f[k][5] - f[k][6])) + (f[k][8] - f[k][7]);
-            jy[k] = ((f[k][2] - f[k][4]) + (f[k][5] + f[k][6])) - (f[k][7] + f[k][8]);
+            momentum(f[k], jx[k], jy[k]);
         } else {
             r = node_rho<ST, CT>(A, F, gxw, gy, small_y);
         }
@@ -301,7 +341,7 @@ __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __rest
             c = (q - 4 * RW) % 2;
         } else {
             r = 2 + (q - 4 * RW - 2 * TY) / 2;
-            c = TILE_X + 2 + (q - 4 * RW - 2 * TY) % 2;
+            c = TX + 2 + (q - 4 * RW - 2 * TY) % 2;
         }
         rs[r][c] = node_rho<ST, CT>(A, F, wrap_fast(x0 - 2 + c, A.nx, small_x), y0 - 2 + r, small_y);
     }
@@ -339,7 +379,7 @@ __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __rest
     const CT b0 = CT(A.rho_ref) * Wt<CT>::w0, b1 = CT(A.rho_ref) * Wt<CT>::w1,
              b2 = CT(A.rho_ref) * Wt<CT>::w2;
 #pragma unroll
-    for (int k = 0; k < ROWS_PER_THREAD; ++k) {
+    for (int k = 0; k < RPT; ++k) {
         const int ry = ly + k * RS;
         const int gy = y0 + ry;
         if (gx_raw >= A.nx || gy >= A.ny) continue;
@@ -361,56 +401,40 @@ __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __rest
         CT gmx, gmy, grx, gry;
         grad9<CT, MW>(ms, ry + 1, lx + 1, gmx, gmy);
         grad9<CT, RW>(rs, ry + 2, lx + 2, grx, gry);
-        constexpr CT third = CT(1) / CT(3);
-        const CT Fx = -rho * gmx + grx * third;
-        const CT Fy = -rho * gmy + gry * third;
-        const CT inv_rho = rcp(rho);
-        const CT ux = jx[k] * inv_rho, uy = jy[k] * inv_rho;
         if (MODE == MODE_FIELDS) {
+            constexpr CT third = CT(1) / CT(3);
+            const CT Fx = -rho * gmx + grx * third;
+            const CT Fy = -rho * gmy + gry * third;
+            const CT inv_rho = rcp(rho);
             const long long o = (long long)gy * A.nx + gx_raw;
             const long long P = (long long)A.nx * A.ny;
             out[o] = double(rho);
-            out[P + o] = double(ux + CT(0.5) * Fx * inv_rho);
-            out[2 * P + o] = double(uy + CT(0.5) * Fy * inv_rho);
+            out[P + o] = double(jx[k] * inv_rho + CT(0.5) * Fx * inv_rho);
+            out[2 * P + o] = double(jy[k] * inv_rho + CT(0.5) * Fy * inv_rho);
             out[3 * P + o] = double(ms[ry + 1][lx + 1]);
             continue;
         }
-        const CT uex = ux + tau * Fx * inv_rho, uey = uy + tau * Fy * inv_rho;
-        const CT usq = CT(1.5) * (uex * uex + uey * uey);
-        const CT r0 = Wt<CT>::w0 * rho, r1 = Wt<CT>::w1 * rho, r2 = Wt<CT>::w2 * rho;
-        CT feq[9];
-        feq[0] = r0 * (CT(1) - usq);
-        {
-            const CT e1 = uex, e2 = uey;
-            feq[1] = r1 * (CT(1) + CT(3) * e1 + CT(4.5) * e1 * e1 - usq);
-            feq[3] = r1 * (CT(1) - CT(3) * e1 + CT(4.5) * e1 * e1 - usq);
-            feq[2] = r1 * (CT(1) + CT(3) * e2 + CT(4.5) * e2 * e2 - usq);
-            feq[4] = r1 * (CT(1) - CT(3) * e2 + CT(4.5) * e2 * e2 - usq);
-            const CT d5 = uex + uey, d6 = uey - uex;
-            feq[5] = r2 * (CT(1) + CT(3) * d5 + CT(4.5) * d5 * d5 - usq);
-            feq[7] = r2 * (CT(1) - CT(3) * d5 + CT(4.5) * d5 * d5 - usq);
-            feq[6] = r2 * (CT(1) + CT(3) * d6 + CT(4.5) * d6 * d6 - usq);
-            feq[8] = r2 * (CT(1) - CT(3) * d6 + CT(4.5) * d6 * d6 - usq);
-        }
+        CT fs[9];
+        collide<CT>(f[k], rho, jx[k], jy[k], gmx, gmy, grx, gry, tau, inv_tau, fs);
         const unsigned o = unsigned(gy) * unsigned(A.pitch) + unsigned(gx_raw);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const CT fs = f[k][i] - (f[k][i] - feq[i]) * inv_tau;
             const CT base = i == 0 ? b0 : (i < 5 ? b1 : b2);
-            C::st(fout + (long long)i * A.plane, o, fs, base);
+            C::st(fout + (long long)i * A.plane, o, fs[i], base);
         }
     }
 }
 
 // One lattice: one workgroup per tile.
-template <typename ST, int EOS, int MODE, int TY>
-__global__ __launch_bounds__(TILE_X * TY / ROWS_PER_THREAD) void step_kernel(
-    LatticeArgs A, const ST* __restrict__ fin, ST* __restrict__ fout,
-    const typename Codec<ST>::CT* __restrict__ mu_w, double* __restrict__ out) {
-    __shared__ TileLds<typename Codec<ST>::CT, TY> L;
+template <typename ST, int EOS, int MODE, int TY, int TX = TILE_X, int RPT = ROWS_PER_THREAD>
+__global__ __launch_bounds__(TX * TY / RPT) void step_kernel(LatticeArgs A, const ST* __restrict__ fin,
+                                                            ST* __restrict__ fout,
+                                                            const typename Codec<ST>::CT* __restrict__ mu_w,
+                                                            double* __restrict__ out) {
+    __shared__ TileLds<typename Codec<ST>::CT, TY, TX> L;
     const int t = tile_of_block(blockIdx.x, gridDim.x);
-    const int tiles_x = (A.nx + TILE_X - 1) / TILE_X;
-    step_tile<ST, EOS, MODE, TY>(A, fin, fout, mu_w, out, (t % tiles_x) * TILE_X, (t / tiles_x) * TY, L);
+    const int tiles_x = (A.nx + TX - 1) / TX;
+    step_tile<ST, EOS, MODE, TY, TX, RPT>(A, fin, fout, mu_w, out, (t % tiles_x) * TX, (t / tiles_x) * TY, L);
 }
 
 // Many lattices in one persistent launch: each workgroup walks a contiguous range
@@ -439,6 +463,368 @@ __global__ __launch_bounds__(TILE_X * TY / ROWS_PER_THREAD) void batch_step_kern
         }
         __syncthreads();  // the next tile reuses the LDS
     }
+}
+
+// ---------------------------------------------------------------- column-marching step
+// For large lattices a workgroup owns a strip of MARCH_OWN columns and a segment of
+// rows, one lane per column plus two halo lanes on each side, and marches up the
+// segment one row per iteration.  Iteration R pulls row R (its loads were issued one
+// iteration earlier) and puts its density into an LDS ring of rows, evaluates the
+// chemical potential of row R - 2 into a second ring, and collides row R - 3 from
+// distributions it kept in registers.  Every (plane, row) of f*(t-1) is read once
+// per strip, the only redundant work is the two halo lanes per side and four extra
+// rows per segment, and one barrier per row orders the rings.  Loads and stores are
+// raw buffer accesses: the lane's column is a fixed byte offset, plane and row a
+// uniform one, so no per-load address arithmetic remains.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* p, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
+}
+
+// ldr: the raw stored value; dec: the distribution it holds (deviation formats add
+// w_i rho_ref back); st: encode and store.  Loads stay raw until their row is used,
+// so that a row's loads are issued back to back.
+template <typename ST>
+struct RawIO;
+template <>
+struct RawIO<double> {
+    using RT = double;
+    static __device__ __forceinline__ RT ldr(__amdgpu_buffer_rsrc_t r, int v, int s) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+    }
+    static __device__ __forceinline__ double dec(RT x, double) { return x; }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int v, int s, double x, double) {
+        using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, x), r, v, s, 0);
+    }
+};
+template <>
+struct RawIO<float> {
+    using RT = float;
+    static __device__ __forceinline__ RT ldr(__amdgpu_buffer_rsrc_t r, int v, int s) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+    }
+    static __device__ __forceinline__ float dec(RT x, float) { return x; }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int v, int s, float x, float) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, 0);
+    }
+};
+template <>
+struct RawIO<__half> {
+    using RT = unsigned short;
+    static __device__ __forceinline__ RT ldr(__amdgpu_buffer_rsrc_t r, int v, int s) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0);
+    }
+    static __device__ __forceinline__ float dec(RT x, float base) {
+        return __half2float(__builtin_bit_cast(__half, x)) + base;
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int v, int s, float x, float base) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(x - base)), r, v,
+                                              s, 0);
+    }
+};
+template <>
+struct RawIO<__hip_bfloat16> {
+    using RT = unsigned short;
+    static __device__ __forceinline__ RT ldr(__amdgpu_buffer_rsrc_t r, int v, int s) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0);
+    }
+    static __device__ __forceinline__ float dec(RT x, float base) {
+        return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, x)) + base;
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int v, int s, float x, float base) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2bfloat16(x - base)), r, v,
+                                              s, 0);
+    }
+};
+
+__device__ __forceinline__ int wrap_col(int x, int n) {
+    x %= n;
+    return x < 0 ? x + n : x;
+}
+
+template <typename ST, int EOS>
+struct March {
+    using CT = typename Codec<ST>::CT;
+    using IO = RawIO<ST>;
+    static constexpr int NT = MARCH_NT;
+    static constexpr int LW = MARCH_NT + 2;  // ring row: one pad entry on each side
+    static constexpr int SZ = int(sizeof(ST));
+    // A byte offset no buffer reaches: raw buffer accesses beyond the buffer's size
+    // are dropped (stores) or read zero (loads), which masks a lane without a branch.
+    static constexpr int NOWHERE = int(0x80000000u);
+
+    const LatticeArgs& A;
+    CT (*rs)[LW];  // density ring, 8 rows
+    CT (*ms)[LW];  // chemical-potential ring, 4 rows
+    const CT* mu_w;
+    __amdgpu_buffer_rsrc_t rin, rout;
+    int l, ys, ye, xr, xw;  // lane, segment rows [ys, ye), raw and wrapped column
+    int vc, vm, vp;         // byte offsets of the columns x, x - 1, x + 1
+    int vs;                 // store offset: vc on owned lanes, NOWHERE elsewhere
+    int PB, RB;             // bytes per plane, per row
+    bool walled, live, mu_lane, owned;
+    bool nr;  // the next lane holds a density of this strip
+    CT b0, b1, b2, tau, inv_tau, kappa;
+    typename IO::RT fr[9];  // raw values of row R + 1, in flight
+    CT fd[4][9];            // distributions of rows R, R-1, R-2, R-3 (slot = phase)
+
+    __device__ __forceinline__ CT* rrow(int R) const { return rs[R & 7] + 1; }
+    __device__ __forceinline__ CT* mrow(int m) const { return ms[m & 3] + 1; }
+
+    __device__ __forceinline__ int wrap_row(int r) const {
+        while (r < 0) r += A.ny;
+        while (r >= A.ny) r -= A.ny;
+        return r;
+    }
+    __device__ __forceinline__ bool fluid_row(int R) const {
+        return walled ? (R >= 1 && R <= A.ny - 2) : true;
+    }
+    __device__ __forceinline__ CT base(int i) const { return i == 0 ? b0 : (i < 5 ? b1 : b2); }
+
+    // f_i of row r from rows rm (below) and rp (above) at the column whose own /
+    // left / right byte offsets are cc / cm / cp (pull streaming; reflected
+    // populations when the row below / above is solid, sm / sp).
+    __device__ __forceinline__ void pull_rows(int r, int rm, int rp, bool sm, bool sp, typename IO::RT g[9],
+                                              int cc, int cm, int cp) const {
+        const int oc = r * RB, om = rm * RB, op = rp * RB;
+        g[0] = IO::ldr(rin, cc, oc);
+        g[1] = IO::ldr(rin, cm, PB + oc);
+        g[3] = IO::ldr(rin, cp, 3 * PB + oc);
+        if (sm) {
+            g[2] = IO::ldr(rin, cc, 4 * PB + oc);
+            g[5] = IO::ldr(rin, cc, 7 * PB + oc);
+            g[6] = IO::ldr(rin, cc, 8 * PB + oc);
+        } else {
+            g[2] = IO::ldr(rin, cc, 2 * PB + om);
+            g[5] = IO::ldr(rin, cm, 5 * PB + om);
+            g[6] = IO::ldr(rin, cp, 6 * PB + om);
+        }
+        if (sp) {
+            g[4] = IO::ldr(rin, cc, 2 * PB + oc);
+            g[7] = IO::ldr(rin, cc, 5 * PB + oc);
+            g[8] = IO::ldr(rin, cc, 6 * PB + oc);
+        } else {
+            g[4] = IO::ldr(rin, cc, 4 * PB + op);
+            g[7] = IO::ldr(rin, cp, 7 * PB + op);
+            g[8] = IO::ldr(rin, cm, 8 * PB + op);
+        }
+    }
+    // f_i of fluid row R, any row of the lattice.
+    __device__ __forceinline__ void pull_row(int R, typename IO::RT g[9], int cc, int cm, int cp) const {
+        if (walled)
+            pull_rows(R, R - 1, R + 1, R - 1 == 0, R + 1 == A.ny - 1, g, cc, cm, cp);
+        else
+            pull_rows(wrap_row(R), wrap_row(R - 1), wrap_row(R + 1), false, false, g, cc, cm, cp);
+    }
+    __device__ __forceinline__ void decode(const typename IO::RT g[9], CT d[9]) const {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] = IO::dec(g[i], base(i));
+    }
+
+    // Density of fluid row rf at the column next to this lane's (dx = -1 or +1).
+    __device__ __forceinline__ CT side_rho(int rf, int dx) const {
+        const int x = wrap_col(xw + dx, A.nx);
+        typename IO::RT g[9];
+        CT d[9];
+        pull_row(rf, g, x * SZ, wrap_col(x - 1, A.nx) * SZ, wrap_col(x + 1, A.nx) * SZ);
+        decode(g, d);
+        return sum9(d);
+    }
+
+    // Eq 28: density of the solid row next to fluid row rf.
+    __device__ __forceinline__ CT ghost(int rf) const {
+        const CT* q = rrow(rf);
+        const CT r0 = q[l];
+        const CT rl = l > 0 ? q[l - 1] : side_rho(rf, -1);
+        const CT rr = nr ? q[l + 1] : side_rho(rf, +1);
+        return CT(2) / CT(3) * r0 + CT(1) / CT(6) * rl + CT(1) / CT(6) * rr;
+    }
+
+    __device__ __forceinline__ CT lap(const CT* a, const CT* b, const CT* c) const {
+        const CT axis = (b[l - 1] + b[l + 1]) + (a[l] + c[l]);
+        const CT diag = (a[l - 1] + a[l + 1]) + (c[l - 1] + c[l + 1]);
+        return CT(2) / CT(3) * axis + CT(1) / CT(6) * diag - CT(10) / CT(3) * b[l];
+    }
+    __device__ __forceinline__ void grad(const CT* a, const CT* b, const CT* c, CT& gx, CT& gy) const {
+        const CT ne = c[l + 1], nw = c[l - 1], se = a[l + 1], sw = a[l - 1];
+        constexpr CT third = CT(1) / CT(3), twelfth = CT(1) / CT(12);
+        gx = (b[l + 1] - b[l - 1]) * third + ((ne - nw) + (se - sw)) * twelfth;
+        gy = (c[l] - a[l]) * third + ((ne + nw) - (se + sw)) * twelfth;
+    }
+    __device__ __forceinline__ CT mu_at(int m) const {
+        return mu_bulk<EOS, CT>(A.eos, rrow(m)[l]) - kappa * lap(rrow(m - 1), rrow(m), rrow(m + 1));
+    }
+    // Collision of row c with the distributions g, stored to f*(t) at store offset v.
+    __device__ __forceinline__ void collide_row(int c, const CT g[9], int v) const {
+        CT gmx, gmy, grx, gry, jx, jy;
+        grad(mrow(c - 1), mrow(c), mrow(c + 1), gmx, gmy);
+        grad(rrow(c - 1), rrow(c), rrow(c + 1), grx, gry);
+        momentum(g, jx, jy);
+        CT fs[9];
+        collide<CT>(g, rrow(c)[l], jx, jy, gmx, gmy, grx, gry, tau, inv_tau, fs);
+        const int oc = c * RB;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) IO::st(rout, v, i * PB + oc, fs[i], base(i));
+    }
+
+    // Any iteration: every row kind (periodic wrap, walls, Eq 28 ghosts, wall mu).
+    template <int P>
+    __device__ __forceinline__ void iter(int R) {
+        constexpr int PC = (P + 1) % 4;         // slot of row R - 3
+        R = __builtin_amdgcn_readfirstlane(R);  // uniform: keeps row offsets scalar
+        // (a) density of row R (its loads were issued one iteration earlier)
+        if (R <= ye + 1 && live) {
+            if (fluid_row(R)) {
+                decode(fr, fd[P]);
+                rrow(R)[l] = sum9(fd[P]);
+            } else if (walled && R == A.ny - 1) {
+                rrow(R)[l] = ghost(R - 1);
+            }
+        }
+        // (b) issue the loads of row R + 1; they complete under (c), the barrier and (d)
+        if (R + 1 <= ye + 1 && live && fluid_row(R + 1)) pull_row(R + 1, fr, vc, vm, vp);
+        // (c) chemical potential of row m = R - 2 (Eq 8; wall rows from Sec. IV / V)
+        const int m = R - 2;
+        if (m >= ys - 1 && m <= ye) {
+            if (!walled || (m >= 1 && m <= A.ny - 2)) {
+                if (mu_lane) {
+                    const CT mu = mu_at(m);
+                    mrow(m)[l] = mu;
+                    if (walled && m == 1) {
+                        CT w = mu;
+                        if (A.bottom == BC_CPWALL) w = mu_w[xw];
+                        mrow(0)[l] = w;
+                    }
+                }
+            } else if (walled && m == 0) {
+                if (live) rrow(0)[l] = ghost(1);
+            } else if (walled && m == A.ny - 1) {
+                if (mu_lane) {
+                    CT mu;
+                    if (A.top == BC_CPWALL) {
+                        mu = mu_w[A.pitch + xw];
+                    } else {
+                        mu = mrow(m - 1)[l];
+                    }
+                    mrow(m)[l] = mu;
+                }
+            }
+        }
+        __syncthreads();
+        // (d) collision of row c = R - 3, stored to f*(t)
+        const int c = R - 3;
+        if (c >= ys && c < ye && owned && fluid_row(c)) collide_row(c, fd[PC], vc);
+    }
+
+    // An interior iteration (rows R - 4 .. R + 2 are fluid rows inside the lattice,
+    // no wrap, no wall): the same work with no branch, so the memory operations of
+    // every iteration are the same and the loads of row R need not wait for the
+    // stores issued after them.  Lanes outside the strip's columns compute values
+    // nobody reads (the ring rows are padded) and store nowhere.
+    template <int P>
+    __device__ __forceinline__ void steady(int R) {
+        constexpr int PC = (P + 1) % 4;
+        R = __builtin_amdgcn_readfirstlane(R);
+        decode(fr, fd[P]);
+        rrow(R)[l] = sum9(fd[P]);
+        pull_rows(R + 1, R, R + 2, false, false, fr, vc, vm, vp);
+        mrow(R - 2)[l] = mu_at(R - 2);
+        __syncthreads();
+        collide_row(R - 3, fd[PC], vs);
+    }
+
+    __device__ __forceinline__ void run() {
+        const int R0 = ys - 2, Rend = ye + 2;
+        int R = R0;
+        if (live && fluid_row(R)) pull_row(R, fr, vc, vm, vp);
+        // interior iterations [S0, S1]; S0p: first iteration of a four-row block at
+        // or after S0, so that the register rotation's phase there is zero
+        const int S0 = walled ? max(ys + 3, 4) : ys + 3;
+        const int S1 = min(ye, walled ? A.ny - 4 : A.ny - 3);
+        const int S0p = R0 + 4 * ((S0 - R0 + 3) / 4);
+        const int stop = min(S0p, Rend + 1);
+        while (R < stop) {  // iterations past Rend do nothing
+            iter<0>(R);
+            iter<1>(R + 1);
+            iter<2>(R + 2);
+            iter<3>(R + 3);
+            R += 4;
+        }
+        if (R == S0p && R + 3 <= S1) {
+            __builtin_amdgcn_s_waitcnt(0);  // the interior loop starts with nothing in flight
+            do {
+                steady<0>(R);
+                steady<1>(R + 1);
+                steady<2>(R + 2);
+                steady<3>(R + 3);
+                R += 4;
+            } while (R + 3 <= S1);
+        }
+        for (;;) {
+            if (R > Rend) break;
+            iter<0>(R);
+            if (++R > Rend) break;
+            iter<1>(R);
+            if (++R > Rend) break;
+            iter<2>(R);
+            if (++R > Rend) break;
+            iter<3>(R);
+            ++R;
+        }
+    }
+};
+
+// One strip-segment per workgroup.  The lattice's columns are split evenly into
+// `strips` strips of at most MARCH_OWN columns and its rows evenly into `segs`
+// segments of at least 4 rows (so only the first segment touches the bottom wall
+// rows).  The host keeps the nine planes of one buffer below 2 GiB (32-bit buffer
+// offsets) and sizes the grid so that every workgroup is resident at once.
+#ifndef MARCH_WAVES_PER_EU
+#define MARCH_WAVES_PER_EU 4
+#endif
+template <typename ST, int EOS>
+__global__ __launch_bounds__(MARCH_NT) __attribute__((amdgpu_waves_per_eu(MARCH_WAVES_PER_EU))) void march_kernel(
+    LatticeArgs A, const ST* __restrict__ fin, ST* __restrict__ fout,
+    const typename Codec<ST>::CT* __restrict__ mu_w, int strips, int segs) {
+    using CT = typename Codec<ST>::CT;
+    using M_t = March<ST, EOS>;
+    __shared__ CT rs[8][MARCH_NT + 2];
+    __shared__ CT ms[4][MARCH_NT + 2];
+    const int t = tile_of_block(blockIdx.x, gridDim.x);
+    const int s = t % strips, g = t / strips;
+    M_t M{A};
+    M.rs = rs;
+    M.ms = ms;
+    M.mu_w = mu_w;
+    const int bytes = int(9 * A.plane * (long long)sizeof(ST));
+    M.rin = buffer_of(fin, bytes);
+    M.rout = buffer_of(fout, bytes);
+    M.l = threadIdx.x;
+    M.ys = int((long long)g * A.ny / segs);
+    M.ye = int((long long)(g + 1) * A.ny / segs);
+    const int x0 = int((long long)s * A.nx / strips), x1 = int((long long)(s + 1) * A.nx / strips);
+    const int xr = x0 - 2 + M.l;  // this lane's raw column
+    M.xr = xr;
+    M.xw = wrap_col(xr, A.nx);
+    M.walled = A.bottom != BC_PERIODIC;
+    M.live = xr < x1 + 2;
+    M.mu_lane = M.l >= 1 && xr < x1 + 1;
+    M.owned = M.l >= 2 && xr < x1;
+    M.nr = M.live && M.l < MARCH_NT - 1 && xr + 1 < x1 + 2;
+    // lanes past the strip's halo read nowhere (zero, no memory traffic)
+    M.vc = M.live ? M.xw * int(sizeof(ST)) : M_t::NOWHERE;
+    M.vm = M.live ? wrap_col(xr - 1, A.nx) * int(sizeof(ST)) : M_t::NOWHERE;
+    M.vp = M.live ? wrap_col(xr + 1, A.nx) * int(sizeof(ST)) : M_t::NOWHERE;
+    M.vs = M.owned ? M.vc : M_t::NOWHERE;
+    M.PB = int(A.plane * (long long)sizeof(ST));
+    M.RB = A.pitch * int(sizeof(ST));
+    M.b0 = CT(A.rho_ref) * Wt<CT>::w0;
+    M.b1 = CT(A.rho_ref) * Wt<CT>::w1;
+    M.b2 = CT(A.rho_ref) * Wt<CT>::w2;
+    M.tau = CT(A.tau);
+    M.inv_tau = CT(A.inv_tau);
+    M.kappa = CT(A.kappa);
+    M.run();
 }
 
 // ---------------------------------------------------------------- monitors
@@ -701,33 +1087,56 @@ __global__ void get_state_kernel(LatticeArgs A, const ST* __restrict__ fstore, d
     for (int i = 0; i < 9; ++i) f_out[(long long)i * n + c] = double(f[i]);
 }
 
+template <typename ST, int EOS, int MODE, int TY, int TX, int RPT>
+hipError_t step_launch(const LatticeArgs& A, const void* fin, void* fout, const void* mu_w, double* out,
+                       hipStream_t s) {
+    using CT = typename Codec<ST>::CT;
+    const int tiles = ((A.nx + TX - 1) / TX) * ((A.ny + TY - 1) / TY);
+    (void)hipGetLastError();  // drop any error left by earlier runtime calls
+    hipLaunchKernelGGL((step_kernel<ST, EOS, MODE, TY, TX, RPT>), dim3(tiles), dim3(TX * TY / RPT), 0, s, A,
+                       (const ST*)fin, (ST*)fout, (const CT*)mu_w, out);
+    return hipGetLastError();
+}
+
 template <typename ST, int EOS, int MODE>
 hipError_t step_ty(int tile_y, const LatticeArgs& A, const void* fin, void* fout, const void* mu_w, double* out,
                    hipStream_t s) {
-    using CT = typename Codec<ST>::CT;
-    const int tiles = ((A.nx + TILE_X - 1) / TILE_X) * ((A.ny + tile_y - 1) / tile_y);
-    (void)hipGetLastError();  // drop any error left by earlier runtime calls
     switch (tile_y) {
-    case 8:
-        hipLaunchKernelGGL((step_kernel<ST, EOS, MODE, 8>), dim3(tiles), dim3(TILE_X * 8 / ROWS_PER_THREAD), 0, s, A,
-                           (const ST*)fin, (ST*)fout, (const CT*)mu_w, out);
-        break;
-    case 16:
-        hipLaunchKernelGGL((step_kernel<ST, EOS, MODE, 16>), dim3(tiles), dim3(TILE_X * 16 / ROWS_PER_THREAD), 0, s,
-                           A, (const ST*)fin, (ST*)fout, (const CT*)mu_w, out);
-        break;
-    case 32:
-        hipLaunchKernelGGL((step_kernel<ST, EOS, MODE, 32>), dim3(tiles), dim3(TILE_X * 32 / ROWS_PER_THREAD), 0, s,
-                           A, (const ST*)fin, (ST*)fout, (const CT*)mu_w, out);
-        break;
+    case 8: return step_launch<ST, EOS, MODE, 8, 64, 4>(A, fin, fout, mu_w, out, s);
+    case 16: return step_launch<ST, EOS, MODE, 16, 64, 4>(A, fin, fout, mu_w, out, s);
+    case 32: return step_launch<ST, EOS, MODE, 32, 64, 4>(A, fin, fout, mu_w, out, s);
+    case 12816: return step_launch<ST, EOS, MODE, 16, 128, 4>(A, fin, fout, mu_w, out, s);
+    case 12832: return step_launch<ST, EOS, MODE, 32, 128, 8>(A, fin, fout, mu_w, out, s);
+    case 25608: return step_launch<ST, EOS, MODE, 8, 256, 4>(A, fin, fout, mu_w, out, s);
+    case 25616: return step_launch<ST, EOS, MODE, 16, 256, 8>(A, fin, fout, mu_w, out, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+// Column-marching launch with k resident workgroups per CU: the rows are split
+// into as many segments as fill k workgroups per CU over all strips (one round).
+template <typename ST, int EOS>
+hipError_t march_launch(int k, const LatticeArgs& A, const void* fin, void* fout, const void* mu_w, hipStream_t s) {
+    using CT = typename Codec<ST>::CT;
+    if (k < 1 || k > MARCH_K_MAX || 9 * A.plane * (long long)sizeof(ST) > MARCH_MAX_BYTES)
+        return hipErrorInvalidValue;
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    const long long strips = (A.nx + MARCH_OWN - 1) / MARCH_OWN;
+    long long segs = (long long)k * cus / strips;
+    segs = std::min<long long>(segs, A.ny / 4);
+    segs = std::max<long long>(segs, 1);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL((march_kernel<ST, EOS>), dim3(unsigned(strips * segs)), dim3(MARCH_NT), 0, s, A,
+                       (const ST*)fin, (ST*)fout, (const CT*)mu_w, int(strips), int(segs));
     return hipGetLastError();
 }
 
 template <typename ST, int EOS>
 hipError_t step_eos(int mode, int tile_y, const LatticeArgs& A, const void* fin, void* fout, const void* mu_w,
                     double* out, hipStream_t s) {
+    if (mode == MODE_STEP && tile_y < 0) return march_launch<ST, EOS>(-tile_y, A, fin, fout, mu_w, s);
     if (mode == MODE_STEP) return step_ty<ST, EOS, MODE_STEP>(tile_y, A, fin, fout, mu_w, out, s);
     return step_ty<ST, EOS, MODE_FIELDS>(16, A, fin, fout, mu_w, out, s);  // output uses one shape
 }

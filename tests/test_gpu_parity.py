@@ -63,19 +63,84 @@ def test_fp64_walled_pr_2000_steps():
         _compare_state(lat, ora, 1e-10)
 
 
-@pytest.mark.parametrize("nx,ny,walls", [(70, 37, False), (130, 45, True), (5, 7, False), (1, 9, False),
-                                         (3, 4, True), (65, 17, True), (200, 3, True), (64, 16, False),
-                                         (129, 18, False)])
+RAGGED = [(70, 37, False), (130, 45, True), (5, 7, False), (1, 9, False), (3, 4, True), (65, 17, True),
+          (200, 3, True), (64, 16, False), (129, 18, False)]
+
+
+def _ragged_case(nx, ny, walls):
+    kw = dict(bottom=CPWALL, top=NEUTRAL, drop="sessile") if walls else dict(drop="circle")
+    return Case(nx, ny, thermo.PR, 0.8, 1.3, omega=0.344, radius=max(min(nx, ny) / 3, 0.8), noise=1e-3,
+                seed=nx * 1000 + ny, mu_w_bottom=0.25, **kw)
+
+
+@pytest.mark.parametrize("nx,ny,walls", RAGGED)
 def test_fp64_ragged_and_tiny(nx, ny, walls):
     """Sizes that are not multiples of the 64 x 16 tile, smaller than one tile,
     one column wide, or a single fluid row between walls."""
-    kw = dict(bottom=CPWALL, top=NEUTRAL, drop="sessile") if walls else dict(drop="circle")
-    c = Case(nx, ny, thermo.PR, 0.8, 1.3, omega=0.344, radius=max(min(nx, ny) / 3, 0.8), noise=1e-3,
-             seed=nx * 1000 + ny, mu_w_bottom=0.25, **kw)
+    c = _ragged_case(nx, ny, walls)
     lat, ora = _gpu(c, lbm.LBM_F64), c.oracle()
     lat.step(25)
     ora.step(25)
     _compare_state(lat, ora, 1e-10)
+
+
+WIDE_CASES = RAGGED + [(300, 70, False), (257, 37, True), (520, 130, True), (129, 33, True)]
+
+
+@pytest.mark.parametrize("code", [12816, 12832, 25608, 25616])
+@pytest.mark.parametrize("nx,ny,walls", WIDE_CASES)
+def test_fp64_wide_tiles(nx, ny, walls, code):
+    """Tiles of 128 and 256 columns (shape code 100 * width + height) on ragged,
+    tiny and walled lattices."""
+    c = _ragged_case(nx, ny, walls)
+    lat, ora = _gpu(c, lbm.LBM_F64), c.oracle()
+    lat.set_tile(code)
+    lat.step(25)
+    ora.step(25)
+    _compare_state(lat, ora, 1e-10)
+
+
+# Column marching: strips of at most 252 columns (256 lanes with two halo lanes per
+# side), rows split into segments of at least 4 rows that fill k workgroups per CU.
+# Cases span several strips and segments with ragged ends, strips one column past
+# 252, segments that hold the bottom wall's ghost rows and the top wall, segments
+# of 4 rows, and lattices narrower than one strip.
+MARCH_CASES = RAGGED + [(300, 70, False), (252, 64, True), (253, 37, True), (520, 130, True),
+                        (505, 97, False), (700, 300, False)]
+
+
+@pytest.mark.parametrize("shape", [-1, -2, -4, -8])
+@pytest.mark.parametrize("nx,ny,walls", MARCH_CASES)
+def test_fp64_marching_shapes(nx, ny, walls, shape):
+    c = _ragged_case(nx, ny, walls)
+    lat, ora = _gpu(c, lbm.LBM_F64), c.oracle()
+    lat.set_tile(shape)
+    lat.step(25)
+    ora.step(25)
+    _compare_state(lat, ora, 1e-10)
+
+
+def test_fp64_marching_cp_top_and_every_eos():
+    """Per-column surface chemical potentials on both walls, and each EOS, marching."""
+    c = Case(300, 40, thermo.PR, 0.8, 1.3, omega=0.344, bottom=CPWALL, top=CPWALL, drop="sessile",
+             radius=14, noise=1e-3, seed=9)
+    x = np.arange(300)
+    c.mu_w_bottom = 0.2 + 0.05 * np.sin(2 * np.pi * x / 300)
+    c.mu_w_top = 0.27 + 0.01 * np.cos(2 * np.pi * x / 60)
+    lat, ora = _gpu(c, lbm.LBM_F64), c.oracle()
+    lat.set_tile(-4)
+    lat.step(300)
+    ora.step(300)
+    _compare_state(lat, ora, 1e-10)
+    for eos in (thermo.VDW, thermo.CS, thermo.PR, thermo.RKS, thermo.RK):
+        Tr = {thermo.CS: 0.8}.get(eos, 0.85)
+        c = Case(260, 48, eos, Tr, 1.3, omega=0.344 if eos in (thermo.PR, thermo.RKS) else 0.0,
+                 drop="circle", radius=12, noise=1e-3, seed=eos + 20)
+        lat, ora = _gpu(c, lbm.LBM_F64), c.oracle()
+        lat.set_tile(-2)
+        lat.step(100)
+        ora.step(100)
+        _compare_state(lat, ora, 1e-10)
 
 
 def test_fp64_per_node_wall_mu_and_cp_top():
@@ -188,20 +253,24 @@ def test_reduced_storage_one_and_ten_steps(prec, u):
     _compare_state(lat, ora, 12 * u)
 
 
-def test_fp32_full_size_config2():
-    """1024 x 1024 wetting case in the benchmark's launch configuration: every
-    node against the oracle after 20 steps."""
+@pytest.mark.parametrize("shape", [16, 32, 25616, -4])
+def test_fp32_full_size_config2(shape):
+    """1024 x 1024 wetting case in both launch shapes: every node against the
+    oracle after 20 steps."""
     lat, ora = _gpu(C2, lbm.LBM_F32), C2.oracle()
+    lat.set_tile(shape)
     lat.step(20)
     ora.step(20)
     _compare_state(lat, ora, 2e-5)
 
 
-def test_fp32_full_size_4096_sampled():
+@pytest.mark.parametrize("shape", [16, 25616, -2])
+def test_fp32_full_size_4096_sampled(shape):
     """4096^2 spinodal case: after k steps a node depends on the initial field within
     3k nodes, so periodic oracle windows with a 3k margin give exact samples."""
     k = 8
     lat = _gpu(C3, lbm.LBM_F32)
+    lat.set_tile(shape)
     rho0 = C3.rho0()
     lat.step(k)
     f, _ = lat.get_state()
