@@ -392,6 +392,13 @@ class Batch:
                "lbm_batch_get_fields")
         return out
 
+    def rho(self, i: int):
+        """Density of case i (the other output fields are not computed into host memory)."""
+        p = self.cases[i]
+        r = np.empty((p.ny, p.nx))
+        _check(self.lib.lbm_batch_get_fields(self.ctx, int(i), _p(r), None, None, None), "lbm_batch_get_fields")
+        return r
+
     def get_state(self, i: int):
         p = self.cases[i]
         f = np.empty((9, p.ny, p.nx))

@@ -47,7 +47,13 @@ class CaseSpec:
                                bc_bottom=lbm.LBM_BC_CPWALL, bc_top=lbm.LBM_BC_NEUTRAL)
 
     def coexistence(self):
-        return lbm.lbm_coexistence(self.params())
+        key = (self.eos, self.Tr)
+        if key not in _COEX:
+            _COEX[key] = lbm.lbm_coexistence(self.params())
+        return _COEX[key]
+
+
+_COEX: dict = {}   # (eos, Tr) -> (rho_g, rho_l, p_sat, mu_sat): host FP64, independent of the lattice
 
 
 def initial_density(spec: CaseSpec):
@@ -56,15 +62,19 @@ def initial_density(spec: CaseSpec):
 
 
 def measure_angle(rho):
-    """Contact angle of the drop on the first fluid row (NaN if there is no drop)."""
+    """Contact angle of the drop on the first fluid row (NaN if there is no drop, or
+    if the liquid covers the whole base row, a film rather than a drop)."""
     rg = float(np.median(rho[-10:-2]))
     rl = float(np.max(rho[1:-1]))
     if not np.isfinite(rg + rl) or rl <= rg * 1.5:
         return float("nan")
     try:
-        return lbm.lbm_contact_angle(rho, 0.5 * (rg + rl), base_row=1)[0]
+        th, L, _ = lbm.lbm_contact_angle(rho, 0.5 * (rg + rl), base_row=1)
     except lbm.LbmError:
         return float("nan")
+    if not (0.0 < th < 180.0) or L >= rho.shape[1] - 2:
+        return float("nan")
+    return th
 
 
 # ---------------------------------------------------------------- 1. calibration
@@ -84,7 +94,7 @@ def calibrate(Tr_grid=(0.6, 0.7, 0.8, 0.9), side=128, steps=20000, offsets=None)
         b = lbm.Batch([s.params() for s in specs], [initial_density(s) for s in specs],
                       mu_w_bottom=[s.mu_w for s in specs])
         b.step(steps)
-        th = np.array([measure_angle(b.fields(i)["rho"]) for i in range(len(specs))])
+        th = np.array([measure_angle(b.rho(i)) for i in range(len(specs))])
         b.close()
         k = len(offsets[eos])
         for j, Tr in enumerate(Tr_grid):
@@ -124,27 +134,33 @@ def generate(specs, max_steps=60000, check_every=2000, window=1000, tol=1e-9):
                   mu_w_bottom=[s.mu_w for s in specs])
     b.run(max_steps, check_every=check_every, window=window, tol=tol)
     st = b.status()
-    rho = [b.fields(i)["rho"] for i in range(len(specs))]
+    rho = [b.rho(i) for i in range(len(specs))]
     b.close()
     return rho, st["state"], st["steps"]
 
 
 # ---------------------------------------------------------------- 3. features
-def features(spec: CaseSpec):
-    """Network input [4][side][side] for a case."""
+def phase(spec: CaseSpec, rho):
+    """(rho - rho_g) / (rho_l - rho_g): 0 in the vapour, 1 in the liquid at coexistence."""
     rg, rl, _, _ = spec.coexistence()
+    return (np.asarray(rho, np.float64) - rg) / (rl - rg)
+
+
+def features(spec: CaseSpec):
+    """Network input [4][side][side] for a case: solid mask, phase of the initial
+    density, T/Tc, and the wall chemical potential's place in the wetting range."""
     x = np.zeros((4, spec.side, spec.side), np.float32)
     x[0, 0, :] = 1.0
     x[0, -1, :] = 1.0
-    x[1] = initial_density(spec) / rl
+    x[1] = phase(spec, initial_density(spec))
     x[2] = spec.Tr
     x[3] = spec.frac
     return x
 
 
 def target(spec: CaseSpec, rho_eq):
-    rl = spec.coexistence()[1]
-    return (rho_eq / rl).astype(np.float32)
+    """Network target: the phase of the equilibrium density."""
+    return phase(spec, rho_eq).astype(np.float32)
 
 
 def he_init(seed):
@@ -158,47 +174,191 @@ def he_init(seed):
 
 
 # ---------------------------------------------------------------- 5. time to equilibrium
-def time_to_angle(specs, rho_starts, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000):
-    """Steps until each case's angle enters tol of theta_eq and stays there at every
-    later check, starting from rho_starts; also the device time per batched step."""
+def time_to_angle(specs, rho_starts, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000, hold=4,
+                  log=None):
+    """Per case, the step from which the contact angle stays within tol of theta_eq
+    (checked every check_every steps, -1 if never), running all cases as one batch
+    until every case has stayed inside for `hold` checks; also the device time per
+    batched step."""
     b = lbm.Batch([s.params() for s in specs], rho_starts, mu_w_bottom=[s.mu_w for s in specs])
     n = len(specs)
     first_in = np.full(n, -1, np.int64)
     t_dev = 0.0
     steps = 0
-    while steps < max_steps:
-        th = np.array([measure_angle(b.fields(i)["rho"]) for i in range(n)])
+    while True:
+        th = np.array([measure_angle(b.rho(i)) for i in range(n)])
         inside = np.abs(th - theta_eq) <= tol_deg
-        for i in range(n):
-            if inside[i] and first_in[i] < 0:
-                first_in[i] = steps
-            elif not inside[i]:
-                first_in[i] = -1
-        if steps > 0 and (first_in >= 0).all() and steps - first_in.min() >= 4 * check_every:
+        first_in[~inside] = -1
+        first_in[inside & (first_in < 0)] = steps
+        if (first_in >= 0).all() and steps - first_in.max() >= hold * check_every:
+            break
+        if steps >= max_steps:
             break
         t_dev += b.step_timed(check_every) / 1e3
         steps += check_every
+        if log and steps % (25 * check_every) == 0:
+            log("  step %d: %d of %d cases within %.1f deg" % (steps, int((first_in >= 0).sum()), n, tol_deg))
     b.close()
     step_time = t_dev / max(steps, 1)
     return first_in, step_time
 
 
-def clamp_prediction(spec: CaseSpec, pred):
+def _smooth(a):
+    """One pass of the D2Q9-weighted average (4/9 centre, 1/9 axes, 1/36 diagonals),
+    periodic in x, rows clamped at the edges."""
+    p = np.pad(a, ((1, 1), (0, 0)), mode="edge")
+    p = np.concatenate([p[:, -1:], p, p[:, :1]], axis=1)
+    c = p[1:-1, 1:-1]
+    ax = p[:-2, 1:-1] + p[2:, 1:-1] + p[1:-1, :-2] + p[1:-1, 2:]
+    dg = p[:-2, :-2] + p[:-2, 2:] + p[2:, :-2] + p[2:, 2:]
+    return 4 / 9 * c + 1 / 9 * ax + 1 / 36 * dg
+
+
+def rg_rl_field(spec: CaseSpec, pred):
+    """Density of a predicted phase field (clipped to [0, 1])."""
     rg, rl, _, _ = spec.coexistence()
-    pole = (1.0 if spec.eos == lbm.LBM_EOS_PR else 4.0) / (PR_AB[1] if spec.eos == lbm.LBM_EOS_PR else CS_AB[1])
-    return np.clip(pred * rl, 0.5 * rg, 0.95 * pole)
+    return rg + np.clip(np.asarray(pred, np.float64), 0.0, 1.0) * (rl - rg)
 
 
-def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000):
-    """Cold versus warm start: per-case steps to the plain equilibrium angle and the
-    wall-clock cost (device step time, plus the network inference for the warm start)."""
+def cap_field(spec: CaseSpec, theta_deg):
+    """Sessile circular cap of contact angle theta on the first fluid row, with the
+    liquid area of the cold start's semicircle (radius R0 = side / 4): radius
+    R = R0 sqrt((pi / 2) / (t - sin t cos t)), centre -R cos t above that row, the
+    cold start's interface width, at the coexistence densities."""
+    rg, rl, _, _ = spec.coexistence()
+    t = np.radians(float(np.clip(theta_deg, 5.0, 175.0)))
+    r0 = 0.25 * spec.side
+    R = r0 * np.sqrt((np.pi / 2) / (t - np.sin(t) * np.cos(t)))
+    return inputs.tanh_drop(spec.side, spec.side, rl, rg, R, spec.side / 2.0, 1.0 - R * np.cos(t))
+
+
+def warm_field(spec: CaseSpec, pred):
+    """Warm start from a predicted phase field: the contact angle of the prediction
+    (Sec. V measure on rho_g + phase (rho_l - rho_g)) sets a clean circular cap of
+    the cold start's liquid area (cap_field), whose liquid excess is then scaled so
+    that the fluid rows hold exactly the cold start's mass (the method conserves
+    mass, so a warm start of another mass relaxes to another equilibrium).  The
+    prediction's pixel noise and its small density offsets are not carried over.
+    If no angle can be read from the prediction, the cold start is returned."""
+    rg, rl, _, _ = spec.coexistence()
+    phi = np.clip(np.asarray(pred, np.float64), 0.0, 1.0)
+    theta = measure_angle(rg + _smooth(phi) * (rl - rg))
+    if not np.isfinite(theta):
+        return initial_density(spec)
+    cap = phase(spec, cap_field(spec, theta))
+    fl = slice(1, spec.side - 1)                     # fluid rows between the walls
+    want = phase(spec, initial_density(spec))[fl].sum()
+    for _ in range(3):                               # scaling then clipping: a few passes
+        have = cap[fl].sum()
+        if have <= 0:
+            break
+        cap[fl] = np.clip(cap[fl] * (want / have), 0.0, 1.0)
+    rho = rg + cap * (rl - rg)
+    rho[0] = rho[1]
+    rho[-1] = rho[-2]
+    return rho
+
+
+def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000, log=None):
+    """Cold versus warm start of one batched sweep: per-case steps to the plain
+    equilibrium angle, and the sweep's device time until its last case is there
+    (for the warm start plus the network inference and the warm-field set-up)."""
     cold0 = [initial_density(s) for s in specs]
-    steps_cold, dt_cold = time_to_angle(specs, cold0, theta_eq, tol_deg, check_every, max_steps)
-    x = np.stack([features(s) for s in specs])
+    steps_cold, dt_cold = time_to_angle(specs, cold0, theta_eq, tol_deg, check_every, max_steps, log=log)
     t0 = time.perf_counter()
+    x = np.stack([features(s) for s in specs])
     pred = net.forward(x)
+    warm0 = [warm_field(s, p) for s, p in zip(specs, pred)]
     t_inf = time.perf_counter() - t0
-    warm0 = [clamp_prediction(s, p) for s, p in zip(specs, pred)]
-    steps_warm, dt_warm = time_to_angle(specs, warm0, theta_eq, tol_deg, check_every, max_steps)
+    steps_warm, dt_warm = time_to_angle(specs, warm0, theta_eq, tol_deg, check_every, max_steps, log=log)
+    done = (steps_cold >= 0).all() and (steps_warm >= 0).all()
+    t_cold = float(steps_cold.max() * dt_cold) if done else float("nan")
+    t_warm = float(steps_warm.max() * dt_warm + t_inf) if done else float("nan")
     return {"steps_cold": steps_cold, "steps_warm": steps_warm, "step_time_cold": dt_cold,
-            "step_time_warm": dt_warm, "inference_s": t_inf, "pred": pred}
+            "step_time_warm": dt_warm, "inference_s": t_inf, "pred": pred,
+            "sweep_s_cold": t_cold, "sweep_s_warm": t_warm,
+            "speedup": t_cold / t_warm if done else float("nan")}
+
+
+# ---------------------------------------------------------------- the whole experiment
+def run_experiment(n_cases=2000, side=256, seed=11, n_val=100, n_test=100, train_steps=(2000, 1000, 500),
+                   lrs=(1e-3, 3e-4, 1e-4), batch=16, calib_side=128, calib_steps=20000, gen_steps=60000,
+                   gen_chunk=500, log=print):
+    """Calibrate, generate n_cases equilibria with the batched solver, train the
+    surrogate on the GPU, and compare cold and warm starts on the held-out test cases."""
+    out = {"n_cases": n_cases, "side": side, "seed": seed}
+    t0 = time.perf_counter()
+    table = calibrate(side=calib_side, steps=calib_steps)
+    out["calibration_s"] = time.perf_counter() - t0
+    out["wetting_range"] = {"%d/%.2f" % k: v for k, v in table.items()}
+    log("calibration: %d grid points in %.1f s" % (len(table), out["calibration_s"]))
+    specs = draw_cases(n_cases, seed, table, side=side)
+    rho_eq, state, steps = [], [], []
+    t0 = time.perf_counter()
+    for c0 in range(0, n_cases, gen_chunk):
+        r, st, stp = generate(specs[c0:c0 + gen_chunk], max_steps=gen_steps, check_every=2000, window=1000,
+                              tol=1e-9)
+        rho_eq += r
+        state += list(st)
+        steps += list(stp)
+        log("generated %d / %d equilibria (%.1f s)" % (len(rho_eq), n_cases, time.perf_counter() - t0))
+    out["generation_s"] = time.perf_counter() - t0
+    state, steps = np.array(state), np.array(steps)
+    theta = np.array([measure_angle(r) if np.isfinite(r).all() else np.nan for r in rho_eq])
+    ok = [i for i in range(n_cases) if state[i] != 2 and np.isfinite(theta[i]) and 35 < theta[i] < 160]
+    out["usable"] = len(ok)
+    out["converged"] = int((state == 1).sum())
+    out["relax_steps_median"] = float(np.median(steps[ok])) if ok else None
+    log("usable equilibria: %d (converged %d)" % (len(ok), out["converged"]))
+    test, val, train = ok[-n_test:], ok[-n_test - n_val:-n_test], ok[:-n_test - n_val]
+    net = lbm.Surrogate(side, max_batch=batch)
+    net.set_params(he_init(seed))
+    x = np.stack([features(specs[i]) for i in train])
+    t = np.stack([target(specs[i], rho_eq[i]) for i in train])
+    net.set_dataset(x, t)
+    del x, t
+    losses = []
+    t0 = time.perf_counter()
+    chunk = 250
+    for k, (n, lr) in enumerate(zip(train_steps, lrs)):
+        for j in range(0, n, chunk):
+            losses.append(net.train(min(chunk, n - j), batch, lr, seed=seed + 1000 * k + j))
+            log("trained %d steps at lr %g: loss %.3e (%.1f s)" % (j + min(chunk, n - j), lr,
+                                                                   float(np.mean(losses[-1][-50:])),
+                                                                   time.perf_counter() - t0))
+    out["training_s"] = time.perf_counter() - t0
+    losses = np.concatenate(losses)
+    out["loss_first"] = float(losses[:20].mean())
+    out["loss_last"] = float(losses[-50:].mean())
+    xv = np.stack([features(specs[i]) for i in val])
+    tv = np.stack([target(specs[i], rho_eq[i]) for i in val])
+    out["val_mse"] = float(np.mean((net.forward(xv) - tv) ** 2))
+    tspecs = [specs[i] for i in test]
+    res = evaluate(net, tspecs, theta[test], tol_deg=0.5, check_every=200, max_steps=gen_steps, log=log)
+    pred_theta = np.array([measure_angle(rg_rl_field(s, p)) for s, p in zip(tspecs, res["pred"])])
+    out.update({k: (v.tolist() if isinstance(v, np.ndarray) else v) for k, v in res.items() if k != "pred"})
+    out["theta_eq"] = theta[test].tolist()
+    out["theta_pred_abs_err_median"] = float(np.nanmedian(np.abs(pred_theta - theta[test])))
+    out["steps_saved_median"] = float(np.median(res["steps_cold"] - res["steps_warm"]))
+    log("sweep to 0.5 deg: cold %.3f s, warm %.3f s (inference %.3f s): %.2fx" %
+        (out["sweep_s_cold"], out["sweep_s_warm"], out["inference_s"], out["speedup"]))
+    net.close()
+    return out
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description="learned warm start: calibration, equilibria, training, evaluation")
+    ap.add_argument("--cases", type=int, default=2000)
+    ap.add_argument("--side", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=11)
+    ap.add_argument("--val", type=int, default=100)
+    ap.add_argument("--test", type=int, default=100)
+    ap.add_argument("--out", default=None, help="write the result as JSON here")
+    a = ap.parse_args()
+    r = run_experiment(a.cases, a.side, a.seed, a.val, a.test, log=lambda m: print(m, flush=True))
+    print(json.dumps(r))
+    if a.out:
+        json.dump(r, open(a.out, "w"), indent=1)

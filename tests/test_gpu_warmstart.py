@@ -27,7 +27,7 @@ def test_warm_start_beats_cold_start(table):
     rho_eq, state, steps = W.generate(specs, max_steps=20000, check_every=1000, window=500, tol=1e-7)
     ok = [i for i in range(len(specs)) if state[i] != 2 and np.isfinite(rho_eq[i]).all()]
     theta = np.array([W.measure_angle(rho_eq[i]) for i in ok])
-    ok = [i for i, t in zip(ok, theta) if 20 < t < 160]
+    ok = [i for i, t in zip(ok, theta) if 35 < t < 160]
     assert len(ok) >= 40
     train, test = ok[:-8], ok[-8:]
     net = lbm.Surrogate(64, max_batch=16)
