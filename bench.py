@@ -118,17 +118,18 @@ def measure_batch(lbm, inputs, steps):
 
 
 def traffic_for(workload: str, shape: int):
-    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE counts, each
-    scaled by what the counter reads for a plain copy of known size, if they were
-    taken on the current kernel source and launch shape (else None)."""
+    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE counts of
+    this launch shape, each scaled by what the counter reads for a plain copy of known
+    size, if they were taken on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("kernel_sha") != kernel_sha() or d.get("shape") != shape:
+    rec = d.get("shapes", {}).get("march" if shape < 0 else str(shape))  # marching: all k together
+    if d.get("kernel_sha") != kernel_sha() or rec is None:
         return None
-    return round((d["fetch_kib_per_dispatch"] * d["fetch_factor"] +
-                  d["write_kib_per_dispatch"] * d["write_factor"]) * 1024.0, 0)
+    return round((rec["fetch_kib_per_dispatch"] * d["fetch_factor"] +
+                  rec["write_kib_per_dispatch"] * d["write_factor"]) * 1024.0, 0)
 
 
 def _with_monitor(p, every):
