@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-bytes", type=int, default=1 << 30,
                     help="size of the plain copy whose bandwidth is reported beside the roofline")
+    ap.add_argument("--warmstart", action="store_true",
+                    help="also run the learned warm-start experiment live (2000 cases at 256^2: "
+                         "equilibria, training, cold vs warm sweep; several minutes)")
     ap.add_argument("--workload", choices=("wetting1024", "spinodal4096"), default="wetting1024",
                     help="main measurement: the 1024^2 FP32 wetting configuration (default) or the "
                          "4096^2 FP32 spinodal lattice (for profiling the HBM-bound size)")
@@ -180,6 +183,31 @@ def measure(lbm, p, rho0, mu_w, fluid_nodes, steps, warmup, bytes_per_lu, worklo
     }
 
 
+WARMSTART_RECORD = os.path.join(ROOT, "profiles", "warmstart_c5.json")
+WARMSTART_KEYS = ("n_cases", "side", "usable", "loss_first", "loss_last", "val_mse", "sweep_s_cold", "sweep_s_warm",
+                  "inference_s", "speedup", "steps_saved_median", "theta_pred_abs_err_median", "training_s",
+                  "generation_s")
+
+
+def warmstart_summary(live: bool):
+    """Time to the plain equilibrium contact angle (within 0.5 deg) of a batched sweep of
+    100 held-out 256^2 cases, cold start vs the surrogate's warm start.  Run live with
+    --warmstart (several minutes); otherwise the record of the last full run, marked as
+    such, with the command that made it."""
+    if live:
+        from paper_1611_00907_amd import warmstart
+        r = warmstart.run_experiment(log=lambda m: print(m, file=sys.stderr, flush=True))
+        out = {k: r[k] for k in WARMSTART_KEYS if k in r}
+        out["source"] = "measured in this run"
+        return out
+    if not os.path.exists(WARMSTART_RECORD):
+        return None
+    r = json.load(open(WARMSTART_RECORD))
+    out = {k: r[k] for k in WARMSTART_KEYS if k in r}
+    out["source"] = "recorded: profiles/warmstart_c5.json (%s)" % r.get("command", "")
+    return out
+
+
 def cpu_baseline(seconds: float):
     """The FP64 oracle on the same 1024^2 wetting workload, timed on the host cores."""
     from oracle import thermo
@@ -266,6 +294,9 @@ def main():
                         "step_frac_of_copy": round(main_res["roofline"]["achieved"] / copy_gbs, 4)},
         "aux": aux,
     }
+    ws = warmstart_summary(args.warmstart)
+    if ws is not None:
+        line["warm_start"] = ws
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

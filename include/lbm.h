@@ -286,6 +286,12 @@ lbm_status lbm_critical_point(int32_t eos, double a, double b, double R, double*
 lbm_status lbm_coexistence(const lbm_params* p, double* rho_g, double* rho_l, double* p_sat,
                            double* mu_sat);
 
+/* Spinodal densities of the fluid in p: dp0/drho < 0 for lo < rho < hi (the
+ * unstable branch of Sec. III's p0).  lo = hi = 0 at or above Tc.  The FP16 and
+ * BF16 deviation storage types evaluate psi'(rho) in FP64 inside this band and in
+ * FP32 elsewhere. */
+lbm_status lbm_spinodal(const lbm_params* p, double* lo, double* hi);
+
 /* Bulk chemical potential psi'(rho) and pressure p0(rho) of the fluid in p at n
  * densities (host, FP64). */
 lbm_status lbm_eos_eval(const lbm_params* p, int64_t n, const double* rho, double* mu_b,

@@ -110,6 +110,14 @@ LatticeArgs lattice_args(const lbm_params& p, const thermo::Fluid& fl, const Lay
     A.inv_tau = 1.0 / p.tau;
     A.kappa = p.kappa;
     A.rho_ref = (p.prec == LBM_F16DEV || p.prec == LBM_BF16DEV) ? p.rho_ref : 0.0;
+    A.sp_lo = A.sp_hi = 0.0;
+    if (p.prec == LBM_F16DEV || p.prec == LBM_BF16DEV) {
+        double lo, hi;
+        if (thermo::spinodal(fl, &lo, &hi)) {
+            A.sp_lo = lo;
+            A.sp_hi = hi;
+        }
+    }
     EosConst& E = A.eos;
     E.RT = fl.R * fl.T;
     E.b = fl.b;
@@ -636,6 +644,18 @@ lbm_status lbm_coexistence(const lbm_params* p, double* rho_g, double* rho_l, do
     if (rho_l) *rho_l = l;
     if (p_sat) *p_sat = ps;
     if (mu_sat) *mu_sat = ms;
+    return LBM_OK;
+}
+
+lbm_status lbm_spinodal(const lbm_params* p, double* lo, double* hi) {
+    if (!p || !lo || !hi) return LBM_EINVAL;
+    lbm_params q = *p;
+    q.nx = q.ny = 3;
+    q.bc_bottom = q.bc_top = LBM_BC_PERIODIC;
+    if (validate(&q) != LBM_OK) return LBM_EINVAL;
+    const thermo::Fluid fl = thermo::make_fluid(p->eos, p->a, p->b, p->R, p->Tr, p->omega);
+    *lo = *hi = 0.0;
+    if (!thermo::spinodal(fl, lo, hi)) *lo = *hi = 0.0;
     return LBM_OK;
 }
 

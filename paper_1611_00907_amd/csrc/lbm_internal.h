@@ -53,6 +53,8 @@ struct LatticeArgs {
     long long plane;      // elements per direction plane = ny * pitch
     double tau, inv_tau, kappa;
     double rho_ref;       // deviation base of the half/bf16 storage
+    double sp_lo, sp_hi;  // spinodal band: the 16-bit storage types evaluate psi' in FP64
+                          // for sp_lo < rho < sp_hi (empty band: both 0)
     EosConst eos;
 };
 

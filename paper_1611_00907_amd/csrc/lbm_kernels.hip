@@ -213,6 +213,17 @@ __device__ __forceinline__ CT mu_bulk(const EosConst& E, CT rho) {
     }
 }
 
+// psi'(rho) of a node: FP64 inside the spinodal band for the 16-bit storage types
+// (where psi' is least well conditioned), the compute type elsewhere.
+template <int EOS, typename ST>
+__device__ __forceinline__ typename Codec<ST>::CT mu_node(const LatticeArgs& A, typename Codec<ST>::CT rho) {
+    using CT = typename Codec<ST>::CT;
+    if constexpr (sizeof(ST) == 2) {
+        if (rho > CT(A.sp_lo) && rho < CT(A.sp_hi)) return CT(mu_bulk<EOS, double>(A.eos, double(rho)));
+    }
+    return mu_bulk<EOS, CT>(A.eos, rho);
+}
+
 // Isotropic Laplacian 6 sum_i w_i (phi_i - phi_0) on an LDS tile.
 template <typename CT, int W>
 __device__ __forceinline__ CT lap9(const CT (*s)[W], int r, int c) {
@@ -354,7 +365,7 @@ __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __rest
         const int y = y0 - 1 + r;
         CT m;
         if (A.bottom == BC_PERIODIC) {
-            m = mu_bulk<EOS, CT>(A.eos, rs[r + 1][c + 1]) - kappa * lap9<CT, RW>(rs, r + 1, c + 1);
+            m = mu_node<EOS, ST>(A, rs[r + 1][c + 1]) - kappa * lap9<CT, RW>(rs, r + 1, c + 1);
         } else if (y <= 0 || y >= A.ny - 1) {
             if (y == 0 || y == A.ny - 1) {
                 const int kind = y == 0 ? A.bottom : A.top;
@@ -362,13 +373,13 @@ __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __rest
                     m = mu_w[(y == 0 ? 0 : A.pitch) + wrap_fast(x0 - 1 + c, A.nx, small_x)];
                 } else {  // neutral wall: the chemical potential of the adjacent fluid node
                     const int rn = y == 0 ? r + 2 : r;
-                    m = mu_bulk<EOS, CT>(A.eos, rs[rn][c + 1]) - kappa * lap9<CT, RW>(rs, rn, c + 1);
+                    m = mu_node<EOS, ST>(A, rs[rn][c + 1]) - kappa * lap9<CT, RW>(rs, rn, c + 1);
                 }
             } else {
                 m = CT(0);  // outside the lattice: never read
             }
         } else {
-            m = mu_bulk<EOS, CT>(A.eos, rs[r + 1][c + 1]) - kappa * lap9<CT, RW>(rs, r + 1, c + 1);
+            m = mu_node<EOS, ST>(A, rs[r + 1][c + 1]) - kappa * lap9<CT, RW>(rs, r + 1, c + 1);
         }
         ms[r][c] = m;
     }
@@ -652,7 +663,7 @@ struct March {
         gy = (c[l] - a[l]) * third + ((ne + nw) - (se + sw)) * twelfth;
     }
     __device__ __forceinline__ CT mu_at(int m) const {
-        return mu_bulk<EOS, CT>(A.eos, rrow(m)[l]) - kappa * lap(rrow(m - 1), rrow(m), rrow(m + 1));
+        return mu_node<EOS, ST>(A, rrow(m)[l]) - kappa * lap(rrow(m - 1), rrow(m), rrow(m + 1));
     }
     // Collision of row c with the distributions g, stored to f*(t) at store offset v.
     __device__ __forceinline__ void collide_row(int c, const CT g[9], int v) const {

@@ -191,32 +191,34 @@ double branch_rho(const Fluid& f, double p, double lo, double hi) {
 }
 }  // namespace
 
-bool coexistence(const Fluid& f, double* rho_g, double* rho_l, double* p_sat, double* mu_sat) {
+bool spinodal(const Fluid& f, double* lo, double* hi) {
     if (!(f.T < f.Tc)) return false;
     const double pole = rho_pole(f.eos, f.b);
-    // spinodal: dp0 > 0 on the gas side, < 0 between, > 0 on the liquid side
-    const double rc = f.rho_c;
-    double s1 = bisect_dp0(f, 1e-12 * pole, rc);
-    double s2 = bisect_dp0(f, rc, pole * (1.0 - 1e-12));
-    // scan to make sure the brackets straddle the sign changes (rho_c of alpha = 1 can
-    // differ from the spinodal centre for PR/RKS away from Tc)
-    {
-        const int n = 4000;
-        std::vector<double> xs(n), ds(n);
-        for (int i = 0; i < n; ++i) {
-            xs[i] = pole * (1e-6 + (0.9999 - 1e-6) * i / (n - 1));
-            ds[i] = dp0(f, xs[i]);
-        }
-        int first = -1, last = -1;
-        for (int i = 0; i + 1 < n; ++i)
-            if ((ds[i] > 0) != (ds[i + 1] > 0)) {
-                if (first < 0) first = i;
-                last = i;
-            }
-        if (first < 0 || first == last) return false;
-        s1 = bisect_dp0(f, xs[first], xs[first + 1]);
-        s2 = bisect_dp0(f, xs[last], xs[last + 1]);
+    // dp0 > 0 on the gas side, < 0 between, > 0 on the liquid side; a scan finds the
+    // two sign changes (rho_c of alpha = 1 can differ from the spinodal centre for
+    // PR/RKS away from Tc), bisection refines them
+    const int n = 4000;
+    std::vector<double> xs(n), ds(n);
+    for (int i = 0; i < n; ++i) {
+        xs[i] = pole * (1e-6 + (0.9999 - 1e-6) * i / (n - 1));
+        ds[i] = dp0(f, xs[i]);
     }
+    int first = -1, last = -1;
+    for (int i = 0; i + 1 < n; ++i)
+        if ((ds[i] > 0) != (ds[i + 1] > 0)) {
+            if (first < 0) first = i;
+            last = i;
+        }
+    if (first < 0 || first == last) return false;
+    *lo = bisect_dp0(f, xs[first], xs[first + 1]);
+    *hi = bisect_dp0(f, xs[last], xs[last + 1]);
+    return true;
+}
+
+bool coexistence(const Fluid& f, double* rho_g, double* rho_l, double* p_sat, double* mu_sat) {
+    double s1, s2;
+    if (!spinodal(f, &s1, &s2)) return false;
+    const double pole = rho_pole(f.eos, f.b);
     const double pmax = p0(f, s1), pmin = p0(f, s2);
     double plo = pmin > 0 ? pmin : 0.0, phi = pmax;
     auto dmu = [&](double p, double* rg, double* rl) {

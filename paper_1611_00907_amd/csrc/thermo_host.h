@@ -21,6 +21,8 @@ Fluid make_fluid(int eos, double a, double b, double R, double Tr, double omega)
 double p0(const Fluid& f, double rho);
 double dp0(const Fluid& f, double rho);
 double mu_b(const Fluid& f, double rho);
+// Spinodal densities: dp0/drho < 0 for lo < rho < hi; false at or above Tc.
+bool spinodal(const Fluid& f, double* lo, double* hi);
 bool coexistence(const Fluid& f, double* rho_g, double* rho_l, double* p_sat, double* mu_sat);
 int contact_angle(const double* rho, int nx, int ny, int base_row, double surface_y, double rho_mid,
                   double* theta, double* L, double* H);

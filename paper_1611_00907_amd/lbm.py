@@ -39,7 +39,7 @@ EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lb
             "sur_set_dataset", "sur_train", "sur_destroy",
             "lbm_get_monitors", "lbm_monitor_step", "lbm_get_state", "lbm_set_state",
             "lbm_get_temperature", "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_critical_point",
-            "lbm_coexistence", "lbm_eos_eval", "lbm_contact_angle"]
+            "lbm_coexistence", "lbm_spinodal", "lbm_eos_eval", "lbm_contact_angle"]
 
 
 class LbmParams(C.Structure):
@@ -139,6 +139,7 @@ def load_library():
     lib.sur_destroy.restype = None
     lib.lbm_critical_point.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, dp, dp, dp]
     lib.lbm_coexistence.argtypes = [P, dp, dp, dp, dp]
+    lib.lbm_spinodal.argtypes = [P, dp, dp]
     lib.lbm_eos_eval.argtypes = [P, C.c_int64, vp, vp, vp]
     lib.lbm_contact_angle.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                       dp, dp, dp]
@@ -188,6 +189,14 @@ def lbm_coexistence(p: LbmParams):
     out = [C.c_double() for _ in range(4)]
     _check(lib.lbm_coexistence(C.byref(p), *[C.byref(o) for o in out]), "lbm_coexistence")
     return tuple(o.value for o in out)
+
+
+def lbm_spinodal(p: LbmParams):
+    """(lo, hi): dp0/drho < 0 for lo < rho < hi; (0, 0) at or above Tc."""
+    lib = load_library()
+    lo, hi = C.c_double(), C.c_double()
+    _check(lib.lbm_spinodal(C.byref(p), C.byref(lo), C.byref(hi)), "lbm_spinodal")
+    return lo.value, hi.value
 
 
 def lbm_eos_eval(p: LbmParams, rho):

@@ -128,15 +128,24 @@ def draw_cases(n, seed, table, side=256, Tr_range=(0.6, 0.9)):
     return out
 
 
-def generate(specs, max_steps=60000, check_every=2000, window=1000, tol=1e-9):
-    """Relaxes every case with the batched solver; returns (rho_eq list, state array, steps array)."""
+def generate(specs, max_steps=60000, check_every=2000, window=1000, tol=1e-9, confirm_steps=0):
+    """Relaxes every case with the batched solver; returns (rho_eq list, state array,
+    steps array, angle drift).  With confirm_steps > 0 the cases run that many more
+    steps and the drift is the change of their contact angle over them (an
+    equilibrium angle that still moves is not one)."""
     b = lbm.Batch([s.params() for s in specs], [initial_density(s) for s in specs],
                   mu_w_bottom=[s.mu_w for s in specs])
     b.run(max_steps, check_every=check_every, window=window, tol=tol)
+    drift = np.zeros(len(specs))
+    if confirm_steps > 0:
+        th1 = np.array([measure_angle(b.rho(i)) for i in range(len(specs))])
+        b.step(confirm_steps)
+        th2 = np.array([measure_angle(b.rho(i)) for i in range(len(specs))])
+        drift = np.abs(th2 - th1)
     st = b.status()
     rho = [b.rho(i) for i in range(len(specs))]
     b.close()
-    return rho, st["state"], st["steps"]
+    return rho, st["state"], st["steps"], drift
 
 
 # ---------------------------------------------------------------- 3. features
@@ -214,49 +223,73 @@ def _smooth(a):
     return 4 / 9 * c + 1 / 9 * ax + 1 / 36 * dg
 
 
-def rg_rl_field(spec: CaseSpec, pred):
-    """Density of a predicted phase field (clipped to [0, 1])."""
-    rg, rl, _, _ = spec.coexistence()
-    return rg + np.clip(np.asarray(pred, np.float64), 0.0, 1.0) * (rl - rg)
+def bulk_phases(phi):
+    """Liquid and vapour phase levels of a phase field: medians of the nodes whose
+    whole 5 x 5 neighbourhood lies on one side of 1/2 (periodic in x)."""
+    hi = phi > 0.5
+    all_hi = hi.copy()
+    all_lo = ~hi
+    for dy in (-2, -1, 0, 1, 2):
+        for dx in (-2, -1, 0, 1, 2):
+            s = np.roll(np.roll(hi, dy, 0), dx, 1)
+            all_hi &= s
+            all_lo &= ~s
+    lo = float(np.median(phi[all_lo])) if all_lo.any() else 0.0
+    hi_v = float(np.median(phi[all_hi])) if all_hi.any() else 1.0
+    return hi_v, lo
 
 
-def cap_field(spec: CaseSpec, theta_deg):
-    """Sessile circular cap of contact angle theta on the first fluid row, with the
-    liquid area of the cold start's semicircle (radius R0 = side / 4): radius
-    R = R0 sqrt((pi / 2) / (t - sin t cos t)), centre -R cos t above that row, the
-    cold start's interface width, at the coexistence densities."""
-    rg, rl, _, _ = spec.coexistence()
-    t = np.radians(float(np.clip(theta_deg, 5.0, 175.0)))
-    r0 = 0.25 * spec.side
-    R = r0 * np.sqrt((np.pi / 2) / (t - np.sin(t) * np.cos(t)))
-    return inputs.tanh_drop(spec.side, spec.side, rl, rg, R, spec.side / 2.0, 1.0 - R * np.cos(t))
-
-
-def warm_field(spec: CaseSpec, pred):
-    """Warm start from a predicted phase field: the contact angle of the prediction
-    (Sec. V measure on rho_g + phase (rho_l - rho_g)) sets a clean circular cap of
-    the cold start's liquid area (cap_field), whose liquid excess is then scaled so
-    that the fluid rows hold exactly the cold start's mass (the method conserves
-    mass, so a warm start of another mass relaxes to another equilibrium).  The
-    prediction's pixel noise and its small density offsets are not carried over.
-    If no angle can be read from the prediction, the cold start is returned."""
-    rg, rl, _, _ = spec.coexistence()
-    phi = np.clip(np.asarray(pred, np.float64), 0.0, 1.0)
-    theta = measure_angle(rg + _smooth(phi) * (rl - rg))
-    if not np.isfinite(theta):
-        return initial_density(spec)
-    cap = phase(spec, cap_field(spec, theta))
+def cap_field(spec: CaseSpec, theta_deg, rho_l=None, rho_g=None):
+    """Sessile circular cap of contact angle theta on the first fluid row at the
+    bulk densities rho_l, rho_g (default: the coexistence values), holding the cold
+    start's mass: liquid area A = (M - rho_g N) / (rho_l - rho_g) over the N fluid
+    nodes, radius R = sqrt(A / (t - sin t cos t)), centre -R cos t above that row,
+    the cold start's interface width; the liquid excess is then scaled so that the
+    fluid rows hold exactly the mass M."""
+    rg0, rl0, _, _ = spec.coexistence()
+    rl = rl0 if rho_l is None else float(rho_l)
+    rg = rg0 if rho_g is None else float(rho_g)
+    cold = initial_density(spec)
     fl = slice(1, spec.side - 1)                     # fluid rows between the walls
-    want = phase(spec, initial_density(spec))[fl].sum()
-    for _ in range(3):                               # scaling then clipping: a few passes
-        have = cap[fl].sum()
-        if have <= 0:
-            break
-        cap[fl] = np.clip(cap[fl] * (want / have), 0.0, 1.0)
-    rho = rg + cap * (rl - rg)
+    M, N = float(cold[fl].sum()), cold[fl].size
+    A = max((M - rg * N) / (rl - rg), 1.0)
+    t = np.radians(float(np.clip(theta_deg, 5.0, 175.0)))
+    R = np.sqrt(A / (t - np.sin(t) * np.cos(t)))
+    rho = inputs.tanh_drop(spec.side, spec.side, rl, rg, R, spec.side / 2.0, 1.0 - R * np.cos(t))
+    excess = rho[fl] - rg
+    if excess.sum() > 0:
+        rho[fl] = rg + excess * ((M - rg * N) / excess.sum())
     rho[0] = rho[1]
     rho[-1] = rho[-2]
     return rho
+
+
+def read_prediction(spec: CaseSpec, pred):
+    """Contact angle and bulk densities of a predicted phase field (clipped to
+    [-0.2, 1.2], which keeps the few-percent offsets of the equilibrium phases, and
+    smoothed once): the angle by the Sec. V measure, the bulk phases by
+    bulk_phases.  NaN angle if none can be read."""
+    rg, rl, _, _ = spec.coexistence()
+    phi = _smooth(np.clip(np.asarray(pred, np.float64), -0.2, 1.2))
+    theta = measure_angle(rg + phi * (rl - rg))
+    ph_l, ph_g = bulk_phases(phi)
+    return theta, rg + ph_l * (rl - rg), rg + ph_g * (rl - rg)
+
+
+def warm_field(spec: CaseSpec, pred):
+    """Warm start from a predicted phase field: a clean circular cap with the
+    prediction's contact angle and bulk densities and the cold start's mass
+    (cap_field).  The prediction's pixel noise is not carried over; the mass is
+    the cold start's because the method conserves it (a start of another mass
+    relaxes to another equilibrium); the bulk densities are the prediction's
+    because the equilibrium ones differ from Maxwell's by a few percent (the
+    discrete equilibrium and the Laplace pressure), and moving that mass between
+    the phases is the slowest part of the relaxation.  If no angle can be read
+    from the prediction, the cold start is returned."""
+    theta, rl, rg = read_prediction(spec, pred)
+    if not np.isfinite(theta) or not rl > rg:
+        return initial_density(spec)
+    return cap_field(spec, theta, rl, rg)
 
 
 def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000, log=None):
@@ -281,9 +314,9 @@ def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000
 
 
 # ---------------------------------------------------------------- the whole experiment
-def run_experiment(n_cases=2000, side=256, seed=11, n_val=100, n_test=100, train_steps=(2000, 1000, 500),
-                   lrs=(1e-3, 3e-4, 1e-4), batch=16, calib_side=128, calib_steps=20000, gen_steps=60000,
-                   gen_chunk=500, log=print):
+def run_experiment(n_cases=2000, side=256, seed=11, n_val=100, n_test=100, train_steps=(4000, 3000, 2000, 1000),
+                   lrs=(1e-3, 5e-4, 2e-4, 1e-4), batch=16, calib_side=128, calib_steps=20000, gen_steps=80000,
+                   confirm_steps=20000, gen_chunk=500, log=print):
     """Calibrate, generate n_cases equilibria with the batched solver, train the
     surrogate on the GPU, and compare cold and warm starts on the held-out test cases."""
     out = {"n_cases": n_cases, "side": side, "seed": seed}
@@ -293,23 +326,29 @@ def run_experiment(n_cases=2000, side=256, seed=11, n_val=100, n_test=100, train
     out["wetting_range"] = {"%d/%.2f" % k: v for k, v in table.items()}
     log("calibration: %d grid points in %.1f s" % (len(table), out["calibration_s"]))
     specs = draw_cases(n_cases, seed, table, side=side)
-    rho_eq, state, steps = [], [], []
+    rho_eq, state, steps, drift = [], [], [], []
     t0 = time.perf_counter()
     for c0 in range(0, n_cases, gen_chunk):
-        r, st, stp = generate(specs[c0:c0 + gen_chunk], max_steps=gen_steps, check_every=2000, window=1000,
-                              tol=1e-9)
+        r, st, stp, dr = generate(specs[c0:c0 + gen_chunk], max_steps=gen_steps, check_every=2000, window=1000,
+                                  tol=1e-9, confirm_steps=confirm_steps)
         rho_eq += r
         state += list(st)
         steps += list(stp)
+        drift += list(dr)
         log("generated %d / %d equilibria (%.1f s)" % (len(rho_eq), n_cases, time.perf_counter() - t0))
     out["generation_s"] = time.perf_counter() - t0
-    state, steps = np.array(state), np.array(steps)
+    state, steps, drift = np.array(state), np.array(steps), np.array(drift)
     theta = np.array([measure_angle(r) if np.isfinite(r).all() else np.nan for r in rho_eq])
-    ok = [i for i in range(n_cases) if state[i] != 2 and np.isfinite(theta[i]) and 35 < theta[i] < 160]
+    # usable: not diverged, a drop (not a film) between 35 and 160 degrees whose angle
+    # moved less than 0.1 degree over the last confirm_steps steps
+    ok = [i for i in range(n_cases) if state[i] != 2 and np.isfinite(theta[i]) and 35 < theta[i] < 160
+          and drift[i] < 0.1]
+    out["unsettled"] = int(np.sum(np.isfinite(drift) & (drift >= 0.1)))
     out["usable"] = len(ok)
     out["converged"] = int((state == 1).sum())
     out["relax_steps_median"] = float(np.median(steps[ok])) if ok else None
-    log("usable equilibria: %d (converged %d)" % (len(ok), out["converged"]))
+    log("usable equilibria: %d (converged %d, angle still moving %d)" % (len(ok), out["converged"],
+                                                                          out["unsettled"]))
     test, val, train = ok[-n_test:], ok[-n_test - n_val:-n_test], ok[:-n_test - n_val]
     net = lbm.Surrogate(side, max_batch=batch)
     net.set_params(he_init(seed))
@@ -334,10 +373,12 @@ def run_experiment(n_cases=2000, side=256, seed=11, n_val=100, n_test=100, train
     tv = np.stack([target(specs[i], rho_eq[i]) for i in val])
     out["val_mse"] = float(np.mean((net.forward(xv) - tv) ** 2))
     tspecs = [specs[i] for i in test]
-    res = evaluate(net, tspecs, theta[test], tol_deg=0.5, check_every=200, max_steps=gen_steps, log=log)
-    pred_theta = np.array([measure_angle(rg_rl_field(s, p)) for s, p in zip(tspecs, res["pred"])])
+    res = evaluate(net, tspecs, theta[test], tol_deg=0.5, check_every=200, max_steps=gen_steps + confirm_steps,
+                   log=log)
+    pred_theta = np.array([read_prediction(s, p)[0] for s, p in zip(tspecs, res["pred"])])
     out.update({k: (v.tolist() if isinstance(v, np.ndarray) else v) for k, v in res.items() if k != "pred"})
     out["theta_eq"] = theta[test].tolist()
+    out["theta_pred"] = pred_theta.tolist()
     out["theta_pred_abs_err_median"] = float(np.nanmedian(np.abs(pred_theta - theta[test])))
     out["steps_saved_median"] = float(np.median(res["steps_cold"] - res["steps_warm"]))
     log("sweep to 0.5 deg: cold %.3f s, warm %.3f s (inference %.3f s): %.2fx" %

@@ -24,7 +24,7 @@ def test_calibration_orders_wetting_range(table):
 
 def test_warm_start_beats_cold_start(table):
     specs = W.draw_cases(72, seed=5, table=table, side=64, Tr_range=(0.7, 0.9))
-    rho_eq, state, steps = W.generate(specs, max_steps=20000, check_every=1000, window=500, tol=1e-7)
+    rho_eq, state, steps, _ = W.generate(specs, max_steps=20000, check_every=1000, window=500, tol=1e-7)
     ok = [i for i in range(len(specs)) if state[i] != 2 and np.isfinite(rho_eq[i]).all()]
     theta = np.array([W.measure_angle(rho_eq[i]) for i in ok])
     ok = [i for i, t in zip(ok, theta) if 35 < t < 160]

@@ -114,6 +114,19 @@ def test_coexistence_above_critical(lbm):
     assert e.value.status == lbm.LBM_EDOMAIN
 
 
+@pytest.mark.parametrize("eos,Tr,om", [(0, 0.85, 0.0), (1, 0.7, 0.0), (2, 0.8, 0.344), (3, 0.8, 0.344),
+                                       (4, 0.75, 0.0)])
+def test_spinodal_matches_oracle(lbm, eos, Tr, om):
+    """The band where the 16-bit storage types evaluate psi' in FP64."""
+    a, b = {0: (9 / 49, 2 / 21), 1: (1.0, 4.0)}.get(eos, (2 / 49, 2 / 21))
+    p = lbm.make_params(8, 8, eos, a, b, Tr, 1.3, 0.01, omega=om)
+    lo, hi = lbm.lbm_spinodal(p)
+    olo, ohi = thermo.spinodal(thermo.fluid_at(eos, a, b, 1.0, Tr, om))
+    assert abs(lo - olo) < 1e-9 * olo and abs(hi - ohi) < 1e-9 * ohi
+    above = lbm.make_params(8, 8, eos, a, b, 1.05, 1.3, 0.01, omega=om)
+    assert lbm.lbm_spinodal(above) == (0.0, 0.0)
+
+
 def test_eos_eval_matches_oracle(lbm):
     p = lbm.make_params(8, 8, 2, 2 / 49, 2 / 21, 0.8, 1.3, 0.01, omega=0.344)
     fl = thermo.fluid_at(2, 2 / 49, 2 / 21, 1.0, 0.8, 0.344)
