@@ -39,6 +39,7 @@ class CaseSpec:
     frac: float        # position of the wall mu inside the wetting range (0 -> 30 deg, 1 -> 150 deg)
     mu_w: float
     side: int
+    theta0: float = 90.0  # contact angle the calibration sweeps give for this case
 
     def params(self, prec=lbm.LBM_F32):
         a, b = CS_AB if self.eos == lbm.LBM_EOS_CS else PR_AB
@@ -78,11 +79,21 @@ def measure_angle(rho):
 
 
 # ---------------------------------------------------------------- 1. calibration
+class Calibration(dict):
+    """{(eos, Tr): (mu_30, mu_150)}, the wetting range at each grid point, with the
+    sweeps it came from in .sweeps: {(eos, Tr): (mu_w values, contact angles)}."""
+
+    def __init__(self):
+        super().__init__()
+        self.sweeps = {}
+
+
 def calibrate(Tr_grid=(0.6, 0.7, 0.8, 0.9), side=128, steps=20000, offsets=None):
-    """{(eos, Tr): (mu_30, mu_150)} from sweeps of mu_w - mu_sat at each grid point."""
+    """Sweeps of mu_w - mu_sat at each grid point; the wall mu giving 30 and 150
+    degrees by monotone interpolation of the measured angles."""
     if offsets is None:
         offsets = {lbm.LBM_EOS_PR: np.linspace(-0.3, 0.3, 13), lbm.LBM_EOS_CS: np.linspace(-0.06, 0.06, 13)}
-    table = {}
+    table = Calibration()
     for eos in (lbm.LBM_EOS_CS, lbm.LBM_EOS_PR):
         specs, mu_sats = [], []
         for Tr in Tr_grid:
@@ -106,6 +117,7 @@ def calibrate(Tr_grid=(0.6, 0.7, 0.8, 0.9), side=128, steps=20000, offsets=None)
             # monotone interpolation of mu at 30 and 150 degrees
             tt, mm = np.maximum.accumulate(t[ok]), mus[ok]
             table[(eos, Tr)] = (float(np.interp(30.0, tt, mm)), float(np.interp(150.0, tt, mm)))
+            table.sweeps[(eos, Tr)] = (mm, tt)
     return table
 
 
@@ -116,6 +128,17 @@ def wetting_range(table, eos, Tr):
     return float(lo), float(hi)
 
 
+def theta_guess(table, eos, Tr, mu_w):
+    """Contact angle of (eos, Tr, mu_w) from the calibration sweeps: the angle at
+    mu_w of each grid temperature's sweep, interpolated linearly in Tr."""
+    sw = getattr(table, "sweeps", {})
+    grid = sorted(T for (e, T) in sw if e == eos)
+    if not grid:
+        return 90.0
+    per_T = [float(np.interp(mu_w, *sw[(eos, T)])) for T in grid]
+    return float(np.interp(Tr, grid, per_T))
+
+
 # ---------------------------------------------------------------- 2. cases and equilibria
 def draw_cases(n, seed, table, side=256, Tr_range=(0.6, 0.9)):
     u = inputs.uniform(seed, 3 * n).reshape(n, 3)
@@ -124,7 +147,8 @@ def draw_cases(n, seed, table, side=256, Tr_range=(0.6, 0.9)):
         eos = lbm.LBM_EOS_CS if u[k, 0] < 0.5 else lbm.LBM_EOS_PR
         Tr = Tr_range[0] + (Tr_range[1] - Tr_range[0]) * u[k, 1]
         lo, hi = wetting_range(table, eos, Tr)
-        out.append(CaseSpec(eos, Tr, float(u[k, 2]), lo + (hi - lo) * float(u[k, 2]), side))
+        mu_w = lo + (hi - lo) * float(u[k, 2])
+        out.append(CaseSpec(eos, Tr, float(u[k, 2]), mu_w, side, theta_guess(table, eos, Tr, mu_w)))
     return out
 
 
@@ -150,18 +174,29 @@ def generate(specs, max_steps=60000, check_every=2000, window=1000, tol=1e-9, co
 
 # ---------------------------------------------------------------- 3. features
 def phase(spec: CaseSpec, rho):
-    """(rho - rho_g) / (rho_l - rho_g): 0 in the vapour, 1 in the liquid at coexistence."""
+    """ln(rho / rho_g) / ln(rho_l / rho_g): 0 in the vapour, 1 in the liquid at
+    coexistence.  Logarithmic, so that a vapour density several times Maxwell's (the
+    discrete equilibrium of a thin interface next to a small drop) is as visible to
+    the network as a few percent on the liquid."""
     rg, rl, _, _ = spec.coexistence()
-    return (np.asarray(rho, np.float64) - rg) / (rl - rg)
+    return np.log(np.maximum(np.asarray(rho, np.float64), 1e-300) / rg) / np.log(rl / rg)
+
+
+def density(spec: CaseSpec, phi):
+    """Inverse of phase."""
+    rg, rl, _, _ = spec.coexistence()
+    return rg * np.exp(np.asarray(phi, np.float64) * np.log(rl / rg))
 
 
 def features(spec: CaseSpec):
     """Network input [4][side][side] for a case: solid mask, phase of the initial
-    density, T/Tc, and the wall chemical potential's place in the wetting range."""
+    density (the cap of the calibrated angle theta0 at the cold start's mass; the
+    semicircle when theta0 = 90), T/Tc, and the wall chemical potential's place in
+    the wetting range."""
     x = np.zeros((4, spec.side, spec.side), np.float32)
     x[0, 0, :] = 1.0
     x[0, -1, :] = 1.0
-    x[1] = phase(spec, initial_density(spec))
+    x[1] = phase(spec, cap_field(spec, spec.theta0))
     x[2] = spec.Tr
     x[3] = spec.frac
     return x
@@ -252,13 +287,17 @@ def cap_field(spec: CaseSpec, theta_deg, rho_l=None, rho_g=None):
     cold = initial_density(spec)
     fl = slice(1, spec.side - 1)                     # fluid rows between the walls
     M, N = float(cold[fl].sum()), cold[fl].size
-    A = max((M - rg * N) / (rl - rg), 1.0)
+    if not M - rg * N > 0.05 * (M - rg0 * N):
+        # the vapour alone would hold (nearly) all the mass: no drop at these densities
+        if rho_l is None and rho_g is None:
+            return cold
+        return cap_field(spec, theta_deg)
+    A = (M - rg * N) / (rl - rg)
     t = np.radians(float(np.clip(theta_deg, 5.0, 175.0)))
     R = np.sqrt(A / (t - np.sin(t) * np.cos(t)))
     rho = inputs.tanh_drop(spec.side, spec.side, rl, rg, R, spec.side / 2.0, 1.0 - R * np.cos(t))
     excess = rho[fl] - rg
-    if excess.sum() > 0:
-        rho[fl] = rg + excess * ((M - rg * N) / excess.sum())
+    rho[fl] = rg + excess * ((M - rg * N) / excess.sum())
     rho[0] = rho[1]
     rho[-1] = rho[-2]
     return rho
@@ -266,14 +305,13 @@ def cap_field(spec: CaseSpec, theta_deg, rho_l=None, rho_g=None):
 
 def read_prediction(spec: CaseSpec, pred):
     """Contact angle and bulk densities of a predicted phase field (clipped to
-    [-0.2, 1.2], which keeps the few-percent offsets of the equilibrium phases, and
-    smoothed once): the angle by the Sec. V measure, the bulk phases by
-    bulk_phases.  NaN angle if none can be read."""
-    rg, rl, _, _ = spec.coexistence()
-    phi = _smooth(np.clip(np.asarray(pred, np.float64), -0.2, 1.2))
-    theta = measure_angle(rg + phi * (rl - rg))
+    [-0.5, 1.5], which keeps the offsets of the equilibrium phases, and smoothed
+    once): the angle by the Sec. V measure, the bulk phases by bulk_phases.  NaN
+    angle if none can be read."""
+    phi = _smooth(np.clip(np.asarray(pred, np.float64), -0.5, 1.5))
+    theta = measure_angle(density(spec, phi))
     ph_l, ph_g = bulk_phases(phi)
-    return theta, rg + ph_l * (rl - rg), rg + ph_g * (rl - rg)
+    return theta, float(density(spec, ph_l)), float(density(spec, ph_g))
 
 
 def warm_field(spec: CaseSpec, pred):
@@ -282,17 +320,22 @@ def warm_field(spec: CaseSpec, pred):
     (cap_field).  The prediction's pixel noise is not carried over; the mass is
     the cold start's because the method conserves it (a start of another mass
     relaxes to another equilibrium); the bulk densities are the prediction's
-    because the equilibrium ones differ from Maxwell's by a few percent (the
-    discrete equilibrium and the Laplace pressure), and moving that mass between
-    the phases is the slowest part of the relaxation.  If no angle can be read
+    because the equilibrium ones differ from Maxwell's (the liquid by up to 2 %,
+    the vapour by up to several times next to thin interfaces), and moving that
+    mass between the phases is the slowest part of the relaxation.  If no angle can be read
     from the prediction, the cold start is returned."""
     theta, rl, rg = read_prediction(spec, pred)
     if not np.isfinite(theta) or not rl > rg:
         return initial_density(spec)
+    # plausibility: the discrete equilibrium's liquid sits within a few percent of
+    # Maxwell's, its vapour within a factor of ten (thin interfaces, small drops)
+    rg0, rl0, _, _ = spec.coexistence()
+    rl = float(np.clip(rl, 0.9 * rl0, 1.1 * rl0))
+    rg = float(np.clip(rg, 0.1 * rg0, 10.0 * rg0))
     return cap_field(spec, theta, rl, rg)
 
 
-def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000, log=None):
+def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000, log=None, calibration_arm=False):
     """Cold versus warm start of one batched sweep: per-case steps to the plain
     equilibrium angle, and the sweep's device time until its last case is there
     (for the warm start plus the network inference and the warm-field set-up)."""
@@ -307,21 +350,31 @@ def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000
     done = (steps_cold >= 0).all() and (steps_warm >= 0).all()
     t_cold = float(steps_cold.max() * dt_cold) if done else float("nan")
     t_warm = float(steps_warm.max() * dt_warm + t_inf) if done else float("nan")
-    return {"steps_cold": steps_cold, "steps_warm": steps_warm, "step_time_cold": dt_cold,
-            "step_time_warm": dt_warm, "inference_s": t_inf, "pred": pred,
-            "sweep_s_cold": t_cold, "sweep_s_warm": t_warm,
-            "speedup": t_cold / t_warm if done else float("nan")}
+    out = {"steps_cold": steps_cold, "steps_warm": steps_warm, "step_time_cold": dt_cold,
+           "step_time_warm": dt_warm, "inference_s": t_inf, "pred": pred,
+           "sweep_s_cold": t_cold, "sweep_s_warm": t_warm,
+           "speedup": t_cold / t_warm if done else float("nan")}
+    if calibration_arm:
+        # the same sweep started from the calibration's angle alone (no network):
+        # what the trained network adds over the method without it
+        cal0 = [cap_field(s, s.theta0) for s in specs]
+        steps_cal, dt_cal = time_to_angle(specs, cal0, theta_eq, tol_deg, check_every, max_steps, log=log)
+        ok = (steps_cold >= 0).all() and (steps_cal >= 0).all()
+        out["steps_calibration_only"] = steps_cal
+        out["sweep_s_calibration_only"] = float(steps_cal.max() * dt_cal) if ok else float("nan")
+        out["speedup_calibration_only"] = t_cold / out["sweep_s_calibration_only"] if ok else float("nan")
+    return out
 
 
 # ---------------------------------------------------------------- the whole experiment
 def run_experiment(n_cases=2000, side=256, seed=11, n_val=100, n_test=100, train_steps=(4000, 3000, 2000, 1000),
-                   lrs=(1e-3, 5e-4, 2e-4, 1e-4), batch=16, calib_side=128, calib_steps=20000, gen_steps=80000,
-                   confirm_steps=20000, gen_chunk=500, log=print):
+                   lrs=(1e-3, 5e-4, 2e-4, 1e-4), batch=16, calib_side=256, calib_steps=30000, gen_steps=80000,
+                   confirm_steps=20000, gen_chunk=500, log=print, debug_path=None):
     """Calibrate, generate n_cases equilibria with the batched solver, train the
     surrogate on the GPU, and compare cold and warm starts on the held-out test cases."""
     out = {"n_cases": n_cases, "side": side, "seed": seed}
     t0 = time.perf_counter()
-    table = calibrate(side=calib_side, steps=calib_steps)
+    table = calibrate(Tr_grid=(0.6, 0.65, 0.7, 0.75, 0.8, 0.85, 0.9), side=calib_side, steps=calib_steps)
     out["calibration_s"] = time.perf_counter() - t0
     out["wetting_range"] = {"%d/%.2f" % k: v for k, v in table.items()}
     log("calibration: %d grid points in %.1f s" % (len(table), out["calibration_s"]))
@@ -373,16 +426,25 @@ def run_experiment(n_cases=2000, side=256, seed=11, n_val=100, n_test=100, train
     tv = np.stack([target(specs[i], rho_eq[i]) for i in val])
     out["val_mse"] = float(np.mean((net.forward(xv) - tv) ** 2))
     tspecs = [specs[i] for i in test]
-    res = evaluate(net, tspecs, theta[test], tol_deg=0.5, check_every=200, max_steps=gen_steps + confirm_steps,
-                   log=log)
+    res = evaluate(net, tspecs, theta[test], tol_deg=0.5, check_every=200, max_steps=40000, log=log,
+                   calibration_arm=True)
+    out["theta_calibration_abs_err_median"] = float(np.median(np.abs([s.theta0 for s in tspecs] - theta[test])))
     pred_theta = np.array([read_prediction(s, p)[0] for s, p in zip(tspecs, res["pred"])])
+    if debug_path:
+        never = [k for k in range(len(tspecs)) if res["steps_warm"][k] < 0]
+        np.savez_compressed(debug_path, never=np.array(never), pred=res["pred"][never] if never else np.zeros(0),
+                            eq=np.array([rho_eq[test[k]] for k in never]) if never else np.zeros(0),
+                            warm=np.array([warm_field(tspecs[k], res["pred"][k]) for k in never]) if never else
+                            np.zeros(0), eos=np.array([tspecs[k].eos for k in never]),
+                            Tr=np.array([tspecs[k].Tr for k in never]), mu_w=np.array([tspecs[k].mu_w for k in never]))
     out.update({k: (v.tolist() if isinstance(v, np.ndarray) else v) for k, v in res.items() if k != "pred"})
     out["theta_eq"] = theta[test].tolist()
     out["theta_pred"] = pred_theta.tolist()
     out["theta_pred_abs_err_median"] = float(np.nanmedian(np.abs(pred_theta - theta[test])))
     out["steps_saved_median"] = float(np.median(res["steps_cold"] - res["steps_warm"]))
-    log("sweep to 0.5 deg: cold %.3f s, warm %.3f s (inference %.3f s): %.2fx" %
-        (out["sweep_s_cold"], out["sweep_s_warm"], out["inference_s"], out["speedup"]))
+    log("sweep to 0.5 deg: cold %.3f s, warm %.3f s (inference %.3f s): %.2fx; calibration angle alone %.2fx" %
+        (out["sweep_s_cold"], out["sweep_s_warm"], out["inference_s"], out["speedup"],
+         out.get("speedup_calibration_only", float("nan"))))
     net.close()
     return out
 
@@ -398,8 +460,10 @@ if __name__ == "__main__":
     ap.add_argument("--val", type=int, default=100)
     ap.add_argument("--test", type=int, default=100)
     ap.add_argument("--out", default=None, help="write the result as JSON here")
+    ap.add_argument("--debug", default=None, help="write the cases whose warm start missed to this .npz")
     a = ap.parse_args()
-    r = run_experiment(a.cases, a.side, a.seed, a.val, a.test, log=lambda m: print(m, flush=True))
+    r = run_experiment(a.cases, a.side, a.seed, a.val, a.test, log=lambda m: print(m, flush=True),
+                       debug_path=a.debug)
     print(json.dumps(r))
     if a.out:
         json.dump(r, open(a.out, "w"), indent=1)
