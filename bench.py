@@ -156,7 +156,7 @@ def measure(lbm, p, rho0, mu_w, fluid_nodes, steps, warmup, bytes_per_lu, worklo
 
     # launch shape from the library's tuner (tiles of several widths, column marching)
     lat = lattice(0)
-    shape, _ = lat.tune(trial_steps=20)
+    shape, _ = lat.tune(trial_steps=60)
     lat.close()
     # kernel only: back-to-back fused steps, no monitors
     lat = lattice(0, shape)

@@ -471,7 +471,8 @@ lbm_status lbm_batch_tune(lbm_batch* b, int32_t trial_steps, int32_t* tile_y, in
     lbm_status st = set_schedule(b, best_ty, best_bpc);
     if (st != LBM_OK) return st;
     if (tile_y) *tile_y = best_ty;
-    if (blocks_per_cu) *blocks_per_cu = best_bpc;
+    // 0 stands for "as many as fit"; report how many that is
+    if (blocks_per_cu) *blocks_per_cu = best_bpc > 0 ? best_bpc : batch_blocks_per_cu(b->prec, best_ty);
     if (best_ms) *best_ms = best / trial_steps;
     return LBM_OK;
 }
