@@ -441,9 +441,16 @@ lbm_status lbm_batch_tune(lbm_batch* b, int32_t trial_steps, int32_t* tile_y, in
     const int parity = int(b->step & 1);
     double best = 1e300;
     int best_ty = b->tile_y, best_bpc = b->blocks_per_cu;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    struct Events {  // destroyed on every return path
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     for (int ty : TILE_Y_CHOICES) {
         for (int bpc : {0, 1, 2, 4}) {
             lbm_status st = set_schedule(b, ty, bpc);
@@ -466,8 +473,6 @@ lbm_status lbm_batch_tune(lbm_batch* b, int32_t trial_steps, int32_t* tile_y, in
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     lbm_status st = set_schedule(b, best_ty, best_bpc);
     if (st != LBM_OK) return st;
     if (tile_y) *tile_y = best_ty;

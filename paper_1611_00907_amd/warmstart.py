@@ -317,6 +317,22 @@ def read_prediction(spec: CaseSpec, pred):
 VAPOUR_PINNING = 1.5   # predicted vapour / Maxwell vapour above which the interface is sub-grid
 
 
+def predicted_field(spec: CaseSpec, pred, rho_g, rho_max):
+    """The predicted density field (phase clipped to [-0.5, 1.5], smoothed once,
+    densities capped at rho_max) with its excess over rho_g scaled so that the fluid
+    rows hold the cold start's mass."""
+    rho = np.minimum(density(spec, _smooth(np.clip(np.asarray(pred, np.float64), -0.5, 1.5))), rho_max)
+    fl = slice(1, spec.side - 1)
+    M, N = float(initial_density(spec)[fl].sum()), rho[fl].size
+    excess = np.maximum(rho[fl] - rho_g, 0.0)
+    if not (excess.sum() > 0 and M - rho_g * N > 0):
+        return cap_field(spec, read_prediction(spec, pred)[0])
+    rho[fl] = np.minimum(rho_g + excess * ((M - rho_g * N) / excess.sum()), rho_max)
+    rho[0] = rho[1]
+    rho[-1] = rho[-2]
+    return rho
+
+
 def warm_field(spec: CaseSpec, pred):
     """Warm start from a predicted phase field: a clean circular cap with the
     prediction's contact angle and bulk densities and the cold start's mass
@@ -340,10 +356,12 @@ def warm_field(spec: CaseSpec, pred):
     if rg > VAPOUR_PINNING * rg0:
         # A vapour this far above Maxwell's marks an interface thinner than the
         # lattice spacing: there the contact line is pinned by the lattice and the
-        # equilibrium angle depends on the path (a start that needs less mass
-        # exchange stops up to 2 degrees away from the cold start's angle).  Start
-        # from Maxwell's densities, as the cold start does, with the predicted angle.
-        return cap_field(spec, theta)
+        # equilibrium angle depends on the path (a clean cap stops up to 2 degrees
+        # away from the cold start's angle).  The network learned the cold path's
+        # end state, pinned contact line included, so the start is its predicted
+        # field itself (smoothed, liquid kept below 1.02 Maxwell, the excess over
+        # the predicted vapour scaled to the cold start's mass).
+        return predicted_field(spec, pred, rg, 1.02 * rl0)
     rl = float(np.clip(rl, rl0, 1.02 * rl0))
     rg = float(np.clip(rg, 0.9 * rg0, 8.0 * rg0))
     return cap_field(spec, theta, rl, rg)
@@ -453,6 +471,8 @@ def run_experiment(n_cases=2000, side=256, seed=11, n_val=100, n_test=100, train
                             Tr=np.array([tspecs[k].Tr for k in never]), mu_w=np.array([tspecs[k].mu_w for k in never]))
     out.update({k: (v.tolist() if isinstance(v, np.ndarray) else v) for k, v in res.items() if k != "pred"})
     out["theta_eq"] = theta[test].tolist()
+    out["test_eos"] = [s.eos for s in tspecs]
+    out["test_Tr"] = [s.Tr for s in tspecs]
     out["theta_pred"] = pred_theta.tolist()
     out["theta_pred_abs_err_median"] = float(np.nanmedian(np.abs(pred_theta - theta[test])))
     out["steps_saved_median"] = float(np.median(res["steps_cold"] - res["steps_warm"]))
