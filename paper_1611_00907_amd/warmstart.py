@@ -333,7 +333,7 @@ def predicted_field(spec: CaseSpec, pred, rho_g, rho_max):
     return rho
 
 
-def warm_field(spec: CaseSpec, pred):
+def warm_field(spec: CaseSpec, pred, pinned="cap"):
     """Warm start from a predicted phase field: a clean circular cap with the
     prediction's contact angle and bulk densities and the cold start's mass
     (cap_field).  The prediction's pixel noise is not carried over; the mass is
@@ -356,18 +356,23 @@ def warm_field(spec: CaseSpec, pred):
     if rg > VAPOUR_PINNING * rg0:
         # A vapour this far above Maxwell's marks an interface thinner than the
         # lattice spacing: there the contact line is pinned by the lattice and the
-        # equilibrium angle depends on the path (a clean cap stops up to 2 degrees
-        # away from the cold start's angle).  The network learned the cold path's
-        # end state, pinned contact line included, so the start is its predicted
-        # field itself (smoothed, liquid kept below 1.02 Maxwell, the excess over
-        # the predicted vapour scaled to the cold start's mass).
-        return predicted_field(spec, pred, rg, 1.02 * rl0)
+        # equilibrium angle depends on the path (a clean cap at the predicted
+        # densities stops up to 2 degrees away from the cold start's angle).
+        # pinned == "cap": start from Maxwell's densities, as the cold start does,
+        # with the predicted angle (every case then reaches the cold start's angle);
+        # pinned == "field": start from the predicted field itself, which carries
+        # the cold path's end state (faster, but about 1 case in 10 still stops
+        # elsewhere).
+        if pinned == "field":
+            return predicted_field(spec, pred, rg, 1.02 * rl0)
+        return cap_field(spec, theta)
     rl = float(np.clip(rl, rl0, 1.02 * rl0))
     rg = float(np.clip(rg, 0.9 * rg0, 8.0 * rg0))
     return cap_field(spec, theta, rl, rg)
 
 
-def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000, log=None, calibration_arm=False):
+def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000, log=None, calibration_arm=False,
+             pinned="cap"):
     """Cold versus warm start of one batched sweep: per-case steps to the plain
     equilibrium angle, and the sweep's device time until its last case is there
     (for the warm start plus the network inference and the warm-field set-up)."""
@@ -376,7 +381,7 @@ def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000
     t0 = time.perf_counter()
     x = np.stack([features(s) for s in specs])
     pred = net.forward(x)
-    warm0 = [warm_field(s, p) for s, p in zip(specs, pred)]
+    warm0 = [warm_field(s, p, pinned) for s, p in zip(specs, pred)]
     t_inf = time.perf_counter() - t0
     steps_warm, dt_warm = time_to_angle(specs, warm0, theta_eq, tol_deg, check_every, max_steps, log=log)
     done = (steps_cold >= 0).all() and (steps_warm >= 0).all()
@@ -401,10 +406,10 @@ def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000
 # ---------------------------------------------------------------- the whole experiment
 def run_experiment(n_cases=2000, side=256, seed=11, n_val=100, n_test=100, train_steps=(4000, 3000, 2000, 1000),
                    lrs=(1e-3, 5e-4, 2e-4, 1e-4), batch=16, calib_side=256, calib_steps=30000, gen_steps=80000,
-                   confirm_steps=20000, gen_chunk=500, log=print, debug_path=None):
+                   confirm_steps=20000, gen_chunk=500, log=print, debug_path=None, pinned="cap"):
     """Calibrate, generate n_cases equilibria with the batched solver, train the
     surrogate on the GPU, and compare cold and warm starts on the held-out test cases."""
-    out = {"n_cases": n_cases, "side": side, "seed": seed}
+    out = {"n_cases": n_cases, "side": side, "seed": seed, "pinned": pinned}
     t0 = time.perf_counter()
     table = calibrate(Tr_grid=(0.6, 0.65, 0.7, 0.75, 0.8, 0.85, 0.9), side=calib_side, steps=calib_steps)
     out["calibration_s"] = time.perf_counter() - t0
@@ -459,14 +464,14 @@ def run_experiment(n_cases=2000, side=256, seed=11, n_val=100, n_test=100, train
     out["val_mse"] = float(np.mean((net.forward(xv) - tv) ** 2))
     tspecs = [specs[i] for i in test]
     res = evaluate(net, tspecs, theta[test], tol_deg=0.5, check_every=200, max_steps=40000, log=log,
-                   calibration_arm=True)
+                   calibration_arm=True, pinned=pinned)
     out["theta_calibration_abs_err_median"] = float(np.median(np.abs([s.theta0 for s in tspecs] - theta[test])))
     pred_theta = np.array([read_prediction(s, p)[0] for s, p in zip(tspecs, res["pred"])])
     if debug_path:
         never = [k for k in range(len(tspecs)) if res["steps_warm"][k] < 0]
         np.savez_compressed(debug_path, never=np.array(never), pred=res["pred"][never] if never else np.zeros(0),
                             eq=np.array([rho_eq[test[k]] for k in never]) if never else np.zeros(0),
-                            warm=np.array([warm_field(tspecs[k], res["pred"][k]) for k in never]) if never else
+                            warm=np.array([warm_field(tspecs[k], res["pred"][k], pinned) for k in never]) if never else
                             np.zeros(0), eos=np.array([tspecs[k].eos for k in never]),
                             Tr=np.array([tspecs[k].Tr for k in never]), mu_w=np.array([tspecs[k].mu_w for k in never]))
     out.update({k: (v.tolist() if isinstance(v, np.ndarray) else v) for k, v in res.items() if k != "pred"})
@@ -495,9 +500,11 @@ if __name__ == "__main__":
     ap.add_argument("--test", type=int, default=100)
     ap.add_argument("--out", default=None, help="write the result as JSON here")
     ap.add_argument("--debug", default=None, help="write the cases whose warm start missed to this .npz")
+    ap.add_argument("--pinned", choices=("cap", "field"), default="cap",
+                    help="warm start of the sub-grid-interface cases (see warm_field)")
     a = ap.parse_args()
     r = run_experiment(a.cases, a.side, a.seed, a.val, a.test, log=lambda m: print(m, flush=True),
-                       debug_path=a.debug)
+                       debug_path=a.debug, pinned=a.pinned)
     print(json.dumps(r))
     if a.out:
         json.dump(r, open(a.out, "w"), indent=1)
