@@ -132,27 +132,19 @@ __device__ __forceinline__ void pull9(const LatticeArgs& A, const Planes<ST>& F,
     }
     const unsigned pitch = unsigned(A.pitch), ux = unsigned(gx), uxm = unsigned(xm), uxp = unsigned(xp);
     const unsigned rc = unsigned(gy) * pitch, rm = unsigned(ym) * pitch, rp = unsigned(yp) * pitch;
-    f[0] = C::ld(F.p[0], rc + ux, b0);
+    // Links that would come from a solid row return reversed from the node itself
+    // (halfway bounce-back).  The source plane and offset are selected, not
+    // branched on, so that the nine loads issue back to back.
+    const unsigned oc = rc + ux;
+    f[0] = C::ld(F.p[0], oc, b0);
     f[1] = C::ld(F.p[1], rc + uxm, b1);
     f[3] = C::ld(F.p[3], rc + uxp, b1);
-    if (sm) {  // links from the wall below return reversed (halfway bounce-back)
-        f[2] = C::ld(F.p[4], rc + ux, b1);
-        f[5] = C::ld(F.p[7], rc + ux, b2);
-        f[6] = C::ld(F.p[8], rc + ux, b2);
-    } else {
-        f[2] = C::ld(F.p[2], rm + ux, b1);
-        f[5] = C::ld(F.p[5], rm + uxm, b2);
-        f[6] = C::ld(F.p[6], rm + uxp, b2);
-    }
-    if (sp) {
-        f[4] = C::ld(F.p[2], rc + ux, b1);
-        f[7] = C::ld(F.p[5], rc + ux, b2);
-        f[8] = C::ld(F.p[6], rc + ux, b2);
-    } else {
-        f[4] = C::ld(F.p[4], rp + ux, b1);
-        f[7] = C::ld(F.p[7], rp + uxp, b2);
-        f[8] = C::ld(F.p[8], rp + uxm, b2);
-    }
+    f[2] = C::ld(sm ? F.p[4] : F.p[2], sm ? oc : rm + ux, b1);
+    f[5] = C::ld(sm ? F.p[7] : F.p[5], sm ? oc : rm + uxm, b2);
+    f[6] = C::ld(sm ? F.p[8] : F.p[6], sm ? oc : rm + uxp, b2);
+    f[4] = C::ld(sp ? F.p[2] : F.p[4], sp ? oc : rp + ux, b1);
+    f[7] = C::ld(sp ? F.p[5] : F.p[7], sp ? oc : rp + uxp, b2);
+    f[8] = C::ld(sp ? F.p[6] : F.p[8], sp ? oc : rp + uxm, b2);
 }
 
 template <typename CT>
@@ -322,13 +314,20 @@ __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __rest
     CT jx[RPT], jy[RPT];
     const int gx_raw = x0 + lx;
     const int gxw = wrap_fast(gx_raw, A.nx, small_x);
+    // All RPT pulls go out before the first wait: every thread pulls a fluid node
+    // (rows clamped into the fluid range; what a thread does not own is dropped).
+    const int y_lo = A.bottom == BC_PERIODIC ? 0 : 1, y_hi = A.bottom == BC_PERIODIC ? A.ny - 1 : A.ny - 2;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int gy = y0 + ly + k * RS;
+        pull9<ST, CT>(A, F, gxw, gy < y_lo ? y_lo : (gy > y_hi ? y_hi : gy), f[k]);
+    }
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         const int gy = y0 + ly + k * RS;
         const bool own = gx_raw < A.nx && gy < A.ny && !solid_row(A, gy);
         CT r;
         if (own) {
-            pull9<ST, CT>(A, F, gxw, gy, f[k]);
             r = sum9(f[k]);
             momentum(f[k], jx[k], jy[k]);
         } else {
