@@ -113,9 +113,13 @@ struct Planes {
 };
 
 // f_i(x, t), i = 0..8, of a fluid node (gx, gy) by pulling from the storage.
-template <typename ST, typename CT>
+// With UNIFORM_ROW the caller guarantees that gy is the same in all lanes of the
+// wave: the row, and with it the choice of source planes, is then scalar, so each
+// load takes a scalar base and one 32-bit lane offset.
+template <typename ST, typename CT, bool UNIFORM_ROW = false>
 __device__ __forceinline__ void pull9(const LatticeArgs& A, const Planes<ST>& F, int gx, int gy,
                                       CT f[9]) {
+    if (UNIFORM_ROW) gy = __builtin_amdgcn_readfirstlane(gy);
     using C = Codec<ST>;
     const CT b0 = CT(A.rho_ref) * Wt<CT>::w0, b1 = CT(A.rho_ref) * Wt<CT>::w1,
              b2 = CT(A.rho_ref) * Wt<CT>::w2;
@@ -286,13 +290,34 @@ struct TileLds {
     CT ms[TY + 2][TX + 2];  // chemical potential, tile + 1-node ring
 };
 
-// One TX x TY tile of the step (MODE_STEP) or of the field output (MODE_FIELDS),
-// run by a workgroup of TX * TY / RPT threads, RPT nodes of one column per thread.
-template <typename ST, int EOS, int MODE, int TY, int TX = TILE_X, int RPT = ROWS_PER_THREAD>
-__device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __restrict__ fin,
-                                          ST* __restrict__ fout,
+// Own-node pulls of a TX x TY tile: thread (lx, ly) pulls the nine distributions
+// of its RPT nodes (column x0 + lx, rows y0 + ly + k TY/RPT).  All RPT pulls go
+// out before any wait; every thread pulls a fluid node (rows clamped into the
+// fluid range, columns wrapped), and what a thread does not own is dropped later.
+template <typename ST, int TY, int TX, int RPT>
+__device__ __forceinline__ void tile_pull(const LatticeArgs& A, const Planes<ST>& F, int x0, int y0,
+                                          typename Codec<ST>::CT f[RPT][9]) {
+    using CT = typename Codec<ST>::CT;
+    constexpr int RS = TY / RPT;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int gxw = wrap_fast(x0 + lx, A.nx, A.nx < TX + 2);
+    const int y_lo = A.bottom == BC_PERIODIC ? 0 : 1, y_hi = A.bottom == BC_PERIODIC ? A.ny - 1 : A.ny - 2;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int gy = y0 + ly + k * RS;
+        // rows are uniform across a wave: TX is a multiple of the wave width
+        pull9<ST, CT, TX % 64 == 0>(A, F, gxw, gy < y_lo ? y_lo : (gy > y_hi ? y_hi : gy), f[k]);
+    }
+}
+
+// The rest of one tile of the step (MODE_STEP) or of the field output
+// (MODE_FIELDS), from the own nodes' pulled distributions f: densities of the
+// tile and its ring into LDS, chemical potential, force, collision and store.
+template <typename ST, int EOS, int MODE, int TY, int TX, int RPT>
+__device__ __forceinline__ void tile_rest(const LatticeArgs& A, const Planes<ST>& F, ST* __restrict__ fout,
                                           const typename Codec<ST>::CT* __restrict__ mu_w,
                                           double* __restrict__ out, int x0, int y0,
+                                          typename Codec<ST>::CT f[RPT][9],
                                           TileLds<typename Codec<ST>::CT, TY, TX>& L) {
     using CT = typename Codec<ST>::CT;
     using C = Codec<ST>;
@@ -302,26 +327,13 @@ __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __rest
     auto& rs = L.rs;
     auto& ms = L.ms;
 
-    Planes<ST> F;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) F.p[i] = fin + (long long)i * A.plane;
-
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     const bool small_x = A.nx < TX + 2, small_y = A.ny < TY + 2;
 
-    // 1. own nodes: pull, keep f, density into LDS
-    CT f[RPT][9];
+    // 1. own nodes: density and momentum from the pulls, density into LDS
     CT jx[RPT], jy[RPT];
     const int gx_raw = x0 + lx;
     const int gxw = wrap_fast(gx_raw, A.nx, small_x);
-    // All RPT pulls go out before the first wait: every thread pulls a fluid node
-    // (rows clamped into the fluid range; what a thread does not own is dropped).
-    const int y_lo = A.bottom == BC_PERIODIC ? 0 : 1, y_hi = A.bottom == BC_PERIODIC ? A.ny - 1 : A.ny - 2;
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        const int gy = y0 + ly + k * RS;
-        pull9<ST, CT>(A, F, gxw, gy < y_lo ? y_lo : (gy > y_hi ? y_hi : gy), f[k]);
-    }
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         const int gy = y0 + ly + k * RS;
@@ -334,6 +346,24 @@ __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __rest
             r = node_rho<ST, CT>(A, F, gxw, gy, small_y);
         }
         rs[ly + k * RS + 2][lx + 2] = r;
+    }
+
+    // Wall chemical potentials (Eq 29) of a CP wall row inside the chemical-potential
+    // tile go out with the ring's pulls and land in LDS with the densities, so that
+    // step 3 reads no global memory.
+    const int mwb = 1 - y0, mwt = A.ny - y0;  // ms rows of y = 0 and y = ny - 1
+    const bool cpb = A.bottom == BC_CPWALL && mwb >= 0;
+    const bool cpt = A.top == BC_CPWALL && mwt <= TY + 1;
+    constexpr int MWR = (2 * MW + NT - 1) / NT;
+    CT mwv[MWR];
+    if (cpb || cpt) {
+#pragma unroll
+        for (int j = 0; j < MWR; ++j) {
+            const int q = threadIdx.x + j * NT, w = q / MW, c = q % MW;
+            mwv[j] = (q < 2 * MW && (w == 0 ? cpb : cpt))
+                         ? mu_w[(w == 0 ? 0 : A.pitch) + wrap_fast(x0 - 1 + c, A.nx, small_x)]
+                         : CT(0);
+        }
     }
 
     // 2. the two-node ring of densities around the tile
@@ -355,6 +385,13 @@ __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __rest
         }
         rs[r][c] = node_rho<ST, CT>(A, F, wrap_fast(x0 - 2 + c, A.nx, small_x), y0 - 2 + r, small_y);
     }
+    if (cpb || cpt) {
+#pragma unroll
+        for (int j = 0; j < MWR; ++j) {
+            const int q = threadIdx.x + j * NT, w = q / MW, c = q % MW;
+            if (q < 2 * MW && (w == 0 ? cpb : cpt)) ms[w == 0 ? mwb : mwt][c] = mwv[j];
+        }
+    }
     __syncthreads();
 
     // 3. chemical potential, Eq 8, on the tile and a one-node ring
@@ -369,7 +406,7 @@ __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __rest
             if (y == 0 || y == A.ny - 1) {
                 const int kind = y == 0 ? A.bottom : A.top;
                 if (kind == BC_CPWALL) {
-                    m = mu_w[(y == 0 ? 0 : A.pitch) + wrap_fast(x0 - 1 + c, A.nx, small_x)];
+                    continue;  // in LDS since step 2
                 } else {  // neutral wall: the chemical potential of the adjacent fluid node
                     const int rn = y == 0 ? r + 2 : r;
                     m = mu_node<EOS, ST>(A, rs[rn][c + 1]) - kappa * lap9<CT, RW>(rs, rn, c + 1);
@@ -433,6 +470,23 @@ __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __rest
             C::st(fout + (long long)i * A.plane, o, fs[i], base);
         }
     }
+}
+
+// One TX x TY tile of the step or of the field output, run by a workgroup of
+// TX * TY / RPT threads, RPT nodes of one column per thread.
+template <typename ST, int EOS, int MODE, int TY, int TX = TILE_X, int RPT = ROWS_PER_THREAD>
+__device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __restrict__ fin,
+                                          ST* __restrict__ fout,
+                                          const typename Codec<ST>::CT* __restrict__ mu_w,
+                                          double* __restrict__ out, int x0, int y0,
+                                          TileLds<typename Codec<ST>::CT, TY, TX>& L) {
+    using CT = typename Codec<ST>::CT;
+    Planes<ST> F;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) F.p[i] = fin + (long long)i * A.plane;
+    CT f[RPT][9];
+    tile_pull<ST, TY, TX, RPT>(A, F, x0, y0, f);
+    tile_rest<ST, EOS, MODE, TY, TX, RPT>(A, F, fout, mu_w, out, x0, y0, f, L);
 }
 
 // One lattice: one workgroup per tile.
