@@ -156,6 +156,25 @@ def test_fp64_per_node_wall_mu_and_cp_top():
     _compare_state(lat, ora, 1e-10)
 
 
+@pytest.mark.parametrize("code", [8, 16, 32, 12816, 12832, 25608, 25616])
+@pytest.mark.parametrize("nx,ny", [(150, 33), (300, 65), (70, 17)])
+def test_fp64_cp_walls_every_tile_shape(nx, ny, code):
+    """CP walls on both sides with per-column surface chemical potentials, on every
+    tile shape.  ny - 1 is a multiple of every tile height, so the top wall is the
+    first row of the last tile row and sits in the chemical-potential ring of the
+    tiles below it."""
+    c = Case(nx, ny, thermo.PR, 0.8, 1.3, omega=0.344, bottom=CPWALL, top=CPWALL, drop="sessile",
+             radius=min(nx, ny) / 3, noise=1e-3, seed=nx + ny)
+    x = np.arange(nx)
+    c.mu_w_bottom = 0.2 + 0.05 * np.sin(2 * np.pi * x / nx)
+    c.mu_w_top = 0.27 + 0.01 * np.cos(2 * np.pi * x / 30)
+    lat, ora = _gpu(c, lbm.LBM_F64), c.oracle()
+    lat.set_tile(code)
+    lat.step(40)
+    ora.step(40)
+    _compare_state(lat, ora, 1e-10)
+
+
 @pytest.mark.parametrize("eos", [thermo.VDW, thermo.CS, thermo.PR, thermo.RKS, thermo.RK])
 def test_fp64_every_eos(eos):
     Tr = {thermo.CS: 0.8}.get(eos, 0.85)
