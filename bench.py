@@ -231,7 +231,7 @@ def cpu_baseline(seconds: float):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)"
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (requested --gpus %d)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
     from paper_1611_00907_amd import inputs, lbm
