@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-aux", action="store_true")
+    ap.add_argument("--surrogate-only", type=int, default=0, metavar="STEPS",
+                    help="time STEPS surrogate training steps only, print their JSON and exit (for profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-bytes", type=int, default=1 << 30,
                     help="size of the plain copy whose bandwidth is reported beside the roofline")
@@ -118,6 +120,49 @@ def measure_batch(lbm, inputs, steps):
             "roofline": {"bound": "hbm", "achieved": round(nodes * 72.0 * n / t / 1e9, 1), "peak": PEAK_HBM_GBS,
                          "unit": "GB/s", "frac": round(nodes * 72.0 * n / t / 1e9 / PEAK_HBM_GBS, 4),
                          "traffic": None}}
+
+
+PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
+
+
+def surrogate_step_flops(lbm, size, batch):
+    """Algorithmic flops of one training step of the surrogate: every 3x3
+    convolution costs 2 * 9 * c_in * c_out per output pixel in the forward pass, the
+    same again for its weight gradient and, except the first layer (whose input
+    needs no gradient), for its input gradient."""
+    level = {"0": 0, "1": 1, "2": 2, "3": 3, "u": 0}
+    fwd = first = 0.0
+    for name, ci, co in lbm.Surrogate.LAYERS:
+        lv = level[name[1]]
+        f = 2.0 * 9 * ci * co * (size >> lv) ** 2
+        fwd += f
+        if name == lbm.Surrogate.LAYERS[0][0]:
+            first = f
+    return batch * (3.0 * fwd - first)
+
+
+def measure_surrogate(lbm, size=256, batch=16, steps=40):
+    """Training steps of the surrogate (BF16 MFMA convolutions, FP32 accumulation)
+    on a device-resident synthetic dataset, timed on the host around sur_train."""
+    from paper_1611_00907_amd import warmstart
+    rng = np.random.default_rng(7)
+    n = 4 * batch
+    x = rng.normal(size=(n, 4, size, size)).astype(np.float32)
+    t = rng.normal(size=(n, size, size)).astype(np.float32)
+    net = lbm.Surrogate(size, max_batch=batch)
+    net.set_params(warmstart.he_init(3))
+    net.set_dataset(x, t)
+    net.train(3, batch, 1e-4, seed=1)
+    t0 = time.perf_counter()
+    net.train(steps, batch, 1e-4, seed=2)
+    dt = (time.perf_counter() - t0) / steps
+    flops = surrogate_step_flops(lbm, size, batch)
+    tf = flops / dt / 1e12
+    return {"workload": "surrogate training step: batch %d at %d^2, 4-level U-Net (32-128 channels), BF16 MFMA "
+                        "convolutions with FP32 accumulation, Adam" % (batch, size),
+            "ms_per_step": round(dt * 1e3, 3), "gflop_per_step": round(flops / 1e9, 1),
+            "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tf / PEAK_BF16_TFLOPS, 5), "traffic": None}}
 
 
 def traffic_for(workload: str, shape: int):
@@ -237,6 +282,9 @@ def main():
     from paper_1611_00907_amd import inputs, lbm
 
     lbm.load_library()
+    if args.surrogate_only > 0:
+        print(json.dumps(measure_surrogate(lbm, steps=args.surrogate_only)), flush=True)
+        return
 
     copy_gbs = lbm.lbm_copy_bandwidth(args.copy_bytes, 20)
     print("copy: %.1f GB/s over %d bytes" % (copy_gbs, args.copy_bytes), file=sys.stderr, flush=True)
@@ -271,6 +319,10 @@ def main():
         aux.append(res)
         print("aux batch: %.1f MLUPS %.1f GB/s (tile %d, %d/CU)" % (res["mlups"], res["roofline"]["achieved"],
                                                                    res["tile_y"], res["blocks_per_cu"]),
+              file=sys.stderr, flush=True)
+        res = measure_surrogate(lbm)
+        aux.append(res)
+        print("aux surrogate: %.2f ms/step %.2f TFLOP/s" % (res["ms_per_step"], res["roofline"]["achieved"]),
               file=sys.stderr, flush=True)
 
     line = {

@@ -161,10 +161,9 @@ hipError_t wgrad(sur_net* n, int li, TView x, TView dz, int N, int H, int W) {
     a.cin_p = l.cin_p;
     a.cout = l.d.cout;
     a.cout_p = l.cout_p;
+    a.db = n->grad + l.b_off;
     a.chunk_px = 2048;
-    hipError_t e = conv3x3_wgrad(a, n->stream);
-    if (e != hipSuccess) return e;
-    return bias_grad(dz, (long long)N * H * W, l.d.cout, n->grad + l.b_off, n->stream);
+    return conv3x3_wgrad(a, n->stream);
 }
 
 hipError_t refresh_flipped(sur_net* n) {

@@ -40,6 +40,7 @@ struct WgradArgs {
     TView x;             // convolution input
     TView dz;            // gradient at the convolution output (before its bias)
     float* dw;           // [9][cout_p][cin_p] FP32, accumulated atomically
+    float* db;           // [cout] FP32 bias gradient, accumulated atomically
     int N, H, W;
     int cin, cin_p, cout, cout_p;
     long long chunk_px;  // pixels per wave
@@ -47,7 +48,6 @@ struct WgradArgs {
 
 hipError_t conv3x3(const ConvArgs& a, hipStream_t s);
 hipError_t conv3x3_wgrad(const WgradArgs& a, hipStream_t s);
-hipError_t bias_grad(TView dz, long long npx, int cout, float* db, hipStream_t s);
 hipError_t avgpool2(TView in, TView out, int N, int H, int W, int C, hipStream_t s);
 hipError_t upsample2(TView in, TView out, int N, int H, int W, int C, hipStream_t s);
 hipError_t upsample2_grad(const float* dcat, int dcs, int dco, TView act, TView dz, int N, int Ho, int Wo, int C,

@@ -137,73 +137,136 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
 // ---------------------------------------------------------------- weight gradient
 // dW[tap][co][ci] += sum_p dZ[p][co] X[p shifted by tap][ci]: GEMM with the pixels as
 // the reduction axis.  A = dZ^T (rows co), B = shifted X (columns ci); the operands
-// are gathered 8 pixels at a time.  Each wave owns one tap, a 16 x 16 (co, ci) tile
-// and a chunk of pixels, and adds its partial tile to dW atomically.
+// are gathered 8 pixels at a time.  Each wave owns one tap, a (16 WM) x (16 WN)
+// block of (co, ci) and a chunk of pixels, and adds its partial block to dW
+// atomically; every gathered operand feeds WN (A) or WM (B) MFMAs.  A lane's pixel
+// coordinates come from one division per 32 pixels and then by increments; inside
+// the image, the tap's source pixel is p + du W + dv.  The waves of the centre tap
+// and the first ci block also sum dZ for the bias gradient db[co] = sum_p dZ[p][co].
+template <int WM, int WN, bool PAIRED>
 __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(WgradArgs a) {
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
-    const int co_tiles = a.cout_p / 16, ci_tiles = (a.cin + 15) / 16;
-    const int tiles = 9 * co_tiles * ci_tiles;
+    const int co_blocks = (a.cout + 16 * WM - 1) / (16 * WM), ci_blocks = (a.cin + 16 * WN - 1) / (16 * WN);
+    const int tiles = 9 * co_blocks * ci_blocks;
     const int tile = wave % tiles;
     const int chunk = wave / tiles;
-    const long long npx = (long long)a.N * a.H * a.W;
-    const long long p_begin = (long long)chunk * a.chunk_px;
+    const int npx = a.N * a.H * a.W;  // the host keeps pixel indices below 2^31
+    const int cpx = int(a.chunk_px);
+    const int p_begin = chunk * cpx;
     if (p_begin >= npx) return;
-    const long long p_end = p_begin + a.chunk_px < npx ? p_begin + a.chunk_px : npx;
+    const int p_end = p_begin < npx - cpx ? p_begin + cpx : npx;
     const int tap = tile % 9;
-    const int co_t = (tile / 9) % co_tiles, ci_t = tile / 9 / co_tiles;
+    const int co_t = (tile / 9) % co_blocks, ci_t = tile / 9 / co_blocks;
     const int du = tap / 3 - 1, dv = tap % 3 - 1;
-    const int co_a = co_t * 16 + r;  // A row of this lane
-    const int ci_b = ci_t * 16 + r;  // B column of this lane
-    const bool co_ok = co_a < a.cout, ci_ok = ci_b < a.cin;
-    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (long long pk = p_begin; pk < p_end; pk += 32) {
-        uint16_t ah[8], bh[8];
+    const int shift = du * a.W + dv;
+    int co_a[WM], ci_b[WN];  // A rows / B columns of this lane
+    bool co_ok[WM], ci_ok[WN];
+    // PAIRED (WM = WN = 2, even channel counts and offsets): tile m holds the
+    // channels of parity m, so one 32-bit load brings a lane both of its channels.
+#pragma unroll
+    for (int m = 0; m < WM; ++m) {
+        co_a[m] = PAIRED ? co_t * 32 + 2 * r + m : co_t * 16 * WM + 16 * m + r;
+        co_ok[m] = co_a[m] < a.cout;
+    }
+#pragma unroll
+    for (int n = 0; n < WN; ++n) {
+        ci_b[n] = PAIRED ? ci_t * 32 + 2 * r + n : ci_t * 16 * WN + 16 * n + r;
+        ci_ok[n] = ci_b[n] < a.cin;
+    }
+    const bool bias = tap == 4 && ci_t == 0;  // wave-uniform
+    const unsigned W = unsigned(a.W), H = unsigned(a.H);
+    f32x4 acc[WM][WN];
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+        for (int n = 0; n < WN; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum[WM];
+#pragma unroll
+    for (int m = 0; m < WM; ++m) bsum[m] = 0.f;
+    for (int pk = p_begin; pk < p_end; pk += 32) {
+        const int p0 = pk + 8 * g;
+        const unsigned q = unsigned(p0) / W;
+        int x = int(unsigned(p0) - q * W);
+        int y = int(q % H);
+        uint16_t ah[WM][8], bh[WN][8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const long long p = pk + 8 * g + j;
-            ah[j] = 0;
-            bh[j] = 0;
-            if (p < p_end) {
-                if (co_ok) ah[j] = a.dz.p[p * a.dz.cs + a.dz.co + co_a];
-                const int x = int(p % a.W);
-                const long long t = p / a.W;
-                const int y = int(t % a.H);
-                const long long n = t / a.H;
-                const int yy = y + du, xx = x + dv;
-                if (ci_ok && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-                    bh[j] = a.x.p[((n * a.H + yy) * a.W + xx) * a.x.cs + a.x.co + ci_b];
+            const int p = p0 + j;
+            const int yy = y + du, xx = x + dv;
+            const bool in = p < p_end, src = in && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+            const long long oz = (long long)p * a.dz.cs + a.dz.co, ox = (long long)(p + shift) * a.x.cs + a.x.co;
+            if constexpr (PAIRED) {
+                const uint32_t va = (in && co_ok[0]) ? *reinterpret_cast<const uint32_t*>(a.dz.p + oz + co_a[0]) : 0u;
+                const uint32_t vb = (src && ci_ok[0]) ? *reinterpret_cast<const uint32_t*>(a.x.p + ox + ci_b[0]) : 0u;
+                ah[0][j] = uint16_t(va);
+                ah[1][j] = uint16_t(va >> 16);
+                bh[0][j] = uint16_t(vb);
+                bh[1][j] = uint16_t(vb >> 16);
+            } else {
+#pragma unroll
+                for (int m = 0; m < WM; ++m) ah[m][j] = (in && co_ok[m]) ? a.dz.p[oz + co_a[m]] : uint16_t(0);
+#pragma unroll
+                for (int n = 0; n < WN; ++n) bh[n][j] = (src && ci_ok[n]) ? a.x.p[ox + ci_b[n]] : uint16_t(0);
+            }
+            if (++x == a.W) {
+                x = 0;
+                if (++y == a.H) y = 0;
             }
         }
-        uint4 av, bv;
-        av.x = ah[0] | (uint32_t(ah[1]) << 16);
-        av.y = ah[2] | (uint32_t(ah[3]) << 16);
-        av.z = ah[4] | (uint32_t(ah[5]) << 16);
-        av.w = ah[6] | (uint32_t(ah[7]) << 16);
-        bv.x = bh[0] | (uint32_t(bh[1]) << 16);
-        bv.y = bh[2] | (uint32_t(bh[3]) << 16);
-        bv.z = bh[4] | (uint32_t(bh[5]) << 16);
-        bv.w = bh[6] | (uint32_t(bh[7]) << 16);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), as_bf16x8(bv), acc, 0, 0, 0);
-    }
-    // lane holds D[4 g + i][r]: co = co_t*16 + 4g + i, ci = ci_t*16 + r
+        if (bias) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int co = co_t * 16 + 4 * g + i, ci = ci_t * 16 + r;
-        if (co < a.cout && ci < a.cin) atomicAdd(&a.dw[((size_t)tap * a.cout_p + co) * a.cin_p + ci], acc[i]);
+            for (int m = 0; m < WM; ++m)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) bsum[m] += bf2f(ah[m][j]);
+        }
+        bf16x8 av[WM], bv[WN];
+#pragma unroll
+        for (int m = 0; m < WM; ++m) {
+            uint4 v;
+            v.x = ah[m][0] | (uint32_t(ah[m][1]) << 16);
+            v.y = ah[m][2] | (uint32_t(ah[m][3]) << 16);
+            v.z = ah[m][4] | (uint32_t(ah[m][5]) << 16);
+            v.w = ah[m][6] | (uint32_t(ah[m][7]) << 16);
+            av[m] = as_bf16x8(v);
+        }
+#pragma unroll
+        for (int n = 0; n < WN; ++n) {
+            uint4 v;
+            v.x = bh[n][0] | (uint32_t(bh[n][1]) << 16);
+            v.y = bh[n][2] | (uint32_t(bh[n][3]) << 16);
+            v.z = bh[n][4] | (uint32_t(bh[n][5]) << 16);
+            v.w = bh[n][6] | (uint32_t(bh[n][7]) << 16);
+            bv[n] = as_bf16x8(v);
+        }
+#pragma unroll
+        for (int m = 0; m < WM; ++m)
+#pragma unroll
+            for (int n = 0; n < WN; ++n)
+                acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv[n], acc[m][n], 0, 0, 0);
     }
-}
-
-// db[co] += sum_p dZ[p][co] over a chunk of pixels.
-__global__ __launch_bounds__(256) void bias_grad_kernel(TView dz, long long npx, int cout, long long chunk,
-                                                        float* __restrict__ db) {
-    const int co = threadIdx.x % 64 + 64 * (blockIdx.y);
-    const long long p0 = (long long)blockIdx.x * chunk;
-    if (co >= cout) return;
-    float s = 0.f;
-    for (long long p = p0 + threadIdx.x / 64; p < p0 + chunk && p < npx; p += 4) s += bf2f(dz.p[p * dz.cs + dz.co + co]);
-    atomicAdd(&db[co], s);
+    // lane holds D[4 g + i][r] of each 16 x 16 tile (m, n)
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+        for (int n = 0; n < WN; ++n)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int co = PAIRED ? co_t * 32 + 2 * (4 * g + i) + m : co_t * 16 * WM + 16 * m + 4 * g + i;
+                const int ci = ci_b[n];
+                if (co < a.cout && ci < a.cin)
+                    atomicAdd(&a.dw[((size_t)tap * a.cout_p + co) * a.cin_p + ci], acc[m][n][i]);
+            }
+    if (bias) {  // lanes r, r + 16, r + 32, r + 48 hold partial sums of channel co_a[m]
+#pragma unroll
+        for (int m = 0; m < WM; ++m) {
+            float v = bsum[m];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (g == 0 && co_ok[m]) atomicAdd(&a.db[co_a[m]], v);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- elementwise
@@ -383,22 +446,26 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t conv3x3_wgrad(const WgradArgs& a, hipStream_t s) {
+template <int WM, int WN, bool PAIRED>
+hipError_t wgrad_launch(const WgradArgs& a, hipStream_t s) {
     const long long npx = (long long)a.N * a.H * a.W;
     const long long chunks = (npx + a.chunk_px - 1) / a.chunk_px;
-    const long long tiles = 9LL * (a.cout_p / 16) * ((a.cin + 15) / 16);
+    const long long tiles = 9LL * ((a.cout + 16 * WM - 1) / (16 * WM)) * ((a.cin + 16 * WN - 1) / (16 * WN));
     const long long waves = chunks * tiles;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3(int((waves + 3) / 4)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((conv3x3_wgrad_kernel<WM, WN, PAIRED>), dim3(int((waves + 3) / 4)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t bias_grad(TView dz, long long npx, int cout, float* db, hipStream_t s) {
-    const long long chunk = 4096;
-    (void)hipGetLastError();
-    hipLaunchKernelGGL(bias_grad_kernel, dim3(int((npx + chunk - 1) / chunk), (cout + 63) / 64), dim3(256), 0, s, dz,
-                       npx, cout, chunk, db);
-    return hipGetLastError();
+// 2 x 2 blocks of 16 x 16 tiles for every layer (measured: 4-tile blocks along the
+// wider layers leave too few waves and lose more than the shared gathers gain);
+// channel pairs in one load where every channel count, stride and offset is even.
+hipError_t conv3x3_wgrad(const WgradArgs& a, hipStream_t s) {
+    const long long npx = (long long)a.N * a.H * a.W;
+    if (npx + a.chunk_px >= (1LL << 31) || a.chunk_px % 32 != 0) return hipErrorInvalidValue;
+    const bool even = a.cout % 2 == 0 && a.cin % 2 == 0 && a.dz.cs % 2 == 0 && a.dz.co % 2 == 0 &&
+                      a.x.cs % 2 == 0 && a.x.co % 2 == 0;
+    return even ? wgrad_launch<2, 2, true>(a, s) : wgrad_launch<2, 2, false>(a, s);
 }
 
 hipError_t avgpool2(TView in, TView out, int N, int H, int W, int C, hipStream_t s) {
