@@ -134,6 +134,112 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     }
 }
 
+// LDS-staged convolution for output channels in blocks of 32: a workgroup computes
+// an 8 x 16 pixel tile of one image for 32 output channels.  For each block of 32
+// input channels it stages the 10 x 18 input halo and the 9 x 32 x 32 weights in
+// LDS, and its four waves (two pixel rows of 16 each) take the operands of all nine
+// taps from there.
+constexpr int LT_H = 8, LT_W = 16, LT_CO = 32;
+__global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t xin[(LT_H + 2) * (LT_W + 2) * 32];
+    __shared__ __attribute__((aligned(16))) uint16_t wsh[9 * LT_CO * 32];
+    const int co_blocks = a.cout_p / LT_CO;
+    const int tiles_x = (a.W + LT_W - 1) / LT_W, tiles_y = (a.H + LT_H - 1) / LT_H;
+    int b = blockIdx.x;
+    const int co_blk = b % co_blocks;
+    b /= co_blocks;
+    const int tx = b % tiles_x;
+    b /= tiles_x;
+    const int ty = b % tiles_y;
+    const int img = b / tiles_y;
+    const int x0 = tx * LT_W, y0 = ty * LT_H, co_base = co_blk * LT_CO;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int ci0 = 0; ci0 < a.cin_p; ci0 += 32) {
+        // input halo: (LT_H + 2) x (LT_W + 2) pixels x 32 channels, zero outside the
+        // image and beyond cin; 8 channels (16 bytes) per load
+        for (int q = threadIdx.x; q < (LT_H + 2) * (LT_W + 2) * 4; q += 256) {
+            const int pix = q >> 2, cg = q & 3;
+            const int yy = y0 - 1 + pix / (LT_W + 2), xx = x0 - 1 + pix % (LT_W + 2);
+            const int ci = ci0 + 8 * cg;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W && ci < a.cin)
+                v = *reinterpret_cast<const uint4*>(a.in.p + (((long long)img * a.H + yy) * a.W + xx) * a.in.cs +
+                                                    a.in.co + ci);
+            *reinterpret_cast<uint4*>(xin + pix * 32 + 8 * cg) = v;
+        }
+        // weights of this block: [tap][32 output channels][32 input channels]
+        for (int q = threadIdx.x; q < 9 * LT_CO * 4; q += 256) {
+            const int row = q >> 2, cg = q & 3;
+            const int tap = row / LT_CO, col = row - tap * LT_CO;
+            *reinterpret_cast<uint4*>(wsh + row * 32 + 8 * cg) = *reinterpret_cast<const uint4*>(
+                a.w + ((size_t)(tap * a.cout_p + co_base + col) * a.cin_p + ci0 + 8 * cg));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int du = tap / 3 - 1, dv = tap % 3 - 1;
+            bf16x8 av[2], bv[2];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const int ly = 2 * wave + m + 1 + du, lx = r + 1 + dv;
+                av[m] = as_bf16x8(*reinterpret_cast<const uint4*>(xin + (ly * (LT_W + 2) + lx) * 32 + 8 * g));
+            }
+#pragma unroll
+            for (int n = 0; n < 2; ++n)
+                bv[n] = as_bf16x8(*reinterpret_cast<const uint4*>(wsh + (tap * LT_CO + 16 * n + r) * 32 + 8 * g));
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int n = 0; n < 2; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv[n], acc[m][n], 0, 0, 0);
+        }
+        __syncthreads();  // the next block of channels overwrites the LDS
+    }
+
+    // epilogue: lane holds pixels (y0 + 2 wave + m, x0 + 4 g + i), channel co_base + 16 n + r
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        const int co = co_base + 16 * n + r;
+        if (co >= a.cout) continue;
+        const float bias = (a.bias != nullptr) ? a.bias[co] : 0.0f;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const int y = y0 + 2 * wave + m;
+            if (y >= a.H) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = x0 + 4 * g + i;
+                if (x >= a.W) continue;
+                const long long p = ((long long)img * a.H + y) * a.W + x;
+                const float v = acc[m][n][i] + bias;
+                switch (a.epi) {
+                case EPI_RELU_BF16:
+                    a.out.p[p * a.out.cs + a.out.co + co] = f2bf(v > 0.f ? v : 0.f);
+                    break;
+                case EPI_MASK_BF16: {
+                    const float mk = bf2f(a.mask.p[p * a.mask.cs + a.mask.co + co]);
+                    a.out.p[p * a.out.cs + a.out.co + co] = f2bf(mk > 0.f ? v : 0.f);
+                    break;
+                }
+                case EPI_BF16:
+                    a.out.p[p * a.out.cs + a.out.co + co] = f2bf(v);
+                    break;
+                default:  // EPI_F32
+                    a.out_f32[p * a.out_f32_cs + co] = v;
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- weight gradient
 // dW[tap][co][ci] += sum_p dZ[p][co] X[p shifted by tap][ci]: GEMM with the pixels as
 // the reduction axis.  A = dZ^T (rows co), B = shifted X (columns ci); the operands
@@ -436,9 +542,10 @@ int grid_for(long long n) {
 hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
     const long long npx = (long long)a.N * a.H * a.W;
     (void)hipGetLastError();
-    if (a.cout_p % 32 == 0) {
-        const long long waves = ((npx + 63) / 64) * (a.cout_p / 32);
-        hipLaunchKernelGGL((conv3x3_kernel<4, 2>), dim3(int((waves + 3) / 4)), dim3(256), 0, s, a);
+    if (a.cout_p % LT_CO == 0) {
+        const long long blocks = (long long)a.N * ((a.H + LT_H - 1) / LT_H) * ((a.W + LT_W - 1) / LT_W) *
+                                 (a.cout_p / LT_CO);
+        hipLaunchKernelGGL(conv3x3_lds_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, a);
     } else {
         const long long waves = ((npx + 63) / 64) * (a.cout_p / 16);
         hipLaunchKernelGGL((conv3x3_kernel<4, 1>), dim3(int((waves + 3) / 4)), dim3(256), 0, s, a);
