@@ -1,0 +1,58 @@
+"""CPU: the host-side pieces of bench.py (flop count of the surrogate's training
+step, the counter-traffic lookup, the one-GPU guard and the CPU-baseline record)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_1611_00907_amd import lbm  # noqa: E402
+
+
+def test_surrogate_step_flops_by_hand():
+    """Resolutions written out level by level (encoder 0..3, decoder 2..0, output at
+    full size), independent of the layer-name parsing in bench.py."""
+    size, batch = 64, 3
+    res = {"e0a": 64, "e0b": 64, "e1a": 32, "e1b": 32, "e2a": 16, "e2b": 16, "e3a": 8, "e3b": 8,
+           "d2a": 16, "d2b": 16, "d1a": 32, "d1b": 32, "d0a": 64, "d0b": 64, "out": 64}
+    fwd = {name: 2 * 9 * ci * co * res[name] ** 2 for name, ci, co in lbm.Surrogate.LAYERS}
+    want = batch * (3 * sum(fwd.values()) - fwd["e0a"])
+    assert bench.surrogate_step_flops(lbm, size, batch) == pytest.approx(want, rel=1e-12)
+
+
+def test_surrogate_step_flops_at_the_benchmark_size():
+    assert bench.surrogate_step_flops(lbm, 256, 16) / 1e9 == pytest.approx(789.4, abs=0.05)
+
+
+def test_traffic_lookup_follows_the_kernel_source(monkeypatch):
+    assert bench.traffic_for("no_such_workload", 32) is None
+    path = os.path.join(ROOT, "profiles", "traffic_step_f32_wetting1024.json")
+    d = json.load(open(path))
+    shape = next(k for k in d["shapes"] if k != "march")
+    monkeypatch.setattr(bench, "kernel_sha", lambda: d["kernel_sha"])
+    got = bench.traffic_for("step_f32_wetting1024", int(shape))
+    rec = d["shapes"][shape]
+    want = (rec["fetch_kib_per_dispatch"] * d["fetch_factor"] + rec["write_kib_per_dispatch"] * d["write_factor"]) * 1024
+    assert got == pytest.approx(want, abs=1.0)
+    # counters taken on another kernel source are not reported
+    monkeypatch.setattr(bench, "kernel_sha", lambda: "0" * 16)
+    assert bench.traffic_for("step_f32_wetting1024", int(shape)) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_cpu_baseline_record():
+    rec = bench.cpu_baseline(0.2)
+    assert rec["kind"] == "oracle" and rec["unit"] == "MLUPS"
+    assert rec["cores"] >= 1 and rec["value"] > 0
+    assert "1024x1024 wetting workload" in rec["sample"]
