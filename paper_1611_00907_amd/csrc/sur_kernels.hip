@@ -572,7 +572,14 @@ hipError_t conv3x3_wgrad(const WgradArgs& a, hipStream_t s) {
     if (npx + a.chunk_px >= (1LL << 31) || a.chunk_px % 32 != 0) return hipErrorInvalidValue;
     const bool even = a.cout % 2 == 0 && a.cin % 2 == 0 && a.dz.cs % 2 == 0 && a.dz.co % 2 == 0 &&
                       a.x.cs % 2 == 0 && a.x.co % 2 == 0;
-    return even ? wgrad_launch<2, 2, true>(a, s) : wgrad_launch<2, 2, false>(a, s);
+    // pixel runs sized for about 16384 waves (512 to 8192 pixels): long runs for the
+    // large layers (fewer atomic block updates), short ones for the small layers
+    WgradArgs b = a;
+    const long long tiles = 9LL * ((a.cout + 31) / 32) * ((a.cin + 31) / 32);
+    long long c = npx * tiles / 16384;
+    c = c < 512 ? 512 : (c > 8192 ? 8192 : c);
+    b.chunk_px = c / 32 * 32;
+    return even ? wgrad_launch<2, 2, true>(b, s) : wgrad_launch<2, 2, false>(b, s);
 }
 
 hipError_t avgpool2(TView in, TView out, int N, int H, int W, int C, hipStream_t s) {
