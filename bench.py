@@ -117,6 +117,7 @@ def measure_batch(lbm, inputs, steps):
     return {"workload": "batch of 256 droplet-on-wall cases, side 128-512, CS/PR, Tr 0.6-0.9, f32 storage",
             "fluid_nodes": nodes, "mlups": round(nodes * n / t / 1e6, 1),
             "ms_per_step": round(t / n * 1e3, 4), "tile_y": ty, "blocks_per_cu": bpc,
+            "grid": "one workgroup per (case, tile) entry" if bpc < 0 else "%d workgroups per CU, persistent" % bpc,
             "roofline": {"bound": "hbm", "achieved": round(nodes * 72.0 * n / t / 1e9, 1), "peak": PEAK_HBM_GBS,
                          "unit": "GB/s", "frac": round(nodes * 72.0 * n / t / 1e9 / PEAK_HBM_GBS, 4),
                          "traffic": None}}
@@ -318,8 +319,8 @@ def main():
                   file=sys.stderr, flush=True)
         res = measure_batch(lbm, inputs, 320)
         aux.append(res)
-        print("aux batch: %.1f MLUPS %.1f GB/s (tile %d, %d/CU)" % (res["mlups"], res["roofline"]["achieved"],
-                                                                   res["tile_y"], res["blocks_per_cu"]),
+        print("aux batch: %.1f MLUPS %.1f GB/s (tile %d, %s)" % (res["mlups"], res["roofline"]["achieved"],
+                                                                res["tile_y"], res["grid"]),
               file=sys.stderr, flush=True)
         res = measure_surrogate(lbm)
         aux.append(res)

@@ -217,10 +217,19 @@ lbm_status lbm_batch_get_fields(lbm_batch* b, int32_t i, double* rho, double* vx
                                 double* mu);
 lbm_status lbm_batch_get_state(lbm_batch* b, int32_t i, double* f);
 
-/* Tunes the tile height and the persistent grid (workgroups per CU) on the active
- * cases without changing their state; keeps and returns the fastest. */
+/* Tunes the tile height and the grid of the batched launch on the active cases
+ * without changing their state; keeps and returns the fastest.  The grid is k
+ * workgroups per compute unit, each walking a contiguous run of the (case, tile)
+ * list (*blocks_per_cu = k), or one workgroup per list entry (*blocks_per_cu = -1,
+ * resized whenever the list of active cases changes). */
 lbm_status lbm_batch_tune(lbm_batch* b, int32_t trial_steps, int32_t* tile_y,
                           int32_t* blocks_per_cu, double* best_ms);
+
+/* Sets the tile height (8, 16 or 32) and the grid of the batched launch directly:
+ * blocks_per_cu = k > 0 workgroups per compute unit, 0 as many as fit, -1 one
+ * workgroup per (case, tile) entry.  LBM_EINVAL for other values.  Every schedule
+ * computes the same step. */
+lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t tile_y, int32_t blocks_per_cu);
 
 /* Fluid nodes of all cases (active_only != 0: of the active ones); -1 for NULL. */
 int64_t lbm_batch_fluid_nodes(lbm_batch* b, int32_t active_only);

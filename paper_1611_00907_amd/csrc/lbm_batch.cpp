@@ -38,7 +38,7 @@ struct lbm_batch {
     int ntiles = 0;  // active tiles
     // schedule
     int tile_y = TILE_Y_DEFAULT;
-    int blocks_per_cu = 0;  // 0: the occupancy limit
+    int blocks_per_cu = 0;  // 0: the occupancy limit; -1: one workgroup per (case, tile) entry
     int grid = 0;
     int64_t step = 0;
     std::vector<int32_t> state;  // 0 active, 1 converged, 2 diverged
@@ -131,6 +131,7 @@ lbm_status upload_tiles(lbm_batch* b) {
     }
     begin[b->n] = (int)tiles.size();
     b->ntiles = (int)tiles.size();
+    if (b->blocks_per_cu < 0) b->grid = std::max(1, b->ntiles);  // one workgroup per entry
     if (!tiles.empty())
         HIP_TRY(hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice,
                                b->stream));
@@ -154,7 +155,7 @@ lbm_status set_schedule(lbm_batch* b, int tile_y, int blocks_per_cu) {
     const int occ = batch_blocks_per_cu(b->prec, tile_y);
     b->tile_y = tile_y;
     b->blocks_per_cu = blocks_per_cu;
-    b->grid = std::max(1, cus * (blocks_per_cu > 0 ? std::min(blocks_per_cu, occ) : occ));
+    b->grid = std::max(1, cus * (blocks_per_cu > 0 ? std::min(blocks_per_cu, occ) : occ));  // -1: upload_tiles
     lbm_status st = upload_desc(b);
     if (st != LBM_OK) return st;
     return upload_tiles(b);
@@ -452,7 +453,7 @@ lbm_status lbm_batch_tune(lbm_batch* b, int32_t trial_steps, int32_t* tile_y, in
     HIP_TRY(hipEventCreate(&ev.b));
     hipEvent_t e0 = ev.a, e1 = ev.b;
     for (int ty : TILE_Y_CHOICES) {
-        for (int bpc : {0, 1, 2, 4}) {
+        for (int bpc : {0, 1, 2, 4, -1}) {
             lbm_status st = set_schedule(b, ty, bpc);
             if (st != LBM_OK) return st;
             if (b->ntiles == 0) break;
@@ -476,10 +477,19 @@ lbm_status lbm_batch_tune(lbm_batch* b, int32_t trial_steps, int32_t* tile_y, in
     lbm_status st = set_schedule(b, best_ty, best_bpc);
     if (st != LBM_OK) return st;
     if (tile_y) *tile_y = best_ty;
-    // 0 stands for "as many as fit"; report how many that is
-    if (blocks_per_cu) *blocks_per_cu = best_bpc > 0 ? best_bpc : batch_blocks_per_cu(b->prec, best_ty);
+    // 0 stands for "as many as fit"; report how many that is (-1: one per entry)
+    if (blocks_per_cu) *blocks_per_cu = best_bpc != 0 ? best_bpc : batch_blocks_per_cu(b->prec, best_ty);
     if (best_ms) *best_ms = best / trial_steps;
     return LBM_OK;
+}
+
+lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t tile_y, int32_t blocks_per_cu) {
+    if (!b || blocks_per_cu < -1 || blocks_per_cu > 64) return LBM_EINVAL;
+    bool ok = false;
+    for (int ty : TILE_Y_CHOICES) ok = ok || ty == tile_y;
+    if (!ok) return LBM_EINVAL;
+    if (hipSetDevice(b->device) != hipSuccess) return LBM_EHIP;
+    return set_schedule(b, tile_y, blocks_per_cu);
 }
 
 lbm_status lbm_batch_step_timed(lbm_batch* b, int64_t n, double* ms) {

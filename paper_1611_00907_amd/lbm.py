@@ -34,7 +34,7 @@ EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lb
             "lbm_set_wall_mu", "lbm_tune", "lbm_set_tile",
             "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_step_timed",
             "lbm_batch_run", "lbm_batch_status", "lbm_batch_get_fields", "lbm_batch_get_state",
-            "lbm_batch_tune", "lbm_batch_fluid_nodes", "lbm_batch_destroy", "lbm_copy_bandwidth",
+            "lbm_batch_tune", "lbm_batch_set_schedule", "lbm_batch_fluid_nodes", "lbm_batch_destroy", "lbm_copy_bandwidth",
             "sur_create", "sur_param_count", "sur_set_params", "sur_get_params", "sur_forward", "sur_gradients",
             "sur_set_dataset", "sur_train", "sur_destroy",
             "lbm_get_monitors", "lbm_monitor_step", "lbm_get_state", "lbm_set_state",
@@ -121,6 +121,7 @@ def load_library():
     lib.lbm_batch_get_fields.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     lib.lbm_batch_get_state.argtypes = [vp, C.c_int32, vp]
     lib.lbm_batch_tune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp]
+    lib.lbm_batch_set_schedule.argtypes = [vp, C.c_int32, C.c_int32]
     lib.lbm_batch_fluid_nodes.argtypes = [vp, C.c_int32]
     lib.lbm_batch_fluid_nodes.restype = C.c_int64
     lib.lbm_batch_destroy.argtypes = [vp]
@@ -419,6 +420,9 @@ class Batch:
         _check(self.lib.lbm_batch_tune(self.ctx, int(trial_steps), C.byref(ty), C.byref(bpc), C.byref(ms)),
                "lbm_batch_tune")
         return ty.value, bpc.value, ms.value
+
+    def set_schedule(self, tile_y: int, blocks_per_cu: int):
+        _check(self.lib.lbm_batch_set_schedule(self.ctx, int(tile_y), int(blocks_per_cu)), "lbm_batch_set_schedule")
 
     def fluid_nodes(self, active_only: bool = False) -> int:
         return int(self.lib.lbm_batch_fluid_nodes(self.ctx, 1 if active_only else 0))

@@ -54,6 +54,28 @@ def test_batch_equals_single_runs_fp32():
         assert np.array_equal(b.get_state(i), f), "case %d" % i
 
 
+@pytest.mark.parametrize("bpc", [-1, 0, 1, 2])
+def test_batch_schedules_agree(bpc):
+    """Every grid of the batched launch (k workgroups per CU, as many as fit, one
+    workgroup per (case, tile) entry) gives the single runs' FP32 result bit for bit."""
+    cases = _cases(4)
+    b = _batch(cases, lbm.LBM_F32)
+    b.set_schedule(16, bpc)
+    b.step(40)
+    for i, c in enumerate(cases):
+        lat = _single(c, lbm.LBM_F32)
+        lat.step(40)
+        f, _ = lat.get_state()
+        assert np.array_equal(b.get_state(i), f), "case %d" % i
+
+
+def test_batch_schedule_rejects_bad_values():
+    b = _batch(_cases(1), lbm.LBM_F32)
+    for ty, bpc in ((12, 0), (16, -2), (16, 65)):
+        with pytest.raises(Exception):
+            b.set_schedule(ty, bpc)
+
+
 def test_batch_fp64_matches_oracle():
     cases = _cases(3)
     b = _batch(cases, lbm.LBM_F64)
@@ -99,6 +121,27 @@ def test_batch_run_masks_converged_and_diverged():
     frozen = b.get_state(4).copy()
     b.step(10)
     assert np.array_equal(np.nan_to_num(b.get_state(4)), np.nan_to_num(frozen))
+
+
+def test_per_entry_grid_follows_the_masked_list():
+    """With one workgroup per (case, tile) entry the grid is resized when a case is
+    masked; the run matches the default grid's bit for bit (states, steps, status)."""
+    cases = _cases(4)
+    unstable = Case(C1.nx, C1.ny, C1.eos, C1.Tr, C1.tau, drop="circle", radius=25, noise=1e-4, seed=1)
+    params = [c.lbm_params(lbm.LBM_F64) for c in cases] + [unstable.lbm_params(lbm.LBM_F64)]
+    rhos = [c.rho0() for c in cases] + [unstable.rho0()]
+    mu_w = [float(c.mu_w_bottom) for c in cases] + [0.0]
+    runs = []
+    for bpc in (0, -1):
+        b = lbm.Batch(params, rhos, mu_w_bottom=mu_w)
+        b.set_schedule(16, bpc)
+        b.run(300, check_every=50, window=1, tol=1e-3)
+        runs.append(b)
+    sa, sb = runs[0].status(), runs[1].status()
+    assert sb["state"][4] == lbm.Batch.DIVERGED
+    assert np.array_equal(sa["state"], sb["state"]) and np.array_equal(sa["steps"], sb["steps"])
+    for i in range(4):
+        assert np.array_equal(runs[0].get_state(i), runs[1].get_state(i)), "case %d" % i
 
 
 def test_batch_residual_matches_oracle():

@@ -148,3 +148,9 @@ def test_contact_angle_matches_oracle_and_truth(lbm, theta):
     t_ora, Lo, Ho, _ = oracle_contact_angle(rho, 3.6, base_row=1)
     assert abs(t_lib - theta) < 0.5
     assert abs(t_lib - t_ora) < 1e-9 and abs(L - Lo) < 1e-9 and abs(H - Ho) < 1e-9
+
+
+def test_null_handles_are_rejected(lbm):
+    lib = lbm.load_library()
+    assert lib.lbm_batch_set_schedule(None, 16, 0) == lbm.LBM_EINVAL
+    assert lib.lbm_set_tile(None, 16) == lbm.LBM_EINVAL
