@@ -42,6 +42,7 @@ const LayerDef LAYERS[] = {
 };
 constexpr int NL = sizeof(LAYERS) / sizeof(LAYERS[0]);
 enum { E0A, E0B, E1A, E1B, E2A, E2B, E3A, E3B, D2A, D2B, D1A, D1B, D0A, D0B, OUT };
+static_assert(NL == OUT + 1, "one enumerator per layer of the table");
 
 struct Layer {
     LayerDef d;

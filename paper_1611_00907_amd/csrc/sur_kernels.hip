@@ -476,7 +476,7 @@ __global__ __launch_bounds__(256) void mse_kernel(const float* __restrict__ y, c
     __shared__ double sh[256];
     sh[threadIdx.x] = s;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (unsigned o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
