@@ -227,8 +227,8 @@ lbm_status lbm_batch_tune(lbm_batch* b, int32_t trial_steps, int32_t* tile_y,
 
 /* Sets the tile height (8, 16 or 32) and the grid of the batched launch directly:
  * blocks_per_cu = k > 0 workgroups per compute unit, 0 as many as fit, -1 one
- * workgroup per (case, tile) entry.  LBM_EINVAL for other values.  Every schedule
- * computes the same step. */
+ * workgroup per (case, tile) entry (the schedule of a new batch, with tile height
+ * 16).  LBM_EINVAL for other values.  Every schedule computes the same step. */
 lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t tile_y, int32_t blocks_per_cu);
 
 /* Fluid nodes of all cases (active_only != 0: of the active ones); -1 for NULL. */

@@ -38,7 +38,7 @@ struct lbm_batch {
     int ntiles = 0;  // active tiles
     // schedule
     int tile_y = TILE_Y_DEFAULT;
-    int blocks_per_cu = 0;  // 0: the occupancy limit; -1: one workgroup per (case, tile) entry
+    int blocks_per_cu = -1;  // -1: one workgroup per (case, tile) entry; 0: the occupancy limit
     int grid = 0;
     int64_t step = 0;
     std::vector<int32_t> state;  // 0 active, 1 converged, 2 diverged
@@ -330,7 +330,7 @@ lbm_status lbm_batch_init(const lbm_params* cases, int32_t n, const double* cons
             return st;
         }
     }
-    st = set_schedule(b, TILE_Y_DEFAULT, 0);
+    st = set_schedule(b, TILE_Y_DEFAULT, -1);  // one workgroup per entry until tuned
     if (st != LBM_OK) {
         release(b);
         return st;

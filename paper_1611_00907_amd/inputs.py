@@ -45,7 +45,8 @@ def tanh_drop(nx: int, ny: int, rho_in: float, rho_out: float, radius: float, cx
               cy: float, width: float = 4.0) -> np.ndarray:
     """Circular drop: rho_in inside radius, rho_out outside, tanh interface of
     the given width (distance between the 12 % and 88 % points)."""
-    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    x = np.arange(nx, dtype=np.float64)[None, :]
     r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
     return 0.5 * (rho_in + rho_out) - 0.5 * (rho_in - rho_out) * np.tanh(2.0 * (r - radius) / width)
 
