@@ -121,6 +121,9 @@ lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* ms);
  *   12816, 12832, 25608, 25616
  *                     wider tiles, 100 * columns + rows (128 x 16, 128 x 32,
  *                     256 x 8, 256 x 16), 512 threads each;
+ *   1000016, 1000032  64 x 16 and 64 x 32 tiles whose ring loads are issued
+ *                     together with the tile's own loads (one memory round trip
+ *                     instead of two, more registers per thread);
  *   -1 .. -8          column marching: a workgroup owns a strip of at most 252
  *                     columns and marches up a segment of rows, keeping the
  *                     neighbouring rows' densities and chemical potentials on

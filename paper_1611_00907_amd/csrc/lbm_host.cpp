@@ -429,9 +429,10 @@ lbm_status lbm_tune(lbm_ctx* c, int32_t trial_steps, int32_t* tile_y, double* be
     double best = 1e300;
     int best_ty = c->A.tile_y;
     hipError_t e = hipSuccess;
-    int shapes[7 + MARCH_K_MAX], nshapes = 0;
+    int shapes[9 + MARCH_K_MAX], nshapes = 0;
     for (int ty : TILE_Y_CHOICES) shapes[nshapes++] = ty;
     for (int code : WIDE_TILE_CODES) shapes[nshapes++] = code;
+    for (int code : HOIST_CODES) shapes[nshapes++] = code;
     if (march_allowed(c->A, c->p.prec))
         for (int k = 1; k <= MARCH_K_MAX; ++k) shapes[nshapes++] = -k;
     for (int k = 0; k < nshapes; ++k) {
@@ -473,6 +474,7 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t tile_y) {
     bool ok = false;
     for (int ty : TILE_Y_CHOICES) ok = ok || ty == tile_y;
     for (int code : WIDE_TILE_CODES) ok = ok || code == tile_y;
+    for (int code : HOIST_CODES) ok = ok || code == tile_y;
     if (march_allowed(c->A, c->p.prec))
         ok = ok || (tile_y < 0 && -tile_y <= MARCH_K_MAX);
     if (!ok) return LBM_EINVAL;

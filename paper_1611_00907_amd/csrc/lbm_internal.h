@@ -23,6 +23,10 @@ constexpr int TILE_Y_CHOICES[3] = {8, 16, 32};
 // thread), each run by 512 threads.  A wider tile pulls a smaller fraction of
 // redundant ring nodes.
 constexpr int WIDE_TILE_CODES[4] = {12816, 12832, 25608, 25616};
+// 64-wide tiles whose ring pulls go out with the own pulls (one memory round trip
+// instead of two, more registers), as shape codes 1000000 + height.
+constexpr int HOIST_BASE = 1000000;
+constexpr int HOIST_CODES[2] = {HOIST_BASE + 16, HOIST_BASE + 32};
 
 // Column-marching shape: a workgroup of MARCH_NT lanes owns a strip of at most
 // MARCH_OWN columns (two halo lanes per side) and marches up a segment of rows.  A

@@ -290,6 +290,28 @@ struct TileLds {
     CT ms[TY + 2][TX + 2];  // chemical potential, tile + 1-node ring
 };
 
+// Ring slot q of a TX x TY tile's two-node density ring (2 (TX + 4) + 2 (TX + 4) +
+// 2 TY + 2 TY slots: the two rows below, the two rows above, the two columns on
+// the left, the two columns on the right) as its row r and column c in the
+// (TY + 4) x (TX + 4) density tile.
+template <int TY, int TX>
+__device__ __forceinline__ void ring_slot(int q, int& r, int& c) {
+    constexpr int RW = TX + 4;
+    if (q < 2 * RW) {
+        r = q / RW;
+        c = q % RW;
+    } else if (q < 4 * RW) {
+        r = TY + 2 + (q - 2 * RW) / RW;
+        c = (q - 2 * RW) % RW;
+    } else if (q < 4 * RW + 2 * TY) {
+        r = 2 + (q - 4 * RW) / 2;
+        c = (q - 4 * RW) % 2;
+    } else {
+        r = 2 + (q - 4 * RW - 2 * TY) / 2;
+        c = TX + 2 + (q - 4 * RW - 2 * TY) % 2;
+    }
+}
+
 // Own-node pulls of a TX x TY tile: thread (lx, ly) pulls the nine distributions
 // of its RPT nodes (column x0 + lx, rows y0 + ly + k TY/RPT).  All RPT pulls go
 // out before any wait; every thread pulls a fluid node (rows clamped into the
@@ -313,7 +335,9 @@ __device__ __forceinline__ void tile_pull(const LatticeArgs& A, const Planes<ST>
 // The rest of one tile of the step (MODE_STEP) or of the field output
 // (MODE_FIELDS), from the own nodes' pulled distributions f: densities of the
 // tile and its ring into LDS, chemical potential, force, collision and store.
-template <typename ST, int EOS, int MODE, int TY, int TX, int RPT>
+// HOIST: the ring's pulls go out right after the own pulls, before the first wait
+// (one memory round trip instead of two, at the cost of registers).
+template <typename ST, int EOS, int MODE, int TY, int TX, int RPT, bool HOIST = false>
 __device__ __forceinline__ void tile_rest(const LatticeArgs& A, const Planes<ST>& F, ST* __restrict__ fout,
                                           const typename Codec<ST>::CT* __restrict__ mu_w,
                                           double* __restrict__ out, int x0, int y0,
@@ -329,6 +353,33 @@ __device__ __forceinline__ void tile_rest(const LatticeArgs& A, const Planes<ST>
 
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     const bool small_x = A.nx < TX + 2, small_y = A.ny < TY + 2;
+
+    constexpr int RING = 2 * (TX + 4) * 2 + 2 * TY * 2;
+    constexpr int RPR = HOIST ? (RING + NT - 1) / NT : 1;  // ring slots per thread
+    CT fr[RPR][9];
+    int rpos[RPR];     // r * RW + c of the slot; -1: a spare slot
+    bool rfluid[RPR];  // the slot is a fluid node (its density is the sum of its pulls)
+    if constexpr (HOIST) {
+        const bool periodic = A.bottom == BC_PERIODIC;
+        const int y_lo = periodic ? 0 : 1, y_hi = periodic ? A.ny - 1 : A.ny - 2;
+#pragma unroll
+        for (int j = 0; j < RPR; ++j) {
+            const int q = threadIdx.x + j * NT;
+            const bool live = q < RING;
+            int r, c;
+            ring_slot<TY, TX>(q, r, c);
+            if (!live) {  // a spare slot loads a line that the bottom ring row fetches anyway
+                r = 0;
+                c = q % RW;
+            }
+            int gy = y0 - 2 + r;
+            if (periodic) gy = wrap_fast(gy, A.ny, small_y);
+            rfluid[j] = live && gy >= y_lo && gy <= y_hi;
+            rpos[j] = live ? r * RW + c : -1;
+            pull9<ST, CT>(A, F, wrap_fast(x0 - 2 + c, A.nx, small_x), gy < y_lo ? y_lo : (gy > y_hi ? y_hi : gy),
+                          fr[j]);
+        }
+    }
 
     // 1. own nodes: density and momentum from the pulls, density into LDS
     CT jx[RPT], jy[RPT];
@@ -366,24 +417,27 @@ __device__ __forceinline__ void tile_rest(const LatticeArgs& A, const Planes<ST>
         }
     }
 
-    // 2. the two-node ring of densities around the tile
-    constexpr int RING = 2 * RW * 2 + 2 * TY * 2;
-    for (int q = threadIdx.x; q < RING; q += NT) {
-        int r, c;
-        if (q < 2 * RW) {
-            r = q / RW;
-            c = q % RW;
-        } else if (q < 4 * RW) {
-            r = TY + 2 + (q - 2 * RW) / RW;
-            c = (q - 2 * RW) % RW;
-        } else if (q < 4 * RW + 2 * TY) {
-            r = 2 + (q - 4 * RW) / 2;
-            c = (q - 4 * RW) % 2;
-        } else {
-            r = 2 + (q - 4 * RW - 2 * TY) / 2;
-            c = TX + 2 + (q - 4 * RW - 2 * TY) % 2;
+    // 2. the two-node ring of densities around the tile (Eq 28 for solid rows)
+    if constexpr (HOIST) {
+        CT* rs_flat = &rs[0][0];
+#pragma unroll
+        for (int j = 0; j < RPR; ++j) {
+            if (rpos[j] < 0) continue;
+            CT r;
+            if (rfluid[j]) {
+                r = sum9(fr[j]);
+            } else {
+                const int rr = rpos[j] / RW, cc = rpos[j] % RW;
+                r = node_rho<ST, CT>(A, F, wrap_fast(x0 - 2 + cc, A.nx, small_x), y0 - 2 + rr, small_y);
+            }
+            rs_flat[rpos[j]] = r;
         }
-        rs[r][c] = node_rho<ST, CT>(A, F, wrap_fast(x0 - 2 + c, A.nx, small_x), y0 - 2 + r, small_y);
+    } else {
+        for (int q = threadIdx.x; q < RING; q += NT) {
+            int r, c;
+            ring_slot<TY, TX>(q, r, c);
+            rs[r][c] = node_rho<ST, CT>(A, F, wrap_fast(x0 - 2 + c, A.nx, small_x), y0 - 2 + r, small_y);
+        }
     }
     if (cpb || cpt) {
 #pragma unroll
@@ -474,7 +528,7 @@ __device__ __forceinline__ void tile_rest(const LatticeArgs& A, const Planes<ST>
 
 // One TX x TY tile of the step or of the field output, run by a workgroup of
 // TX * TY / RPT threads, RPT nodes of one column per thread.
-template <typename ST, int EOS, int MODE, int TY, int TX = TILE_X, int RPT = ROWS_PER_THREAD>
+template <typename ST, int EOS, int MODE, int TY, int TX = TILE_X, int RPT = ROWS_PER_THREAD, bool HOIST = false>
 __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __restrict__ fin,
                                           ST* __restrict__ fout,
                                           const typename Codec<ST>::CT* __restrict__ mu_w,
@@ -486,11 +540,11 @@ __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __rest
     for (int i = 0; i < 9; ++i) F.p[i] = fin + (long long)i * A.plane;
     CT f[RPT][9];
     tile_pull<ST, TY, TX, RPT>(A, F, x0, y0, f);
-    tile_rest<ST, EOS, MODE, TY, TX, RPT>(A, F, fout, mu_w, out, x0, y0, f, L);
+    tile_rest<ST, EOS, MODE, TY, TX, RPT, HOIST>(A, F, fout, mu_w, out, x0, y0, f, L);
 }
 
 // One lattice: one workgroup per tile.
-template <typename ST, int EOS, int MODE, int TY, int TX = TILE_X, int RPT = ROWS_PER_THREAD>
+template <typename ST, int EOS, int MODE, int TY, int TX = TILE_X, int RPT = ROWS_PER_THREAD, bool HOIST = false>
 __global__ __launch_bounds__(TX * TY / RPT) void step_kernel(LatticeArgs A, const ST* __restrict__ fin,
                                                             ST* __restrict__ fout,
                                                             const typename Codec<ST>::CT* __restrict__ mu_w,
@@ -498,7 +552,7 @@ __global__ __launch_bounds__(TX * TY / RPT) void step_kernel(LatticeArgs A, cons
     __shared__ TileLds<typename Codec<ST>::CT, TY, TX> L;
     const int t = tile_of_block(blockIdx.x, gridDim.x);
     const int tiles_x = (A.nx + TX - 1) / TX;
-    step_tile<ST, EOS, MODE, TY, TX, RPT>(A, fin, fout, mu_w, out, (t % tiles_x) * TX, (t / tiles_x) * TY, L);
+    step_tile<ST, EOS, MODE, TY, TX, RPT, HOIST>(A, fin, fout, mu_w, out, (t % tiles_x) * TX, (t / tiles_x) * TY, L);
 }
 
 // Many lattices in one persistent launch: each workgroup walks a contiguous range
@@ -1151,13 +1205,13 @@ __global__ void get_state_kernel(LatticeArgs A, const ST* __restrict__ fstore, d
     for (int i = 0; i < 9; ++i) f_out[(long long)i * n + c] = double(f[i]);
 }
 
-template <typename ST, int EOS, int MODE, int TY, int TX, int RPT>
+template <typename ST, int EOS, int MODE, int TY, int TX, int RPT, bool HOIST = false>
 hipError_t step_launch(const LatticeArgs& A, const void* fin, void* fout, const void* mu_w, double* out,
                        hipStream_t s) {
     using CT = typename Codec<ST>::CT;
     const int tiles = ((A.nx + TX - 1) / TX) * ((A.ny + TY - 1) / TY);
     (void)hipGetLastError();  // drop any error left by earlier runtime calls
-    hipLaunchKernelGGL((step_kernel<ST, EOS, MODE, TY, TX, RPT>), dim3(tiles), dim3(TX * TY / RPT), 0, s, A,
+    hipLaunchKernelGGL((step_kernel<ST, EOS, MODE, TY, TX, RPT, HOIST>), dim3(tiles), dim3(TX * TY / RPT), 0, s, A,
                        (const ST*)fin, (ST*)fout, (const CT*)mu_w, out);
     return hipGetLastError();
 }
@@ -1173,6 +1227,8 @@ hipError_t step_ty(int tile_y, const LatticeArgs& A, const void* fin, void* fout
     case 12832: return step_launch<ST, EOS, MODE, 32, 128, 8>(A, fin, fout, mu_w, out, s);
     case 25608: return step_launch<ST, EOS, MODE, 8, 256, 4>(A, fin, fout, mu_w, out, s);
     case 25616: return step_launch<ST, EOS, MODE, 16, 256, 8>(A, fin, fout, mu_w, out, s);
+    case HOIST_BASE + 16: return step_launch<ST, EOS, MODE, 16, 64, 4, true>(A, fin, fout, mu_w, out, s);
+    case HOIST_BASE + 32: return step_launch<ST, EOS, MODE, 32, 64, 4, true>(A, fin, fout, mu_w, out, s);
     default: return hipErrorInvalidValue;
     }
 }

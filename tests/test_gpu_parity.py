@@ -87,10 +87,11 @@ def test_fp64_ragged_and_tiny(nx, ny, walls):
 WIDE_CASES = RAGGED + [(300, 70, False), (257, 37, True), (520, 130, True), (129, 33, True)]
 
 
-@pytest.mark.parametrize("code", [12816, 12832, 25608, 25616])
+@pytest.mark.parametrize("code", [12816, 12832, 25608, 25616, 1000016, 1000032])
 @pytest.mark.parametrize("nx,ny,walls", WIDE_CASES)
 def test_fp64_wide_tiles(nx, ny, walls, code):
-    """Tiles of 128 and 256 columns (shape code 100 * width + height) on ragged,
+    """Tiles of 128 and 256 columns (shape code 100 * width + height) and the
+    64-wide tiles with the ring pulls issued up front (1000000 + height) on ragged,
     tiny and walled lattices."""
     c = _ragged_case(nx, ny, walls)
     lat, ora = _gpu(c, lbm.LBM_F64), c.oracle()
@@ -156,7 +157,7 @@ def test_fp64_per_node_wall_mu_and_cp_top():
     _compare_state(lat, ora, 1e-10)
 
 
-@pytest.mark.parametrize("code", [8, 16, 32, 12816, 12832, 25608, 25616])
+@pytest.mark.parametrize("code", [8, 16, 32, 12816, 12832, 25608, 25616, 1000016, 1000032])
 @pytest.mark.parametrize("nx,ny", [(150, 33), (300, 65), (70, 17)])
 def test_fp64_cp_walls_every_tile_shape(nx, ny, code):
     """CP walls on both sides with per-column surface chemical potentials, on every
@@ -272,7 +273,7 @@ def test_reduced_storage_one_and_ten_steps(prec, u):
     _compare_state(lat, ora, 12 * u)
 
 
-@pytest.mark.parametrize("shape", [16, 32, 25616, -4])
+@pytest.mark.parametrize("shape", [16, 32, 25608, 25616, 1000032, -4])
 def test_fp32_full_size_config2(shape):
     """1024 x 1024 wetting case in both launch shapes: every node against the
     oracle after 20 steps."""
@@ -283,7 +284,7 @@ def test_fp32_full_size_config2(shape):
     _compare_state(lat, ora, 2e-5)
 
 
-@pytest.mark.parametrize("shape", [16, 25616, -2])
+@pytest.mark.parametrize("shape", [16, 25608, 25616, 1000032, -2])
 def test_fp32_full_size_4096_sampled(shape):
     """4096^2 spinodal case: after k steps a node depends on the initial field within
     3k nodes, so periodic oracle windows with a 3k margin give exact samples."""
