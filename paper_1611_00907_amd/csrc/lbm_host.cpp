@@ -7,6 +7,7 @@
 #include <cstring>
 #include <algorithm>
 #include <new>
+#include <iterator>
 #include <vector>
 
 #include "lbm_common.h"
@@ -429,7 +430,9 @@ lbm_status lbm_tune(lbm_ctx* c, int32_t trial_steps, int32_t* tile_y, double* be
     double best = 1e300;
     int best_ty = c->A.tile_y;
     hipError_t e = hipSuccess;
-    int shapes[9 + MARCH_K_MAX], nshapes = 0;
+    constexpr size_t MAX_SHAPES = std::size(TILE_Y_CHOICES) + std::size(WIDE_TILE_CODES) + std::size(HOIST_CODES) +
+                                  MARCH_K_MAX;
+    int shapes[MAX_SHAPES], nshapes = 0;
     for (int ty : TILE_Y_CHOICES) shapes[nshapes++] = ty;
     for (int code : WIDE_TILE_CODES) shapes[nshapes++] = code;
     for (int code : HOIST_CODES) shapes[nshapes++] = code;
