@@ -395,6 +395,92 @@ __global__ void avgpool2_kernel(TView in, TView out, int N, int H, int W, int C)
     }
 }
 
+// Four channels per thread (channel counts, strides and offsets multiples of 4, so
+// the BF16 accesses are 8-byte and the FP32 ones 16-byte aligned).
+__device__ __forceinline__ void ld4(const uint16_t* p, float v[4]) {
+    const uint2 u = *reinterpret_cast<const uint2*>(p);
+    v[0] = bf2f(uint16_t(u.x));
+    v[1] = bf2f(uint16_t(u.x >> 16));
+    v[2] = bf2f(uint16_t(u.y));
+    v[3] = bf2f(uint16_t(u.y >> 16));
+}
+__device__ __forceinline__ void st4(uint16_t* p, const float v[4]) {
+    uint2 u;
+    u.x = uint32_t(f2bf(v[0])) | (uint32_t(f2bf(v[1])) << 16);
+    u.y = uint32_t(f2bf(v[2])) | (uint32_t(f2bf(v[3])) << 16);
+    *reinterpret_cast<uint2*>(p) = u;
+}
+
+__global__ void upsample2_v4_kernel(TView in, TView out, int N, int H, int W, int C) {
+    const int C4 = C / 4;
+    const long long total = (long long)N * H * W * C4;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = int(i % C4) * 4;
+        const long long q = i / C4;
+        const int x = int(q % W);
+        const long long t = q / W;
+        const int y = int(t % H);
+        const long long n = t / H;
+        *reinterpret_cast<uint2*>(out.p + q * out.cs + out.co + c) = *reinterpret_cast<const uint2*>(
+            in.p + ((n * (H / 2) + y / 2) * (W / 2) + x / 2) * in.cs + in.co + c);
+    }
+}
+
+__global__ void upsample2_grad_v4_kernel(const float* __restrict__ dcat, int dcs, int dco, TView act, TView dz,
+                                         int N, int Ho, int Wo, int C) {
+    const int C4 = C / 4;
+    const long long total = (long long)N * Ho * Wo * C4;
+    const int H = 2 * Ho, W = 2 * Wo;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = int(i % C4) * 4;
+        const long long q = i / C4;
+        const int x = int(q % Wo);
+        const long long t = q / Wo;
+        const int y = int(t % Ho);
+        const long long n = t / Ho;
+        float s[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const float4 g =
+                    *reinterpret_cast<const float4*>(dcat + ((n * H + 2 * y + dy) * W + 2 * x + dx) * dcs + dco + c);
+                s[0] += g.x;
+                s[1] += g.y;
+                s[2] += g.z;
+                s[3] += g.w;
+            }
+        float mk[4], o[4];
+        ld4(act.p + q * act.cs + act.co + c, mk);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[k] = mk[k] > 0.f ? s[k] : 0.f;
+        st4(dz.p + q * dz.cs + dz.co + c, o);
+    }
+}
+
+__global__ void skip_grad_v4_kernel(const float* __restrict__ dcat, int dcs, int dco, const float* __restrict__ dpool,
+                                    int pcs, TView act, TView dz, int N, int H, int W, int C) {
+    const int C4 = C / 4;
+    const long long total = (long long)N * H * W * C4;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = int(i % C4) * 4;
+        const long long q = i / C4;
+        const int x = int(q % W);
+        const long long t = q / W;
+        const int y = int(t % H);
+        const long long n = t / H;
+        const float4 gp = *reinterpret_cast<const float4*>(dpool + ((n * (H / 2) + y / 2) * (W / 2) + x / 2) * pcs + c);
+        const float4 gc = *reinterpret_cast<const float4*>(dcat + q * dcs + dco + c);
+        const float sum[4] = {gc.x + 0.25f * gp.x, gc.y + 0.25f * gp.y, gc.z + 0.25f * gp.z, gc.w + 0.25f * gp.w};
+        float mk[4], o[4];
+        ld4(act.p + q * act.cs + act.co + c, mk);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[k] = mk[k] > 0.f ? sum[k] : 0.f;
+        st4(dz.p + q * dz.cs + dz.co + c, o);
+    }
+}
+
 // out (H, W) = in (H/2, W/2) repeated 2 x 2.
 __global__ void upsample2_kernel(TView in, TView out, int N, int H, int W, int C) {
     const long long total = (long long)N * H * W * C;
@@ -588,7 +674,16 @@ hipError_t avgpool2(TView in, TView out, int N, int H, int W, int C, hipStream_t
     return hipGetLastError();
 }
 
+static bool by4(int C, const TView& a, const TView& b) {
+    return C % 4 == 0 && a.cs % 4 == 0 && a.co % 4 == 0 && b.cs % 4 == 0 && b.co % 4 == 0;
+}
+
 hipError_t upsample2(TView in, TView out, int N, int H, int W, int C, hipStream_t s) {
+    if (by4(C, in, out)) {
+        hipLaunchKernelGGL(upsample2_v4_kernel, dim3(grid_for((long long)N * H * W * C / 4)), dim3(256), 0, s, in,
+                           out, N, H, W, C);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(upsample2_kernel, dim3(grid_for((long long)N * H * W * C)), dim3(256), 0, s, in, out, N, H, W,
                        C);
     return hipGetLastError();
@@ -596,6 +691,11 @@ hipError_t upsample2(TView in, TView out, int N, int H, int W, int C, hipStream_
 
 hipError_t upsample2_grad(const float* dcat, int dcs, int dco, TView act, TView dz, int N, int Ho, int Wo, int C,
                           hipStream_t s) {
+    if (by4(C, act, dz) && dcs % 4 == 0 && dco % 4 == 0) {
+        hipLaunchKernelGGL(upsample2_grad_v4_kernel, dim3(grid_for((long long)N * Ho * Wo * C / 4)), dim3(256), 0, s,
+                           dcat, dcs, dco, act, dz, N, Ho, Wo, C);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(upsample2_grad_kernel, dim3(grid_for((long long)N * Ho * Wo * C)), dim3(256), 0, s, dcat, dcs,
                        dco, act, dz, N, Ho, Wo, C);
     return hipGetLastError();
@@ -603,6 +703,11 @@ hipError_t upsample2_grad(const float* dcat, int dcs, int dco, TView act, TView 
 
 hipError_t skip_grad(const float* dcat, int dcs, int dco, const float* dpool, int pcs, TView act, TView dz, int N,
                      int H, int W, int C, hipStream_t s) {
+    if (by4(C, act, dz) && dcs % 4 == 0 && dco % 4 == 0 && pcs % 4 == 0) {
+        hipLaunchKernelGGL(skip_grad_v4_kernel, dim3(grid_for((long long)N * H * W * C / 4)), dim3(256), 0, s, dcat,
+                           dcs, dco, dpool, pcs, act, dz, N, H, W, C);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(skip_grad_kernel, dim3(grid_for((long long)N * H * W * C)), dim3(256), 0, s, dcat, dcs, dco,
                        dpool, pcs, act, dz, N, H, W, C);
     return hipGetLastError();
