@@ -204,7 +204,49 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
         __syncthreads();  // the next block of channels overwrites the LDS
     }
 
-    // epilogue: lane holds pixels (y0 + 2 wave + m, x0 + 4 g + i), channel co_base + 16 n + r
+    // BF16 epilogues: bias and ReLU in registers, the 128 x 32 tile through LDS (the
+    // input halo's space, free after the last barrier), then 16-byte stores of 8
+    // channels (the mask of EPI_MASK_BF16 read 16 bytes at a time as well)
+    if (a.epi != EPI_F32) {
+        uint16_t* ost = xin;  // [LT_H * LT_W pixels][LT_CO channels]
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            const int cl = 16 * n + r, co = co_base + cl;
+            const float bias = (a.bias != nullptr && co < a.cout) ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float v = acc[m][n][i] + bias;
+                    if (a.epi == EPI_RELU_BF16) v = v > 0.f ? v : 0.f;
+                    ost[((2 * wave + m) * LT_W + 4 * g + i) * LT_CO + cl] = f2bf(v);
+                }
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < LT_H * LT_W * (LT_CO / 8); q += 256) {
+            const int pl = q / (LT_CO / 8), cg = q % (LT_CO / 8);
+            const int y = y0 + pl / LT_W, x = x0 + pl % LT_W, co = co_base + 8 * cg;
+            if (y >= a.H || x >= a.W || co >= a.cout) continue;
+            const long long p = ((long long)img * a.H + y) * a.W + x;
+            uint4 v = *reinterpret_cast<const uint4*>(ost + pl * LT_CO + 8 * cg);
+            if (a.epi == EPI_MASK_BF16) {
+                const uint4 mk = *reinterpret_cast<const uint4*>(a.mask.p + p * a.mask.cs + a.mask.co + co);
+                auto keep = [](uint32_t w, uint32_t m) {  // zero each BF16 half whose mask is not > 0
+                    const uint32_t lo = bf2f(uint16_t(m)) > 0.f ? 0x0000ffffu : 0u;
+                    const uint32_t hi = bf2f(uint16_t(m >> 16)) > 0.f ? 0xffff0000u : 0u;
+                    return w & (lo | hi);
+                };
+                v.x = keep(v.x, mk.x);
+                v.y = keep(v.y, mk.y);
+                v.z = keep(v.z, mk.z);
+                v.w = keep(v.w, mk.w);
+            }
+            *reinterpret_cast<uint4*>(a.out.p + p * a.out.cs + a.out.co + co) = v;
+        }
+        return;
+    }
+
+    // FP32 epilogue: lane holds pixels (y0 + 2 wave + m, x0 + 4 g + i), channel co_base + 16 n + r
 #pragma unroll
     for (int n = 0; n < 2; ++n) {
         const int co = co_base + 16 * n + r;
@@ -628,7 +670,9 @@ int grid_for(long long n) {
 hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
     const long long npx = (long long)a.N * a.H * a.W;
     (void)hipGetLastError();
-    if (a.cout_p % LT_CO == 0) {
+    const bool views8 = a.cout % 8 == 0 && a.out.cs % 8 == 0 && a.out.co % 8 == 0 &&
+                        (a.epi != EPI_MASK_BF16 || (a.mask.cs % 8 == 0 && a.mask.co % 8 == 0));
+    if (a.cout_p % LT_CO == 0 && (a.epi == EPI_F32 || views8)) {
         const long long blocks = (long long)a.N * ((a.H + LT_H - 1) / LT_H) * ((a.W + LT_W - 1) / LT_W) *
                                  (a.cout_p / LT_CO);
         hipLaunchKernelGGL(conv3x3_lds_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, a);
