@@ -273,6 +273,31 @@ def test_reduced_storage_one_and_ten_steps(prec, u):
     _compare_state(lat, ora, 12 * u)
 
 
+@pytest.mark.parametrize("prec,u", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+def test_reduced_storage_every_tile_shape(prec, u):
+    """16-bit deviation storage through every tile shape: the per-node arithmetic and
+    its roundings do not depend on the tiling, so the stored states agree bit for
+    bit; column marching (the same arithmetic, possibly contracted differently by
+    the compiler) agrees within a few stored roundings."""
+    p = {"f16": lbm.LBM_F16DEV, "bf16": lbm.LBM_BF16DEV}[prec]
+    ref = _gpu(WALLED_PR, p)
+    ref.set_tile(16)
+    ref.step(20)
+    f0, _ = ref.get_state()
+    for code in (8, 32, 12816, 12832, 25608, 25616, 1000016, 1000032):
+        lat = _gpu(WALLED_PR, p)
+        lat.set_tile(code)
+        lat.step(20)
+        f, _ = lat.get_state()
+        assert np.array_equal(f, f0), code
+    for k in (-2, -4):
+        lat = _gpu(WALLED_PR, p)
+        lat.set_tile(k)
+        lat.step(20)
+        f, _ = lat.get_state()
+        assert rel_err(f, f0) < 4 * u, (k, rel_err(f, f0))
+
+
 @pytest.mark.parametrize("shape", [16, 32, 25608, 25616, 1000032, -4])
 def test_fp32_full_size_config2(shape):
     """1024 x 1024 wetting case in both launch shapes: every node against the
