@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
 // coordinates come from one division per 32 pixels and then by increments; inside
 // the image, the tap's source pixel is p + du W + dv.  The waves of the centre tap
 // and the first ci block also sum dZ for the bias gradient db[co] = sum_p dZ[p][co].
-template <int WM, int WN, bool PAIRED>
+template <int WM, int WN, bool PA, bool PB>
 __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(WgradArgs a) {
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -311,16 +311,18 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(WgradArgs a) {
     const int shift = du * a.W + dv;
     int co_a[WM], ci_b[WN];  // A rows / B columns of this lane
     bool co_ok[WM], ci_ok[WN];
-    // PAIRED (WM = WN = 2, even channel counts and offsets): tile m holds the
-    // channels of parity m, so one 32-bit load brings a lane both of its channels.
+    // PA / PB (2 tiles along that side; even channel count, stride and offset): tile
+    // m (n) holds the channels of parity m (n), so one 32-bit load brings a lane both
+    // of its channels of dZ (of X).
+    static_assert((!PA || WM == 2) && (!PB || WN == 2), "channel pairs need 2 tiles along that side");
 #pragma unroll
     for (int m = 0; m < WM; ++m) {
-        co_a[m] = PAIRED ? co_t * 32 + 2 * r + m : co_t * 16 * WM + 16 * m + r;
+        co_a[m] = PA ? co_t * 32 + 2 * r + m : co_t * 16 * WM + 16 * m + r;
         co_ok[m] = co_a[m] < a.cout;
     }
 #pragma unroll
     for (int n = 0; n < WN; ++n) {
-        ci_b[n] = PAIRED ? ci_t * 32 + 2 * r + n : ci_t * 16 * WN + 16 * n + r;
+        ci_b[n] = PB ? ci_t * 32 + 2 * r + n : ci_t * 16 * WN + 16 * n + r;
         ci_ok[n] = ci_b[n] < a.cin;
     }
     const bool bias = tap == 4 && ci_t == 0;  // wave-uniform
@@ -345,16 +347,19 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(WgradArgs a) {
             const int yy = y + du, xx = x + dv;
             const bool in = p < p_end, src = in && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
             const long long oz = (long long)p * a.dz.cs + a.dz.co, ox = (long long)(p + shift) * a.x.cs + a.x.co;
-            if constexpr (PAIRED) {
+            if constexpr (PA) {
                 const uint32_t va = (in && co_ok[0]) ? *reinterpret_cast<const uint32_t*>(a.dz.p + oz + co_a[0]) : 0u;
-                const uint32_t vb = (src && ci_ok[0]) ? *reinterpret_cast<const uint32_t*>(a.x.p + ox + ci_b[0]) : 0u;
                 ah[0][j] = uint16_t(va);
                 ah[1][j] = uint16_t(va >> 16);
-                bh[0][j] = uint16_t(vb);
-                bh[1][j] = uint16_t(vb >> 16);
             } else {
 #pragma unroll
                 for (int m = 0; m < WM; ++m) ah[m][j] = (in && co_ok[m]) ? a.dz.p[oz + co_a[m]] : uint16_t(0);
+            }
+            if constexpr (PB) {
+                const uint32_t vb = (src && ci_ok[0]) ? *reinterpret_cast<const uint32_t*>(a.x.p + ox + ci_b[0]) : 0u;
+                bh[0][j] = uint16_t(vb);
+                bh[1][j] = uint16_t(vb >> 16);
+            } else {
 #pragma unroll
                 for (int n = 0; n < WN; ++n) bh[n][j] = (src && ci_ok[n]) ? a.x.p[ox + ci_b[n]] : uint16_t(0);
             }
@@ -401,7 +406,7 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(WgradArgs a) {
         for (int n = 0; n < WN; ++n)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int co = PAIRED ? co_t * 32 + 2 * (4 * g + i) + m : co_t * 16 * WM + 16 * m + 4 * g + i;
+                const int co = PA ? co_t * 32 + 2 * (4 * g + i) + m : co_t * 16 * WM + 16 * m + 4 * g + i;
                 const int ci = ci_b[n];
                 if (co < a.cout && ci < a.cin)
                     atomicAdd(&a.dw[((size_t)tap * a.cout_p + co) * a.cin_p + ci], acc[m][n][i]);
@@ -413,6 +418,81 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(WgradArgs a) {
             v += __shfl_xor(v, 16);
             v += __shfl_xor(v, 32);
             if (g == 0 && co_ok[m]) atomicAdd(&a.db[co_a[m]], v);
+        }
+    }
+}
+
+// One output channel (the output layer): dW[tap][0][ci] = sum_p dZ[p] X[p shifted by
+// tap][ci] and db[0] = sum_p dZ[p] on the vector ALUs, where a matrix-core block would
+// be 1/32 full.  Lane k of a 16-lane group holds channels 2k and 2k + 1 for all nine
+// taps; group s of the block takes pixels p_begin + s, p_begin + s + 16, ... of the
+// block's run, so a wave reads four consecutive pixels' channel rows per tap.  Taps
+// that leave the image load the lane's own pixel and weigh it by zero (no branch
+// around the loads); a pass takes eight of the group's pixels at once.  The groups
+// meet in LDS and the block adds one partial sum per weight atomically.  Needs an
+// even channel count of at most 32 and even X strides.
+constexpr int C1_GROUPS = 16, C1_UNROLL = 8;
+__global__ __launch_bounds__(256) void conv3x3_wgrad_c1_kernel(WgradArgs a) {
+    __shared__ float part[C1_GROUPS][9 * 32 + 1];
+    const int k = threadIdx.x & 15, grp = threadIdx.x >> 4;
+    const int npx = a.N * a.H * a.W;  // the host keeps pixel indices below 2^31
+    const int p_begin = blockIdx.x * int(a.chunk_px);
+    const int p_end = p_begin < npx - int(a.chunk_px) ? p_begin + int(a.chunk_px) : npx;
+    const int ch = 2 * k < a.cin ? 2 * k : 0;  // lanes past the channels read channel 0, write nothing
+    const unsigned W = unsigned(a.W), H = unsigned(a.H);
+    float acc[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t][0] = acc[t][1] = 0.f;
+    float bsum = 0.f;
+    // C1_UNROLL pixels per pass, all their loads issued before the arithmetic; a pixel
+    // past the run stands in as the run's first pixel of this group, weighed by zero
+    for (int p0 = p_begin + grp; p0 < p_end; p0 += C1_UNROLL * C1_GROUPS) {
+        float z[C1_UNROLL];
+        uint32_t v[C1_UNROLL][9];
+        bool in[C1_UNROLL][9];
+#pragma unroll
+        for (int u = 0; u < C1_UNROLL; ++u) {
+            const bool live = p0 + u * C1_GROUPS < p_end;
+            const int p = live ? p0 + u * C1_GROUPS : p0;
+            const unsigned q = unsigned(p) / W;
+            const int x = int(unsigned(p) - q * W), y = int(q % H);
+            const float zz = bf2f(a.dz.p[(long long)p * a.dz.cs + a.dz.co]);
+            z[u] = live ? zz : 0.f;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int du = t / 3 - 1, dv = t % 3 - 1;
+                in[u][t] = y + du >= 0 && y + du < a.H && x + dv >= 0 && x + dv < a.W;
+                const int src = in[u][t] ? p + du * a.W + dv : p;
+                v[u][t] = *reinterpret_cast<const uint32_t*>(a.x.p + (long long)src * a.x.cs + a.x.co + ch);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < C1_UNROLL; ++u) {
+            bsum += z[u];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const float w = in[u][t] ? z[u] : 0.f;
+                acc[t][0] += w * bf2f(uint16_t(v[u][t]));
+                acc[t][1] += w * bf2f(uint16_t(v[u][t] >> 16));
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        part[grp][t * 32 + 2 * k] = acc[t][0];
+        part[grp][t * 32 + 2 * k + 1] = acc[t][1];
+    }
+    if (k == 0) part[grp][9 * 32] = bsum;
+    __syncthreads();
+    for (int i = threadIdx.x; i <= 9 * 32; i += 256) {
+        float v = 0.f;
+#pragma unroll
+        for (int g2 = 0; g2 < C1_GROUPS; ++g2) v += part[g2][i];
+        if (i == 9 * 32) {
+            atomicAdd(&a.db[0], v);
+        } else {
+            const int tap = i / 32, ci = i % 32;
+            if (ci < a.cin) atomicAdd(&a.dw[(size_t)tap * a.cout_p * a.cin_p + ci], v);
         }
     }
 }
@@ -683,14 +763,14 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int WM, int WN, bool PAIRED>
+template <int WM, int WN, bool PA, bool PB>
 hipError_t wgrad_launch(const WgradArgs& a, hipStream_t s) {
     const long long npx = (long long)a.N * a.H * a.W;
     const long long chunks = (npx + a.chunk_px - 1) / a.chunk_px;
     const long long tiles = 9LL * ((a.cout + 16 * WM - 1) / (16 * WM)) * ((a.cin + 16 * WN - 1) / (16 * WN));
     const long long waves = chunks * tiles;
     (void)hipGetLastError();
-    hipLaunchKernelGGL((conv3x3_wgrad_kernel<WM, WN, PAIRED>), dim3(int((waves + 3) / 4)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((conv3x3_wgrad_kernel<WM, WN, PA, PB>), dim3(int((waves + 3) / 4)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -700,8 +780,8 @@ hipError_t wgrad_launch(const WgradArgs& a, hipStream_t s) {
 hipError_t conv3x3_wgrad(const WgradArgs& a, hipStream_t s) {
     const long long npx = (long long)a.N * a.H * a.W;
     if (npx + a.chunk_px >= (1LL << 31) || a.chunk_px % 32 != 0) return hipErrorInvalidValue;
-    const bool even = a.cout % 2 == 0 && a.cin % 2 == 0 && a.dz.cs % 2 == 0 && a.dz.co % 2 == 0 &&
-                      a.x.cs % 2 == 0 && a.x.co % 2 == 0;
+    const bool even_a = a.cout % 2 == 0 && a.dz.cs % 2 == 0 && a.dz.co % 2 == 0;
+    const bool even_b = a.cin % 2 == 0 && a.x.cs % 2 == 0 && a.x.co % 2 == 0;
     // pixel runs sized for about 16384 waves (512 to 8192 pixels): long runs for the
     // large layers (fewer atomic block updates), short ones for the small layers
     WgradArgs b = a;
@@ -709,7 +789,19 @@ hipError_t conv3x3_wgrad(const WgradArgs& a, hipStream_t s) {
     long long c = npx * tiles / 16384;
     c = c < 512 ? 512 : (c > 8192 ? 8192 : c);
     b.chunk_px = c / 32 * 32;
-    return even ? wgrad_launch<2, 2, true>(b, s) : wgrad_launch<2, 2, false>(b, s);
+    if (a.cout == 1 && even_b && a.cin <= 32) {  // the output layer
+        // runs of 256 to 8192 pixels for about 2048 blocks
+        long long r = (npx / 2048 + C1_GROUPS - 1) / C1_GROUPS * C1_GROUPS;
+        b.chunk_px = r < 256 ? 256 : (r > 8192 ? 8192 : r);
+        (void)hipGetLastError();
+        hipLaunchKernelGGL(conv3x3_wgrad_c1_kernel, dim3(unsigned((npx + b.chunk_px - 1) / b.chunk_px)), dim3(256),
+                           0, s, b);
+        return hipGetLastError();
+    }
+    if (even_a && even_b) return wgrad_launch<2, 2, true, true>(b, s);
+    if (even_b) return wgrad_launch<2, 2, false, true>(b, s);
+    if (even_a) return wgrad_launch<2, 2, true, false>(b, s);
+    return wgrad_launch<2, 2, false, false>(b, s);
 }
 
 hipError_t avgpool2(TView in, TView out, int N, int H, int W, int C, hipStream_t s) {

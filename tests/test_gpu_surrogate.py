@@ -60,8 +60,11 @@ def test_forward_other_sizes(size):
     assert np.linalg.norm(y - yo) / np.linalg.norm(yo) < 0.03
 
 
-def test_gradients_match_oracle():
-    net, p32, x, t = _setup()
+@pytest.mark.parametrize("size,n", [(32, 2), (24, 3)])
+def test_gradients_match_oracle(size, n):
+    """(24, 3): 1728 pixels per layer-0 map, so the weight-gradient pixel runs end
+    ragged (the one-output-channel kernel's last block has 192 of its 256 pixels)."""
+    net, p32, x, t = _setup(size=size, n=n)
     g, loss = net.gradients(x.astype(np.float32), t.astype(np.float32))
     yo, cache = S.forward(p32, _oracle_input(x))
     lo, dy = S.mse(yo, t[:, None])
