@@ -532,107 +532,144 @@ __device__ __forceinline__ void st4(uint16_t* p, const float v[4]) {
     u.y = uint32_t(f2bf(v[2])) | (uint32_t(f2bf(v[3])) << 16);
     *reinterpret_cast<uint2*>(p) = u;
 }
+// V = 4 or 8 channels: one 8- or 16-byte access (channel counts, strides and offsets
+// multiples of V).
+template <int V>
+__device__ __forceinline__ void ldv(const uint16_t* p, float v[V]) {
+    ld4(p, v);
+    if constexpr (V == 8) ld4(p + 4, v + 4);
+}
+template <int V>
+__device__ __forceinline__ void stv(uint16_t* p, const float v[V]) {
+    if constexpr (V == 8) {
+        uint4 u;
+        u.x = uint32_t(f2bf(v[0])) | (uint32_t(f2bf(v[1])) << 16);
+        u.y = uint32_t(f2bf(v[2])) | (uint32_t(f2bf(v[3])) << 16);
+        u.z = uint32_t(f2bf(v[4])) | (uint32_t(f2bf(v[5])) << 16);
+        u.w = uint32_t(f2bf(v[6])) | (uint32_t(f2bf(v[7])) << 16);
+        *reinterpret_cast<uint4*>(p) = u;
+    } else {
+        st4(p, v);
+    }
+}
+template <int V>
+__device__ __forceinline__ void ldf(const float* p, float v[V]) {
+#pragma unroll
+    for (int k = 0; k < V; k += 4) {
+        const float4 g = *reinterpret_cast<const float4*>(p + k);
+        v[k] = g.x;
+        v[k + 1] = g.y;
+        v[k + 2] = g.z;
+        v[k + 3] = g.w;
+    }
+}
 
-// Index type I of the four-channel kernels: 32-bit where the element count stays
-// below 2^31 (a division by a run-time size then costs a fraction of a 64-bit one),
+// Index type I of the four- and eight-channel kernels: 32-bit where the element count
+// stays below 2^31 (a division by a run-time size then costs a fraction of a 64-bit one),
 // 64-bit otherwise; element offsets, and the fine-grid pixel indices of the kernels
 // that count coarse pixels, are formed in 64 bits either way.
-template <typename I>
-__global__ void avgpool2_v4_kernel(TView in, TView out, int N, int H, int W, int C) {
-    const int Ho = H / 2, Wo = W / 2, C4 = C / 4;
-    const I total = I(N) * I(Ho) * I(Wo) * I(C4);
+template <typename I, int V>
+__global__ void avgpool2_vec_kernel(TView in, TView out, int N, int H, int W, int C) {
+    const int Ho = H / 2, Wo = W / 2, CV = C / V;
+    const I total = I(N) * I(Ho) * I(Wo) * I(CV);
     for (I i = I(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += I(gridDim.x) * blockDim.x) {
-        const int c = int(i % I(C4)) * 4;
-        const I q = i / I(C4);
+        const int c = int(i % I(CV)) * V;
+        const I q = i / I(CV);
         const int x = int(q % I(Wo));
         const I t = q / I(Wo);
         const int y = int(t % I(Ho));
         const I n = t / I(Ho);
-        float sum[4] = {0.f, 0.f, 0.f, 0.f};
+        float sum[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) sum[k] = 0.f;
         for (int dy = 0; dy < 2; ++dy)
             for (int dx = 0; dx < 2; ++dx) {
                 const long long pix = ((long long)n * H + 2 * y + dy) * W + 2 * x + dx;  // the fine grid
-                float v[4];
-                ld4(in.p + pix * in.cs + in.co + c, v);
+                float v[V];
+                ldv<V>(in.p + pix * in.cs + in.co + c, v);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) sum[k] += v[k];
+                for (int k = 0; k < V; ++k) sum[k] += v[k];
             }
-        float o[4];
+        float o[V];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) o[k] = 0.25f * sum[k];
-        st4(out.p + (long long)q * out.cs + out.co + c, o);
+        for (int k = 0; k < V; ++k) o[k] = 0.25f * sum[k];
+        stv<V>(out.p + (long long)q * out.cs + out.co + c, o);
     }
 }
 
-template <typename I>
-__global__ void upsample2_v4_kernel(TView in, TView out, int N, int H, int W, int C) {
-    const int C4 = C / 4;
-    const I total = I(N) * I(H) * I(W) * I(C4);
+template <typename I, int V>
+__global__ void upsample2_vec_kernel(TView in, TView out, int N, int H, int W, int C) {
+    const int CV = C / V;
+    const I total = I(N) * I(H) * I(W) * I(CV);
     for (I i = I(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += I(gridDim.x) * blockDim.x) {
-        const int c = int(i % I(C4)) * 4;
-        const I q = i / I(C4);
+        const int c = int(i % I(CV)) * V;
+        const I q = i / I(CV);
         const int x = int(q % I(W));
         const I t = q / I(W);
         const int y = int(t % I(H));
         const I n = t / I(H);
         const I src = (n * I(H / 2) + I(y / 2)) * I(W / 2) + I(x / 2);
-        *reinterpret_cast<uint2*>(out.p + (long long)q * out.cs + out.co + c) =
-            *reinterpret_cast<const uint2*>(in.p + (long long)src * in.cs + in.co + c);
+        if constexpr (V == 8)
+            *reinterpret_cast<uint4*>(out.p + (long long)q * out.cs + out.co + c) =
+                *reinterpret_cast<const uint4*>(in.p + (long long)src * in.cs + in.co + c);
+        else
+            *reinterpret_cast<uint2*>(out.p + (long long)q * out.cs + out.co + c) =
+                *reinterpret_cast<const uint2*>(in.p + (long long)src * in.cs + in.co + c);
     }
 }
 
-template <typename I>
-__global__ void upsample2_grad_v4_kernel(const float* __restrict__ dcat, int dcs, int dco, TView act, TView dz,
+template <typename I, int V>
+__global__ void upsample2_grad_vec_kernel(const float* __restrict__ dcat, int dcs, int dco, TView act, TView dz,
                                          int N, int Ho, int Wo, int C) {
-    const int C4 = C / 4;
-    const I total = I(N) * I(Ho) * I(Wo) * I(C4);
+    const int CV = C / V;
+    const I total = I(N) * I(Ho) * I(Wo) * I(CV);
     const int H = 2 * Ho, W = 2 * Wo;
     for (I i = I(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += I(gridDim.x) * blockDim.x) {
-        const int c = int(i % I(C4)) * 4;
-        const I q = i / I(C4);
+        const int c = int(i % I(CV)) * V;
+        const I q = i / I(CV);
         const int x = int(q % I(Wo));
         const I t = q / I(Wo);
         const int y = int(t % I(Ho));
         const I n = t / I(Ho);
-        float s[4] = {0.f, 0.f, 0.f, 0.f};
+        float s[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) s[k] = 0.f;
         for (int dy = 0; dy < 2; ++dy)
             for (int dx = 0; dx < 2; ++dx) {
                 const long long pix = ((long long)n * H + 2 * y + dy) * W + 2 * x + dx;  // the fine grid
-                const float4 g = *reinterpret_cast<const float4*>(dcat + pix * dcs + dco + c);
-                s[0] += g.x;
-                s[1] += g.y;
-                s[2] += g.z;
-                s[3] += g.w;
-            }
-        float mk[4], o[4];
-        ld4(act.p + (long long)q * act.cs + act.co + c, mk);
+                float g[V];
+                ldf<V>(dcat + pix * dcs + dco + c, g);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) o[k] = mk[k] > 0.f ? s[k] : 0.f;
-        st4(dz.p + (long long)q * dz.cs + dz.co + c, o);
+                for (int k = 0; k < V; ++k) s[k] += g[k];
+            }
+        float mk[V], o[V];
+        ldv<V>(act.p + (long long)q * act.cs + act.co + c, mk);
+#pragma unroll
+        for (int k = 0; k < V; ++k) o[k] = mk[k] > 0.f ? s[k] : 0.f;
+        stv<V>(dz.p + (long long)q * dz.cs + dz.co + c, o);
     }
 }
 
-template <typename I>
-__global__ void skip_grad_v4_kernel(const float* __restrict__ dcat, int dcs, int dco, const float* __restrict__ dpool,
+template <typename I, int V>
+__global__ void skip_grad_vec_kernel(const float* __restrict__ dcat, int dcs, int dco, const float* __restrict__ dpool,
                                     int pcs, TView act, TView dz, int N, int H, int W, int C) {
-    const int C4 = C / 4;
-    const I total = I(N) * I(H) * I(W) * I(C4);
+    const int CV = C / V;
+    const I total = I(N) * I(H) * I(W) * I(CV);
     for (I i = I(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += I(gridDim.x) * blockDim.x) {
-        const int c = int(i % I(C4)) * 4;
-        const I q = i / I(C4);
+        const int c = int(i % I(CV)) * V;
+        const I q = i / I(CV);
         const int x = int(q % I(W));
         const I t = q / I(W);
         const int y = int(t % I(H));
         const I n = t / I(H);
         const I parent = (n * I(H / 2) + I(y / 2)) * I(W / 2) + I(x / 2);
-        const float4 gp = *reinterpret_cast<const float4*>(dpool + (long long)parent * pcs + c);
-        const float4 gc = *reinterpret_cast<const float4*>(dcat + (long long)q * dcs + dco + c);
-        const float sum[4] = {gc.x + 0.25f * gp.x, gc.y + 0.25f * gp.y, gc.z + 0.25f * gp.z, gc.w + 0.25f * gp.w};
-        float mk[4], o[4];
-        ld4(act.p + (long long)q * act.cs + act.co + c, mk);
+        float gp[V], gc[V], mk[V], o[V];
+        ldf<V>(dpool + (long long)parent * pcs + c, gp);
+        ldf<V>(dcat + (long long)q * dcs + dco + c, gc);
+        ldv<V>(act.p + (long long)q * act.cs + act.co + c, mk);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) o[k] = mk[k] > 0.f ? sum[k] : 0.f;
-        st4(dz.p + (long long)q * dz.cs + dz.co + c, o);
+        for (int k = 0; k < V; ++k) o[k] = mk[k] > 0.f ? gc[k] + 0.25f * gp[k] : 0.f;
+        stv<V>(dz.p + (long long)q * dz.cs + dz.co + c, o);
     }
 }
 
@@ -837,23 +874,29 @@ hipError_t conv3x3_wgrad(const WgradArgs& a, hipStream_t s) {
     return wgrad_launch<2, 2, false, false>(b, s);
 }
 
-static bool by4(int C, const TView& a, const TView& b) {
-    return C % 4 == 0 && a.cs % 4 == 0 && a.co % 4 == 0 && b.cs % 4 == 0 && b.co % 4 == 0;
+static bool byv(int V, int C, const TView& a, const TView& b) {
+    return C % V == 0 && a.cs % V == 0 && a.co % V == 0 && b.cs % V == 0 && b.co % V == 0;
 }
+static bool by4(int C, const TView& a, const TView& b) { return byv(4, C, a, b); }
 
-// Launches a four-channel kernel over `quads` channel quadruples with the narrowest
-// index type that holds the count and the grid stride past it.
-#define SUR_LAUNCH_V4(kernel, quads, s, ...)                                                                 \
-    do {                                                                                                    \
-        if ((quads) < (1LL << 31))                                                                          \
-            hipLaunchKernelGGL(kernel<uint32_t>, dim3(grid_for(quads)), dim3(256), 0, s, __VA_ARGS__);      \
-        else                                                                                                \
-            hipLaunchKernelGGL(kernel<unsigned long long>, dim3(grid_for(quads)), dim3(256), 0, s, __VA_ARGS__); \
+// Launches a V-channel kernel over `groups` channel groups with the narrowest index
+// type that holds the count and the grid stride past it.
+#define SUR_LAUNCH_VEC(kernel, V, groups, s, ...)                                                                 \
+    do {                                                                                                        \
+        if ((groups) < (1LL << 31))                                                                             \
+            hipLaunchKernelGGL((kernel<uint32_t, V>), dim3(grid_for(groups)), dim3(256), 0, s, __VA_ARGS__);    \
+        else                                                                                                    \
+            hipLaunchKernelGGL((kernel<unsigned long long, V>), dim3(grid_for(groups)), dim3(256), 0, s,          \
+                               __VA_ARGS__);                                                                    \
     } while (0)
 
 hipError_t avgpool2(TView in, TView out, int N, int H, int W, int C, hipStream_t s) {
+    if (byv(8, C, in, out)) {
+        SUR_LAUNCH_VEC(avgpool2_vec_kernel, 8, (long long)N * (H / 2) * (W / 2) * (C / 8), s, in, out, N, H, W, C);
+        return hipGetLastError();
+    }
     if (by4(C, in, out)) {
-        SUR_LAUNCH_V4(avgpool2_v4_kernel, (long long)N * (H / 2) * (W / 2) * (C / 4), s, in, out, N, H, W, C);
+        SUR_LAUNCH_VEC(avgpool2_vec_kernel, 4, (long long)N * (H / 2) * (W / 2) * (C / 4), s, in, out, N, H, W, C);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(avgpool2_kernel, dim3(grid_for((long long)N * (H / 2) * (W / 2) * C)), dim3(256), 0, s, in,
@@ -862,8 +905,12 @@ hipError_t avgpool2(TView in, TView out, int N, int H, int W, int C, hipStream_t
 }
 
 hipError_t upsample2(TView in, TView out, int N, int H, int W, int C, hipStream_t s) {
+    if (byv(8, C, in, out)) {
+        SUR_LAUNCH_VEC(upsample2_vec_kernel, 8, (long long)N * H * W * (C / 8), s, in, out, N, H, W, C);
+        return hipGetLastError();
+    }
     if (by4(C, in, out)) {
-        SUR_LAUNCH_V4(upsample2_v4_kernel, (long long)N * H * W * (C / 4), s, in, out, N, H, W, C);
+        SUR_LAUNCH_VEC(upsample2_vec_kernel, 4, (long long)N * H * W * (C / 4), s, in, out, N, H, W, C);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(upsample2_kernel, dim3(grid_for((long long)N * H * W * C)), dim3(256), 0, s, in, out, N, H, W,
@@ -871,11 +918,13 @@ hipError_t upsample2(TView in, TView out, int N, int H, int W, int C, hipStream_
     return hipGetLastError();
 }
 
+// The two gradient kernels take four channels per thread: with eight (two 16-byte FP32
+// loads per input) they measured slower.
 hipError_t upsample2_grad(const float* dcat, int dcs, int dco, TView act, TView dz, int N, int Ho, int Wo, int C,
                           hipStream_t s) {
     if (by4(C, act, dz) && dcs % 4 == 0 && dco % 4 == 0) {
-        SUR_LAUNCH_V4(upsample2_grad_v4_kernel, (long long)N * Ho * Wo * (C / 4), s, dcat, dcs, dco, act, dz, N, Ho,
-                      Wo, C);
+        SUR_LAUNCH_VEC(upsample2_grad_vec_kernel, 4, (long long)N * Ho * Wo * (C / 4), s, dcat, dcs, dco, act, dz, N,
+                       Ho, Wo, C);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(upsample2_grad_kernel, dim3(grid_for((long long)N * Ho * Wo * C)), dim3(256), 0, s, dcat, dcs,
@@ -886,8 +935,8 @@ hipError_t upsample2_grad(const float* dcat, int dcs, int dco, TView act, TView 
 hipError_t skip_grad(const float* dcat, int dcs, int dco, const float* dpool, int pcs, TView act, TView dz, int N,
                      int H, int W, int C, hipStream_t s) {
     if (by4(C, act, dz) && dcs % 4 == 0 && dco % 4 == 0 && pcs % 4 == 0) {
-        SUR_LAUNCH_V4(skip_grad_v4_kernel, (long long)N * H * W * (C / 4), s, dcat, dcs, dco, dpool, pcs, act, dz, N, H,
-                      W, C);
+        SUR_LAUNCH_VEC(skip_grad_vec_kernel, 4, (long long)N * H * W * (C / 4), s, dcat, dcs, dco, dpool, pcs, act, dz,
+                       N, H, W, C);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(skip_grad_kernel, dim3(grid_for((long long)N * H * W * C)), dim3(256), 0, s, dcat, dcs, dco,
