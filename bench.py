@@ -1,14 +1,15 @@
 #!/usr/bin/env python3
 """Throughput of the fused chemical-potential LBM step on one MI355X.
 
-Workload (the plain-method FP32 configuration): 1024 x 1024 D2Q9 lattice,
-periodic in x, surface-chemical-potential wall below and neutral wall above,
-Peng-Robinson EOS (a = 2/49, b = 2/21, R = 1, omega = 0.344) at T = 0.8 Tc,
-tau = 1.3, kappa = 0.01, semicircular drop of radius 200 on the wall at the
-coexistence densities, wall mu drawn from a seeded uniform range.  A step is
-one fused update (moments, Eq 28 wall density, Eq 8 chemical potential, Eq 12
-force, Eqs 13-14 collision, streaming with bounce-back) plus the mass /
-residual / divergence monitors every 100 steps.
+Headline workload (the precision configuration with FP32 storage, the HBM-bound
+size): 4096 x 4096 periodic D2Q9 lattice, van der Waals EOS (a = 9/49, b = 2/21)
+at T = 0.85 Tc, tau = 1, kappa = 0.01, spinodal decomposition from
+rho = 2.6 (1 + 0.01 U(-1, 1)).  A step is one fused update (moments, Eq 8
+chemical potential, Eq 12 force, Eqs 13-14 collision, streaming) plus the
+mass / residual / divergence monitors every min(100, K) steps.  The 1024^2
+wetting lattice (whose 75 MB stay in the 256 MB Infinity Cache), the 16-bit
+storage types, the 256-case batch and the surrogate's training step are
+reported beside it under "aux".
 
 Prints one JSON line: MLUPS (fluid-node updates per second / 1e6) with inputs
 resident in HBM, the roofline of the step kernel (72 algorithmic bytes per node
@@ -50,9 +51,9 @@ def parse():
     ap.add_argument("--warmstart", action="store_true",
                     help="also run the learned warm-start experiment live (2000 cases at 256^2: "
                          "equilibria, training, cold vs warm sweep; several minutes)")
-    ap.add_argument("--workload", choices=("wetting1024", "spinodal4096"), default="wetting1024",
-                    help="main measurement: the 1024^2 FP32 wetting configuration (default) or the "
-                         "4096^2 FP32 spinodal lattice (for profiling the HBM-bound size)")
+    ap.add_argument("--workload", choices=("spinodal4096", "wetting1024"), default="spinodal4096",
+                    help="main measurement: the 4096^2 FP32 spinodal lattice (default, HBM-bound) or the "
+                         "1024^2 FP32 wetting configuration (cache-resident; for profiling)")
     return ap.parse_args()
 
 
@@ -189,8 +190,15 @@ def _with_monitor(p, every):
     return q
 
 
-def measure(lbm, p, rho0, mu_w, fluid_nodes, steps, warmup, bytes_per_lu, workload):
-    """Times the step with HIP events on the lattice's own stream (lbm_step_timed)."""
+def measure(lbm, p, rho0, mu_w, fluid_nodes, steps, warmup, bytes_per_lu, workload, kernel_steps=None):
+    """Times the step with HIP events on the lattice's own stream (lbm_step_timed).
+
+    Whole step: exactly `steps` fused updates with the monitors every
+    min(MONITOR_EVERY, steps) steps.  Kernel: `kernel_steps` (default
+    max(steps, 100)) back-to-back fused updates without monitors, on a fresh
+    lattice of the same state, for the roofline.  The library captures the HIP
+    graph that the steps replay before its first event, so capture and
+    instantiation are never inside a timed interval."""
     def lattice(every, shape=None):
         lat = lbm.Lattice(_with_monitor(p, every), rho0)
         if mu_w is not None:
@@ -206,21 +214,23 @@ def measure(lbm, p, rho0, mu_w, fluid_nodes, steps, warmup, bytes_per_lu, worklo
     lat.close()
     # kernel only: back-to-back fused steps, no monitors
     lat = lattice(0, shape)
-    k_steps = max(steps, 100)
+    k_steps = kernel_steps if kernel_steps is not None else max(steps, 100)
     t_kernel = lat.step_timed(k_steps) / 1e3 / k_steps
     lat.close()
-    # whole step: fused update plus the monitors every MONITOR_EVERY steps
-    lat = lattice(MONITOR_EVERY, shape)
-    n_steps = max(steps // MONITOR_EVERY, 1) * MONITOR_EVERY
-    t_total = lat.step_timed(n_steps) / 1e3
+    # whole step: fused update plus the monitors
+    every = min(MONITOR_EVERY, steps)
+    lat = lattice(every, shape)
+    t_total = lat.step_timed(steps) / 1e3
     mon = lat.monitors()
     lat.close()
     achieved = fluid_nodes * bytes_per_lu / t_kernel / 1e9
     traffic = traffic_for(workload, shape)
     return {
-        "mlups": fluid_nodes * n_steps / t_total / 1e6,
-        "ms_per_step": t_total / n_steps * 1e3,
-        "steps": n_steps,
+        "mlups": fluid_nodes * steps / t_total / 1e6,
+        "ms_per_step": t_total / steps * 1e3,
+        "steps": steps,
+        "monitor_every": every,
+        "kernel_steps": k_steps,
         "kernel_us": t_kernel * 1e6,
         "shape": shape,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -244,35 +254,53 @@ def warmstart_summary(live: bool):
         from paper_1611_00907_amd import warmstart
         r = warmstart.run_experiment(log=lambda m: print(m, file=sys.stderr, flush=True))
         out = {k: r[k] for k in WARMSTART_KEYS if k in r}
+        out["measured_in_this_run"] = True
         out["source"] = "measured in this run"
         return out
     if not os.path.exists(WARMSTART_RECORD):
         return None
     r = json.load(open(WARMSTART_RECORD))
     out = {k: r[k] for k in WARMSTART_KEYS if k in r}
-    out["source"] = "recorded: profiles/warmstart_c5.json (%s)" % r.get("command", "")
+    out["measured_in_this_run"] = False
+    out["source"] = "not measured in this run; record of profiles/warmstart_c5.json (%s)" % r.get("command", "")
     return out
 
 
-def cpu_baseline(seconds: float):
-    """The FP64 oracle on the same 1024^2 wetting workload, timed on the host cores."""
+def cpu_baseline(seconds: float, workload: str):
+    """The FP64 oracle on the main workload, timed on the host cores for about
+    `seconds` (a bounded sample of steps of the same lattice)."""
     from oracle import thermo
     from oracle.lattice import CPWALL, NEUTRAL, OracleLattice, OracleParams, max_threads
     from paper_1611_00907_amd import inputs
 
-    nx = ny = 1024
-    op = OracleParams.from_reduced(nx, ny, thermo.PR, 2 / 49, 2 / 21, 0.8, 1.3, 0.01, omega=0.344,
-                                   bottom=CPWALL, top=NEUTRAL)
-    rg, rl, _, mu_sat = thermo.maxwell(op.fluid())
-    mu_w = float(inputs.draw_uniform(2, mu_sat - 0.18, mu_sat + 0.23, 1)[0])  # the GPU workload's wall
-    ora = OracleLattice(op, inputs.sessile_drop(nx, ny, rl, rg, 200.0), mu_w_bottom=mu_w)
-    t1 = ora.timed_steps(2) / 2
-    n = max(2, int(seconds / max(t1, 1e-6)))
-    t = ora.timed_steps(n)
-    fluid = nx * (ny - 2)
-    return {"value": round(fluid * n / t / 1e6, 3), "unit": "MLUPS", "cores": max_threads(),
+    if workload == "wetting1024":
+        nx = ny = 1024
+        op = OracleParams.from_reduced(nx, ny, thermo.PR, 2 / 49, 2 / 21, 0.8, 1.3, 0.01, omega=0.344,
+                                       bottom=CPWALL, top=NEUTRAL)
+        rg, rl, _, mu_sat = thermo.maxwell(op.fluid())
+        mu_w = float(inputs.draw_uniform(2, mu_sat - 0.18, mu_sat + 0.23, 1)[0])  # the GPU workload's wall
+        ora = OracleLattice(op, inputs.sessile_drop(nx, ny, rl, rg, 200.0), mu_w_bottom=mu_w)
+        fluid, name = nx * (ny - 2), "1024x1024 wetting workload"
+    else:
+        n = 4096
+        op = OracleParams.from_reduced(n, n, thermo.VDW, 9 / 49, 2 / 21, 0.85, 1.0, 0.01)
+        ora = OracleLattice(op, inputs.with_relative_noise(np.full((n, n), 2.6), 0.01, 3))
+        fluid, name = n * n, "4096x4096 spinodal workload"
+    t1 = ora.timed_steps(1)
+    n_steps = max(2, int(seconds / max(t1, 1e-6)))
+    t = ora.timed_steps(n_steps)
+    return {"value": round(fluid * n_steps / t / 1e6, 3), "unit": "MLUPS", "cores": max_threads(),
             "kind": "oracle",
-            "sample": "%d steps of the 1024x1024 wetting workload in FP64 (%.1f s)" % (n, t)}
+            "sample": "%d steps of the %s in FP64 (%.1f s)" % (n_steps, name, t)}
+
+
+SPINODAL_CONFIG = {"workload": "spinodal 4096x4096 D2Q9, VdW a=9/49 b=2/21, Tr=0.85, tau=1, kappa=0.01, "
+                               "periodic, rho = 2.6 (1 + 0.01 U(-1,1)), FP32 storage; HBM-bound (1.2 GB per step)",
+                   "nx": 4096, "ny": 4096, "storage": "f32", "parallelism": "single GPU"}
+WETTING_CONFIG = {"workload": "wetting 1024x1024 D2Q9, PR omega=0.344 Tr=0.8, tau=1.3, kappa=0.01, "
+                              "CP wall + neutral top, drop R=200, FP32 storage; cache-resident (75 MB per step "
+                              "inside the 256 MB Infinity Cache)",
+                  "nx": 1024, "ny": 1024, "storage": "f32", "parallelism": "single GPU"}
 
 
 def main():
@@ -280,6 +308,9 @@ def main():
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (requested --gpus %d)"
               % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
         sys.exit(2)
     from paper_1611_00907_amd import inputs, lbm
 
@@ -290,29 +321,32 @@ def main():
 
     copy_gbs = lbm.lbm_copy_bandwidth(args.copy_bytes, 20)
     print("copy: %.1f GB/s over %d bytes" % (copy_gbs, args.copy_bytes), file=sys.stderr, flush=True)
-    if args.workload == "wetting1024":
-        p, rho0, mu_w, fluid = wetting_workload(lbm, inputs, lbm.LBM_F32)
-        config = {"workload": "wetting 1024x1024 D2Q9, PR omega=0.344 Tr=0.8, tau=1.3, kappa=0.01, "
-                              "CP wall + neutral top, drop R=200, monitors every 100 steps",
-                  "nx": 1024, "ny": 1024, "storage": "f32", "parallelism": "single GPU"}
-    else:
+    if args.workload == "spinodal4096":
         p, rho0, mu_w, fluid = spinodal_workload(lbm, inputs, lbm.LBM_F32)
-        config = {"workload": "spinodal 4096x4096 D2Q9, VdW Tr=0.85, tau=1, kappa=0.01, periodic, "
-                              "rho = 2.6 (1 + 0.01 U), monitors every 100 steps",
-                  "nx": 4096, "ny": 4096, "storage": "f32", "parallelism": "single GPU"}
-    main_res = measure(lbm, p, rho0, mu_w, fluid, args.steps, args.warmup, 72.0,
-                       "step_f32_" + args.workload)
-    print("main: %.1f MLUPS, kernel %.2f us, %.1f GB/s" % (main_res["mlups"], main_res["kernel_us"],
-                                                          main_res["roofline"]["achieved"]),
-          file=sys.stderr, flush=True)
+        config = dict(SPINODAL_CONFIG)
+    else:
+        p, rho0, mu_w, fluid = wetting_workload(lbm, inputs, lbm.LBM_F32)
+        config = dict(WETTING_CONFIG)
+    main_res = measure(lbm, p, rho0, mu_w, fluid, args.steps, args.warmup, 72.0, "step_f32_" + args.workload)
+    config["monitor_every"] = main_res["monitor_every"]
+    print("main: %.1f MLUPS, step %.2f us, kernel %.2f us, %.1f GB/s" % (
+        main_res["mlups"], main_res["ms_per_step"] * 1e3, main_res["kernel_us"], main_res["roofline"]["achieved"]),
+        file=sys.stderr, flush=True)
 
     aux = []
     if not args.no_aux:
-        for prec, name, b in ((lbm.LBM_F32, "f32", 72.0), (lbm.LBM_F16DEV, "f16dev", 36.0),
-                              (lbm.LBM_BF16DEV, "bf16dev", 36.0)):
+        if args.workload == "spinodal4096":
+            pp, r0, mw, fl = wetting_workload(lbm, inputs, lbm.LBM_F32)
+            res = measure(lbm, pp, r0, mw, fl, 1000, 100, 72.0, "step_f32_wetting1024")
+            aux.append({"workload": WETTING_CONFIG["workload"], "mlups": round(res["mlups"], 1),
+                        "ms_per_step": round(res["ms_per_step"], 5), "kernel_us": round(res["kernel_us"], 2),
+                        "shape": res["shape"], "roofline": res["roofline"]})
+            print("aux f32 wetting1024: %.1f MLUPS %.1f GB/s" % (res["mlups"], res["roofline"]["achieved"]),
+                  file=sys.stderr, flush=True)
+        for prec, name, b in ((lbm.LBM_F16DEV, "f16dev", 36.0), (lbm.LBM_BF16DEV, "bf16dev", 36.0)):
             pp, r0, _, fl = spinodal_workload(lbm, inputs, prec)
             res = measure(lbm, pp, r0, None, fl, 300, 20, b, "step_%s_spinodal4096" % name)
-            aux.append({"workload": "spinodal 4096x4096 VdW Tr=0.85, %s storage" % name,
+            aux.append({"workload": "spinodal 4096x4096 VdW Tr=0.85, %s storage (deviations from w_i 2.6)" % name,
                         "mlups": round(res["mlups"], 1), "kernel_us": round(res["kernel_us"], 2),
                         "shape": res["shape"], "roofline": res["roofline"]})
             print("aux %s: %.1f MLUPS %.1f GB/s" % (name, res["mlups"], res["roofline"]["achieved"]),
@@ -343,6 +377,7 @@ def main():
         "config": config,
         "roofline": main_res["roofline"],
         "kernel_us": round(main_res["kernel_us"], 3),
+        "kernel_steps": main_res["kernel_steps"],
         "shape": main_res["shape"],
         "copy_kernel": {"bytes": args.copy_bytes, "gbs": round(copy_gbs, 1),
                         "step_frac_of_copy": round(main_res["roofline"]["achieved"] / copy_gbs, 4)},
@@ -352,7 +387,7 @@ def main():
     if ws is not None:
         line["warm_start"] = ws
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.workload)
     print(json.dumps(line), flush=True)
 
 

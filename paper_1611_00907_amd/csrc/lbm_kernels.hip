@@ -399,7 +399,8 @@ __device__ __forceinline__ void tile_rest(const LatticeArgs& A, const Planes<ST>
         rs[ly + k * RS + 2][lx + 2] = r;
     }
 
-    // Wall chemical potentials (Eq 29) of a CP wall row inside the chemical-potential
+    // Wall chemical potentials (the surface value of Sec. IV, which enters the force of
+    // Eq 12 through grad mu) of a CP wall row inside the chemical-potential
     // tile go out with the ring's pulls and land in LDS with the densities, so that
     // step 3 reads no global memory.
     const int mwb = 1 - y0, mwt = A.ny - y0;  // ms rows of y = 0 and y = ny - 1

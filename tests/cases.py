@@ -85,7 +85,7 @@ class Case:
 
 
 # Plain method, FP64: 100 x 100 periodic CS drop R = 25 with 1e-4 noise, exactly as
-# stated (tau = 1 diverges after ~110 steps), and the companion with tau = 1.3.
+# stated (tau = 1: the oracle turns non-finite at step 12), and the companion with tau = 1.3.
 C1 = Case(100, 100, thermo.CS, 0.7, 1.0, drop="circle", radius=25, noise=1e-4, seed=1)
 C1_TAU13 = Case(100, 100, thermo.CS, 0.7, 1.3, drop="circle", radius=25, noise=1e-4, seed=1)
 # Walled PR twin of the wetting configuration: CP wall below, neutral wall above.

@@ -52,7 +52,69 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_cpu_baseline_record():
-    rec = bench.cpu_baseline(0.2)
+    rec = bench.cpu_baseline(0.2, "wetting1024")
     assert rec["kind"] == "oracle" and rec["unit"] == "MLUPS"
     assert rec["cores"] >= 1 and rec["value"] > 0
     assert "1024x1024 wetting workload" in rec["sample"]
+
+
+def test_cpu_baseline_record_spinodal():
+    rec = bench.cpu_baseline(0.5, "spinodal4096")
+    assert rec["kind"] == "oracle" and rec["value"] > 0
+    assert "4096x4096 spinodal workload" in rec["sample"]
+
+
+class _FakeLattice:
+    """Stands in for lbm.Lattice: records what the bench asks of it."""
+    log = []
+
+    def __init__(self, p, rho0):
+        self.every = p.monitor_every
+        _FakeLattice.log.append(("new", self.every))
+
+    def set_wall_mu(self, wall, mu):
+        pass
+
+    def set_tile(self, shape):
+        _FakeLattice.log.append(("tile", shape))
+
+    def step(self, n):
+        _FakeLattice.log.append(("step", n))
+
+    def tune(self, trial_steps):
+        return 25608, 0.25
+
+    def step_timed(self, n):
+        _FakeLattice.log.append(("timed", n, self.every))
+        return 0.25 * n  # ms
+
+    def monitors(self):
+        return {"mass": 1.0, "residual": 0.0, "flags": 0}
+
+    def close(self):
+        pass
+
+
+class _FakeLbm:
+    Lattice = _FakeLattice
+
+
+@pytest.mark.parametrize("steps,warmup", [(20, 5), (1000, 100), (7, 0)])
+def test_measure_times_exactly_the_requested_steps(steps, warmup):
+    """The whole-step interval covers exactly --steps steps with monitors every
+    min(100, steps) steps; the kernel interval has no monitors; warm-up runs on every
+    lattice before its timed interval."""
+    _FakeLattice.log = []
+    p = lbm.make_params(64, 64, lbm.LBM_EOS_VDW, 9 / 49, 2 / 21, 0.85, 1.0, 0.01)
+    res = bench.measure(_FakeLbm, p, None, None, 4096 * 4096, steps, warmup, 72.0, "no_such_workload")
+    timed = [e for e in _FakeLattice.log if e[0] == "timed"]
+    assert timed[-1] == ("timed", steps, min(100, steps))
+    assert timed[0][2] == 0 and timed[0][1] == max(steps, 100)
+    assert res["steps"] == steps and res["monitor_every"] == min(100, steps)
+    assert res["ms_per_step"] == pytest.approx(0.25)
+    assert res["kernel_us"] == pytest.approx(250.0)
+    assert res["roofline"]["frac"] == pytest.approx(4096 * 4096 * 72 / 250e-6 / 1e9 / 8000.0, rel=1e-3)
+    # every lattice warms up before it is timed
+    for i, e in enumerate(_FakeLattice.log):
+        if e[0] == "timed":
+            assert ("step", warmup) in _FakeLattice.log[:i]
