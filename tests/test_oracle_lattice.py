@@ -227,38 +227,69 @@ def test_drop_equilibrium_mu_uniform_and_at_rest():
     assert np.max(np.hypot(f["vx"], f["vy"])) < 0.05
 
 
-@pytest.mark.slow
-def test_laplace_law():
-    """Pressure jump across drops of radius R is linear in 1/R (Young-Laplace), and
-    its R -> infinity intercept is the offset of a planar interface (the bulk
-    densities of a flat interface sit slightly off Maxwell, so p0 differs there
-    too).  The slope is the model's effective surface tension; the paper prints
-    none, so its value is not pinned (parity unpinned)."""
-    n = 96
-    rg, rl, _, _ = _pr_coex()
-    fl = thermo.fluid_at(thermo.PR, 2 / 49, 2 / 21, 1.0, 0.8, 0.344)
+def _laplace_fit(eos, a, b, om, Tr, tau, bubble, radii=(14.0, 18.0, 24.0, 30.0), n=96, steps=6000):
+    """Pressure jump p0(inside) - p0(outside) against 1/R for relaxed drops (liquid
+    inside) or bubbles (vapour inside), R from the excess mass of the relaxed disc."""
+    fl = thermo.fluid_at(eos, a, b, 1.0, Tr, om)
+    rg, rl, _, _ = thermo.maxwell(fl)
     inv, dp = [], []
-    for R in (14.0, 18.0, 24.0, 30.0):
-        p = _pr_params(n, n)
-        lat = OracleLattice(p, inputs.tanh_drop(n, n, rl, rg, R, n / 2, n / 2, 4.0))
-        lat.step(6000)
+    for R in radii:
+        p = OracleParams.from_reduced(n, n, eos, a, b, Tr, tau, 0.01, omega=om)
+        r_in, r_out = (rg, rl) if bubble else (rl, rg)
+        lat = OracleLattice(p, inputs.tanh_drop(n, n, r_in, r_out, R, n / 2, n / 2, 4.0))
+        lat.step(steps)
         r = lat.fields()["rho"]
-        rin = r[n // 2, n // 2]
-        rout = r[0, 0]
-        # radius from the drop's excess mass
-        Req = np.sqrt(((r - rout).sum() / (rin - rout)) / np.pi)
-        inv.append(1 / Req)
+        rin, rout = r[n // 2, n // 2], r[0, 0]
+        inv.append(1 / np.sqrt(((r - rout).sum() / (rin - rout)) / np.pi))
         dp.append(float(thermo.p0(fl, rin) - thermo.p0(fl, rout)))
     inv, dp = np.array(inv), np.array(dp)
     A = np.vstack([inv, np.ones_like(inv)]).T
     (slope, icpt), res, _, _ = np.linalg.lstsq(A, dp, rcond=None)
     r2 = 1 - res[0] / ((dp - dp.mean()) ** 2).sum()
+    return slope, icpt, r2, dp
+
+
+@pytest.mark.slow
+def test_laplace_law():
+    """Pressure jump across drops of radius R is linear in 1/R (Young-Laplace), and
+    its R -> infinity intercept is the offset of a planar interface (the bulk
+    densities of a flat interface sit slightly off Maxwell, so p0 differs there
+    too).  The slope is the lattice's surface tension; on these interfaces of about
+    two nodes it is about twice the sigma of Eq 1's functional (the scheme's own
+    stresses at unit lattice spacing -- the forcing's (tau - 1/2)^2 F F / rho among
+    them -- are of the order of kappa rho'^2), so its magnitude is not pinned here;
+    the drop / bubble test below pins it as a property of the interface."""
+    slope, icpt, r2, dp = _laplace_fit(thermo.PR, 2 / 49, 2 / 21, 0.344, 0.8, 1.3, bubble=False)
     assert r2 > 0.99
     assert slope > 0
-    lat, _ = _planar((thermo.PR, 2 / 49, 2 / 21, 0.344), 0.8)
+    fl = thermo.fluid_at(thermo.PR, 2 / 49, 2 / 21, 1.0, 0.8, 0.344)
+    lat, (rg, rl, ps, ms) = _planar((thermo.PR, 2 / 49, 2 / 21, 0.344), 0.8)
     rp = lat.fields()["rho"][:, 0]
     dp_planar = float(thermo.p0(fl, rp.max()) - thermo.p0(fl, rp.min()))
     assert abs(icpt - dp_planar) < 0.1 * (dp.max() - dp_planar)
+    sigma = thermo.surface_tension(fl, 0.01, rg, rl, ms, ps)
+    print("PR Tr 0.8: Laplace slope %.4f, sigma of Eq 1 %.4f, ratio %.3f" % (slope, sigma, slope / sigma))
+    assert 1.0 < slope / sigma < 3.0
+
+
+@pytest.mark.slow
+def test_laplace_slope_is_a_property_of_the_interface():
+    """The same interface bent the other way: bubbles of vapour in liquid follow
+    Young-Laplace with the slope of the drops (within 5 %) and the opposite
+    intercept (the planar offset seen from the other side).  A wrong sign or index in
+    a stencil, the force or the streaming breaks this symmetry between the phases;
+    the slope itself is the lattice's surface tension (VdW, Tr = 0.85: 1.24 times the
+    sigma of Eq 1's functional)."""
+    eos, a, b, om, Tr, tau = thermo.VDW, 9 / 49, 2 / 21, 0.0, 0.85, 1.0
+    s_d, i_d, r2_d, _ = _laplace_fit(eos, a, b, om, Tr, tau, bubble=False)
+    s_b, i_b, r2_b, _ = _laplace_fit(eos, a, b, om, Tr, tau, bubble=True)
+    fl = thermo.fluid_at(eos, a, b, 1.0, Tr, om)
+    rg, rl, ps, ms = thermo.maxwell(fl)
+    sigma = thermo.surface_tension(fl, 0.01, rg, rl, ms, ps)
+    print("VdW Tr 0.85: drop slope %.4f, bubble slope %.4f, sigma of Eq 1 %.4f" % (s_d, s_b, sigma))
+    assert r2_d > 0.99 and r2_b > 0.99
+    assert s_b == pytest.approx(s_d, rel=0.05)
+    assert i_d > 0 > i_b and abs(i_d + i_b) < 0.2 * abs(i_d)
 
 
 def test_galilean_invariance():
@@ -297,3 +328,44 @@ def test_galilean_invariance():
     assert abs(rm / rr - 1) < 0.02          # same size
     assert abs(am - 1) < 0.03 and abs(ar - 1) < 0.03   # both stay round
     assert abs(cm / cr - 1) < 0.01          # same liquid density
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("kappa,gas_tol", [(0.01, 0.5), (0.3, 0.3)])
+def test_config1_cs_drop_coexistence(kappa, gas_tol):
+    """Plain-method FP64 configuration (Sec. III): Carnahan-Starling a = 1, b = 4 at
+    Tr = 0.7, drop R = 25 at the Maxwell liquid density in Maxwell vapour with 1e-4
+    noise on 100^2.  As stated (tau = 1) it turns non-finite at step 12; these are its
+    tau = 1.3 companion (kappa = 0.01 as stated) and a kappa-scaled companion
+    (kappa = 0.3, the largest of 0.1, 0.3, 1.0 that runs; the continuum interface at
+    kappa = 0.01 is about 0.35 nodes wide).  After 20000 steps: mass exact, the state
+    stationary, the chemical potential uniform inside the liquid (Eq 8 driven to
+    equilibrium), the liquid within 2 % of Maxwell.  The vapour stays well above
+    Maxwell (+45 % and +23 %) on these sub-lattice interfaces, and the chemical
+    potentials of the two bulk phases differ by 14 % and 8 % of the initial spread;
+    both are printed and bounded loosely."""
+    fl = thermo.fluid_at(thermo.CS, 1.0, 4.0, 1.0, 0.7, 0.0)
+    rg, rl, _, _ = thermo.maxwell(fl)
+    n = 100
+    p = OracleParams.from_reduced(n, n, thermo.CS, 1.0, 4.0, 0.7, 1.3, kappa)
+    rho0 = inputs.with_additive_noise(inputs.tanh_drop(n, n, rl, rg, 25, n / 2, n / 2), 1e-4, 1)
+    lat = OracleLattice(p, rho0)
+    m0 = lat.mass()
+    spread0 = np.ptp(lat.fields()["mu"])
+    lat.step(19000)
+    r1 = lat.fields()["rho"]
+    lat.step(1000)
+    f = lat.fields()
+    r, mu = f["rho"], f["mu"]
+    y, x = np.mgrid[0:n, 0:n]
+    d = np.hypot(x - n / 2, y - n / 2)
+    core, far = d < 12, d > 38
+    liq, gas = r[core].mean() / rl - 1, r[far].mean() / rg - 1
+    print("CS config 1, tau 1.3, kappa %.2f: liquid %+.4f, vapour %+.4f of Maxwell; mu core-far %.3f of spread"
+          % (kappa, liq, gas, (mu[core].mean() - mu[far].mean()) / spread0))
+    assert abs(lat.mass() / m0 - 1) < 1e-11
+    assert np.max(np.abs(r - r1)) < 0.01 * (rl - rg)
+    assert np.ptp(mu[core]) < 1e-3 * spread0
+    assert np.ptp(mu[far]) < 0.05 * spread0
+    assert abs(liq) < 0.02
+    assert abs(gas) < gas_tol

@@ -204,3 +204,47 @@ def test_eq11_divergence_identity():
     rhs = core[3:-3] * d(mu)
     inner = slice(20, -20)
     assert np.max(np.abs(lhs[inner] - rhs[inner])) < 1e-6 * np.max(np.abs(rhs[inner]))
+
+
+# --------------------------------------------------------------------------- surface tension
+@pytest.mark.parametrize("case", [CASES[0], CASES[1], CASES[2], CASES[4]])
+def test_surface_tension_from_the_relaxed_planar_profile(case):
+    """sigma of Eq 1's functional, checked without its first integral: the planar
+    profile is solved as the boundary-value problem that Eq 8 with a uniform chemical
+    potential states, kappa rho'' = mu_b(rho) - mu* with rho -> rho_g, rho_l at the two
+    ends, and sigma is then computed two ways on that profile: as the gradient energy
+    int kappa rho'^2 dx and as the excess grand potential
+    int (psi - mu* rho + p* + kappa rho'^2 / 2) dx.  The oracle's quadrature
+    int sqrt(2 kappa W) d rho must equal both (a dropped 2, a dropped p* or a wrong
+    mu* would not)."""
+    kappa = 0.01
+    fl = _fluid(case)
+    rg, rl, ps, ms = thermo.maxwell(fl)
+    sigma = thermo.surface_tension(fl, kappa, rg, rl, ms, ps)
+    dmu = lambda r: float(thermo.dcs(lambda z: thermo.mu_b(fl, z), r))   # noqa: E731
+    ell = math.sqrt(kappa / min(dmu(rl), dmu(rg)))   # the longer decay length of the two phases
+    L = 40.0 * ell
+    x = np.linspace(-L, L, 801)
+    guess = np.vstack([0.5 * (rl + rg) + 0.5 * (rl - rg) * np.tanh(x / (4.0 * ell)), np.zeros_like(x)])
+    guess[1] = np.gradient(guess[0], x)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        sol = integrate.solve_bvp(lambda t, y: np.vstack([y[1], (thermo.mu_b(fl, y[0]) - ms) / kappa]),
+                                  lambda ya, yb: np.array([ya[0] - rg, yb[0] - rl]), x, guess, tol=1e-6,
+                                  max_nodes=50000)
+    xs = np.linspace(-L, L, 200001)
+    rho, drho = sol.sol(xs)
+    assert np.all(np.diff(rho) > -1e-9 * rl)          # one monotone interface
+    gradient_energy = np.trapezoid(kappa * drho**2, xs)
+    grand_potential = np.trapezoid(thermo.psi(fl, rho) - ms * rho + ps + 0.5 * kappa * drho**2, xs)
+    assert gradient_energy == pytest.approx(sigma, rel=2e-6)
+    assert grand_potential == pytest.approx(sigma, rel=2e-6)
+
+
+def test_surface_tension_scales_as_sqrt_kappa():
+    """W does not depend on kappa, so sigma = int sqrt(2 kappa W) d rho is exactly
+    proportional to sqrt(kappa)."""
+    fl = _fluid(CASES[2])
+    rg, rl, ps, ms = thermo.maxwell(fl)
+    s1 = thermo.surface_tension(fl, 0.01, rg, rl, ms, ps)
+    s4 = thermo.surface_tension(fl, 0.04, rg, rl, ms, ps)
+    assert s4 / s1 == pytest.approx(2.0, rel=1e-9)
