@@ -147,6 +147,19 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t tile_y);
  * wall value on solid rows).  Any pointer may be NULL.  Synchronises. */
 lbm_status lbm_get_fields(lbm_ctx* c, double* rho, double* vx, double* vy, double* mu);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): lbm_get_fields without any
+ * allocation.  The fields go through a staging array that the library holds in
+ * static device memory (64 MiB on every device it runs on, for the life of the
+ * process) instead of a buffer allocated and freed per call; outputs, layout and
+ * NULL handling are those of lbm_get_fields, and the values are identical.
+ * LBM_EINVAL (with lbm_last_error naming the limit) if nx * ny exceeds
+ * LBM_NOALLOC_MAX_NODES.  All calls on one device share the one array: calls that
+ * overlap in time on the same device (several host threads, or several streams)
+ * race and must be serialised by the caller.  Synchronises. */
+#define LBM_NOALLOC_MAX_NODES 2097152
+lbm_status lbm_get_fields_noalloc(lbm_ctx* c, double* rho, double* vx, double* vy, double* mu);
+
 /* Surface chemical potential of a CP wall (Sec. IV): wall 0 = bottom, 1 = top;
  * count 1 sets every column, count nx sets one value per column.  Takes effect
  * from the next step.  LBM_EINVAL if the wall is not LBM_BC_CPWALL. */

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <new>
 #include <iterator>
+#include <mutex>
 #include <vector>
 
 #include "lbm_common.h"
@@ -283,6 +284,36 @@ void release(lbm_ctx* c) {
 
 }  // namespace
 
+// Staging of lbm_get_fields_noalloc: the four FP64 fields of at most
+// LBM_NOALLOC_MAX_NODES nodes.  Every device the library runs on holds its own copy
+// for the life of the process.  Host code never passes this name to a kernel or a
+// copy (on the host it is only a stand-in symbol): it uses the device address that
+// hipGetSymbolAddress returns for the current device, kept per device below.
+static __device__ __align__(256) double scratch[4 * (size_t)LBM_NOALLOC_MAX_NODES];
+
+namespace {
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch[SCRATCH_DEVICES] = {};
+
+// Device address of device dev's copy of `scratch`; dev must be the current device.
+// Looked up on the first call per device and kept.
+lbm_status scratch_on_device(int dev, double** out) {
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return LBM_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_status(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch[dev];
+    return LBM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t lbm_workspace_bytes(const lbm_params* p) {
@@ -526,6 +557,29 @@ lbm_status lbm_get_fields(lbm_ctx* c, double* rho, double* vx, double* vy, doubl
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipFree(d);
     return hip_status(e, "lbm_get_fields");
+}
+
+lbm_status lbm_get_fields_noalloc(lbm_ctx* c, double* rho, double* vx, double* vy, double* mu) {
+    if (!c) return LBM_EINVAL;
+    const size_t n = (size_t)c->p.nx * c->p.ny;
+    if (n > (size_t)LBM_NOALLOC_MAX_NODES) {
+        std::snprintf(g_last_error, sizeof g_last_error,
+                      "lbm_get_fields_noalloc: %zu nodes exceed the %d-node staging array", n,
+                      (int)LBM_NOALLOC_MAX_NODES);
+        return LBM_EINVAL;
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return LBM_EHIP;
+    double* d = nullptr;
+    const lbm_status st = scratch_on_device(c->device, &d);
+    if (st != LBM_OK) return st;
+    // the field kernel writes all four fields of every node, so nothing left in the
+    // array by an earlier call is read
+    hipError_t e = launch_step(c->p.prec, c->p.eos, MODE_FIELDS, c->A, c->f[c->cur], nullptr, c->mu_w, d, c->stream);
+    double* outs[4] = {rho, vx, vy, mu};
+    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+        if (outs[k]) e = hipMemcpyAsync(outs[k], d + k * n, n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return hip_status(e, "lbm_get_fields_noalloc");
 }
 
 lbm_status lbm_set_wall_mu(lbm_ctx* c, int32_t wall, const double* mu_w, int32_t count) {

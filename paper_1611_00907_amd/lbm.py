@@ -29,8 +29,11 @@ LBM_EOS_VDW, LBM_EOS_CS, LBM_EOS_PR, LBM_EOS_RKS, LBM_EOS_RK = 0, 1, 2, 3, 4
 LBM_F64, LBM_F32, LBM_F16DEV, LBM_BF16DEV = 0, 1, 2, 3
 # lbm_bc
 LBM_BC_PERIODIC, LBM_BC_CPWALL, LBM_BC_NEUTRAL = 0, 1, 2
+# nodes of the largest lattice lbm_get_fields_noalloc serves (LBM_NOALLOC_MAX_NODES)
+NOALLOC_MAX_NODES = 2097152
 
 EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lbm_get_fields",
+            "lbm_get_fields_noalloc",
             "lbm_set_wall_mu", "lbm_tune", "lbm_set_tile",
             "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_step_timed",
             "lbm_batch_run", "lbm_batch_status", "lbm_batch_get_fields", "lbm_batch_get_state",
@@ -97,6 +100,7 @@ def load_library():
     lib.lbm_step.argtypes = [vp, C.c_int64]
     lib.lbm_step_timed.argtypes = [vp, C.c_int64, dp]
     lib.lbm_get_fields.argtypes = [vp, vp, vp, vp, vp]
+    lib.lbm_get_fields_noalloc.argtypes = [vp, vp, vp, vp, vp]
     lib.lbm_set_wall_mu.argtypes = [vp, C.c_int32, vp, C.c_int32]
     lib.lbm_get_monitors.argtypes = [vp, dp, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
     lib.lbm_monitor_step.argtypes = [vp]
@@ -298,11 +302,15 @@ class Lattice:
         _check(self.lib.lbm_monitor_step(self.ctx), "lbm_monitor_step")
         return self.monitors()
 
-    def fields(self):
+    def fields(self, noalloc: bool = False, which=("rho", "vx", "vy", "mu")):
+        """Output fields (lbm_get_fields; noalloc=True: lbm_get_fields_noalloc, which
+        stages them in the library's static device array instead of a per-call
+        allocation).  Fields not in `which` are passed as NULL and not returned."""
         shape = (self.ny, self.nx)
-        out = {k: np.empty(shape) for k in ("rho", "vx", "vy", "mu")}
-        _check(self.lib.lbm_get_fields(self.ctx, *[_p(out[k]) for k in ("rho", "vx", "vy", "mu")]),
-               "lbm_get_fields")
+        out = {k: np.empty(shape) for k in which}
+        fn = self.lib.lbm_get_fields_noalloc if noalloc else self.lib.lbm_get_fields
+        _check(fn(self.ctx, *[_p(out.get(k)) for k in ("rho", "vx", "vy", "mu")]),
+               "lbm_get_fields_noalloc" if noalloc else "lbm_get_fields")
         return out
 
     def set_wall_mu(self, wall: int, mu_w):

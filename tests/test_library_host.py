@@ -31,6 +31,14 @@ def test_exports_every_declared_symbol(lbm):
     assert declared == set(lbm.EXPORTED)
 
 
+def test_noalloc_limit_matches_the_header(lbm):
+    header = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    m = re.search(r"#define LBM_NOALLOC_MAX_NODES (\d+)", header)
+    assert m and int(m.group(1)) == lbm.NOALLOC_MAX_NODES
+    # four FP64 fields of the largest lattice: 64 MiB of static device memory
+    assert 4 * 8 * lbm.NOALLOC_MAX_NODES == 64 << 20
+
+
 def _params(lbm, **kw):
     base = dict(nx=32, ny=16, eos=lbm.LBM_EOS_PR, a=2 / 49, b=2 / 21, Tr=0.8, tau=1.3, kappa=0.01,
                 omega=0.344)
