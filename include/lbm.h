@@ -290,6 +290,28 @@ lbm_status sur_set_dataset(sur_net* n, const float* inputs, const float* targets
  * images drawn with replacement from the dataset by SplitMix64 from seed; losses
  * (may be NULL) receives the loss of each step. */
 lbm_status sur_train(sur_net* n, int32_t steps, int32_t batch, float lr, uint64_t seed, float* losses);
+
+/* Inspection of the last pass, for checking each kernel on the exact operands it
+ * used.  sur_trace(n, 1) allocates per-layer copies (about 150 MB at 256^2 and
+ * batch 4) and makes every later backward pass keep each layer's output gradient
+ * dz (as its weight gradient read it) and the gradients of the three pooled
+ * branches; sur_trace(n, 0) frees them.  Tracing does not change any result. */
+lbm_status sur_trace(sur_net* n, int32_t on);
+
+/* Copies an internal tensor of the last forward (and, for the gradients, backward)
+ * pass into out as FP32, NHWC [N][H][W][C] with C the channels of its buffer, and
+ * its shape into shape[4] (out may be NULL to ask for the shape only; capacity is
+ * out's length in floats).  BF16 tensors are converted exactly.  Names:
+ *   forward: x0 (packed input, 16 ch), e0a, c0 ([up(d1) 64 | e0b 32]), p0, e1a,
+ *     c1 ([up(d2) 96 | e1b 64]), p1, e2a, c2 ([up(e3) 128 | e2b 96]), p2, e3a, e3,
+ *     d2a, d2, d1a, d1, d0a, d0 (BF16), y (FP32 prediction);
+ *   backward: dc0, dc1, dc2 (FP32 gradients of the concatenations), and with tracing
+ *     dz_<layer> for every layer (BF16; dz_out has 16 channels, channel 0 used) and
+ *     dp_e3a, dp_e2a, dp_e1a (FP32 input gradients of the first convolution of
+ *     levels 3, 2, 1).
+ * LBM_EINVAL for an unknown name or a short buffer, LBM_ESTATE before any pass, for
+ * a gradient before a backward pass, or for a traced tensor with tracing off. */
+lbm_status sur_read(sur_net* n, const char* name, float* out, int64_t capacity, int64_t* shape);
 void sur_destroy(sur_net* n);
 
 /* ---- measurement -------------------------------------------------------- */

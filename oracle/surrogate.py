@@ -14,7 +14,7 @@ Layout NCHW, float64.  The network shape matches the GPU library's:
 levels of 32, 64, 96, 128 channels, two 3x3 convolutions per level, average
 pooling down, nearest upsampling and skip concatenation up, a final 3x3
 convolution to one channel.  Every function is plain numpy; a matmul over the
-channel axis is the only library primitive used.
+channel axis (einsum contracted through BLAS) is the only library primitive used.
 """
 from __future__ import annotations
 
@@ -34,7 +34,7 @@ def conv3x3(x, w, b):
     for u in range(3):
         for v in range(3):
             patch = xp[:, :, u:u + H, v:v + W]                     # x[n, c, i+u-1, j+v-1]
-            y += np.einsum("oc,nchw->nohw", w[:, :, u, v], patch)
+            y += np.einsum("oc,nchw->nohw", w[:, :, u, v], patch, optimize=True)
     return y + b[None, :, None, None]
 
 
@@ -47,7 +47,7 @@ def conv3x3_grad_input(dy, w):
     for u in range(3):
         for v in range(3):
             patch = dyp[:, :, 2 - u:2 - u + H, 2 - v:2 - v + W]     # dy[n, o, i-u+1, j-v+1]
-            dx += np.einsum("oc,nohw->nchw", w[:, :, u, v], patch)
+            dx += np.einsum("oc,nohw->nchw", w[:, :, u, v], patch, optimize=True)
     return dx
 
 
@@ -59,7 +59,7 @@ def conv3x3_grad_weight(x, dy):
     dw = np.zeros((dy.shape[1], C, 3, 3))
     for u in range(3):
         for v in range(3):
-            dw[:, :, u, v] = np.einsum("nohw,nchw->oc", dy, xp[:, :, u:u + H, v:v + W])
+            dw[:, :, u, v] = np.einsum("nohw,nchw->oc", dy, xp[:, :, u:u + H, v:v + W], optimize=True)
     return dw, dy.sum(axis=(0, 2, 3))
 
 
@@ -139,14 +139,17 @@ def mse(y, t):
     return float((d * d).mean()), 2.0 * d / d.size
 
 
-def backward(params, cache, dy):
-    """Gradients {name: (dw, db)} of the loss whose gradient wrt the prediction is dy."""
+def backward(params, cache, dy, dzs=None):
+    """Gradients {name: (dw, db)} of the loss whose gradient wrt the prediction is dy.
+    If dzs is a dict, it receives each layer's output gradient dz (after its ReLU)."""
     shapes = {n: r for n, _, _, r in layer_shapes()}
     grads = {}
 
     def back(name, da):
         inp, a = cache[name]
         dz = da * (a > 0) if shapes[name] else da
+        if dzs is not None:
+            dzs[name] = dz
         grads[name] = conv3x3_grad_weight(inp, dz)
         return conv3x3_grad_input(dz, params[name][0])
 

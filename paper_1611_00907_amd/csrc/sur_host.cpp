@@ -79,6 +79,13 @@ struct sur_net {
     float *ds_in = nullptr, *ds_t = nullptr;
     int ds_count = 0;
     std::vector<void*> allocs;
+    // trace of the last backward pass (sur_trace): each layer's output gradient dz as its
+    // weight gradient read it, and the pooled-branch gradients of e3a, e2a, e1a
+    bool trace = false;
+    uint16_t* trace_dz[15] = {};
+    float* trace_dp[3] = {};
+    int last_N = 0;         // images of the last forward pass
+    bool have_backward = false;
 };
 
 namespace {
@@ -95,8 +102,21 @@ lbm_status dalloc(sur_net* n, T** p, size_t count) {
     return LBM_OK;
 }
 
+void free_trace(sur_net* n) {
+    for (auto& p : n->trace_dz) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+    }
+    for (auto& p : n->trace_dp) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+    }
+    n->trace = false;
+}
+
 void release(sur_net* n) {
     if (!n) return;
+    free_trace(n);
     for (void* p : n->allocs) (void)hipFree(p);
     if (n->partial_host) (void)hipHostFree(n->partial_host);
     if (n->stream) (void)hipStreamDestroy(n->stream);
@@ -164,7 +184,19 @@ hipError_t wgrad(sur_net* n, int li, TView x, TView dz, int N, int H, int W) {
     a.cout_p = l.cout_p;
     a.db = n->grad + l.b_off;
     a.chunk_px = 2048;
+    if (n->trace && n->trace_dz[li]) {  // dz views start at channel 0 of their buffer
+        const hipError_t e = hipMemcpyAsync(n->trace_dz[li], dz.p, (size_t)N * H * W * dz.cs * sizeof(uint16_t),
+                                            hipMemcpyDeviceToDevice, n->stream);
+        if (e != hipSuccess) return e;
+    }
     return conv3x3_wgrad(a, n->stream);
+}
+
+// Copy of the pooled-branch gradient dp (FP32, C channels) into trace slot k.
+hipError_t trace_dp(sur_net* n, int k, int N, int H, int W, int C) {
+    if (!n->trace || !n->trace_dp[k]) return hipSuccess;
+    return hipMemcpyAsync(n->trace_dp[k], n->dp, (size_t)N * H * W * C * sizeof(float), hipMemcpyDeviceToDevice,
+                          n->stream);
 }
 
 hipError_t refresh_flipped(sur_net* n) {
@@ -185,6 +217,8 @@ hipError_t refresh_flipped(sur_net* n) {
 // Forward pass of N images already packed in x0; prediction (FP32) into y.
 lbm_status forward(sur_net* n, int N) {
     const int S0 = n->size, S1 = S0 / 2, S2 = S0 / 4, S3 = S0 / 8;
+    n->last_N = N;
+    n->have_backward = false;
     SUR_TRY(conv(n, E0A, tv(n->x0, IN_PADDED), N, S0, S0, EPI_RELU_BF16, tv(n->e0a, L0)));
     SUR_TRY(conv(n, E0B, tv(n->e0a, L0), N, S0, S0, EPI_RELU_BF16, tv(n->c0, L1 + L0, L1)));
     SUR_TRY(avgpool2(tv(n->c0, L1 + L0, L1), tv(n->p0, L0), N, S0, S0, L0, n->stream));
@@ -244,24 +278,28 @@ lbm_status backward(sur_net* n, int N, double* loss) {
     SUR_TRY(conv_back(n, E3B, tv(A, L3), N, S3, S3, EPI_MASK_BF16, tv(B, L3), tv(n->e3a, L3)));
     SUR_TRY(wgrad(n, E3A, tv(n->p2, L2), tv(B, L3), N, S3, S3));
     SUR_TRY(conv_back(n, E3A, tv(B, L3), N, S3, S3, EPI_F32, none, none, n->dp, L2));
+    SUR_TRY(trace_dp(n, 0, N, S3, S3, L2));
     // level 2 encoder: skip share of dc2 plus the pooling gradient
     SUR_TRY(skip_grad(n->dc2, L3 + L2, L3, n->dp, L2, tv(n->c2, L3 + L2, L3), tv(A, L2), N, S2, S2, L2, n->stream));
     SUR_TRY(wgrad(n, E2B, tv(n->e2a, L2), tv(A, L2), N, S2, S2));
     SUR_TRY(conv_back(n, E2B, tv(A, L2), N, S2, S2, EPI_MASK_BF16, tv(B, L2), tv(n->e2a, L2)));
     SUR_TRY(wgrad(n, E2A, tv(n->p1, L1), tv(B, L2), N, S2, S2));
     SUR_TRY(conv_back(n, E2A, tv(B, L2), N, S2, S2, EPI_F32, none, none, n->dp, L1));
+    SUR_TRY(trace_dp(n, 1, N, S2, S2, L1));
     // level 1 encoder
     SUR_TRY(skip_grad(n->dc1, L2 + L1, L2, n->dp, L1, tv(n->c1, L2 + L1, L2), tv(A, L1), N, S1, S1, L1, n->stream));
     SUR_TRY(wgrad(n, E1B, tv(n->e1a, L1), tv(A, L1), N, S1, S1));
     SUR_TRY(conv_back(n, E1B, tv(A, L1), N, S1, S1, EPI_MASK_BF16, tv(B, L1), tv(n->e1a, L1)));
     SUR_TRY(wgrad(n, E1A, tv(n->p0, L0), tv(B, L1), N, S1, S1));
     SUR_TRY(conv_back(n, E1A, tv(B, L1), N, S1, S1, EPI_F32, none, none, n->dp, L0));
+    SUR_TRY(trace_dp(n, 2, N, S1, S1, L0));
     // level 0 encoder
     SUR_TRY(skip_grad(n->dc0, L1 + L0, L1, n->dp, L0, tv(n->c0, L1 + L0, L1), tv(A, L0), N, S0, S0, L0, n->stream));
     SUR_TRY(wgrad(n, E0B, tv(n->e0a, L0), tv(A, L0), N, S0, S0));
     SUR_TRY(conv_back(n, E0B, tv(A, L0), N, S0, S0, EPI_MASK_BF16, tv(B, L0), tv(n->e0a, L0)));
     SUR_TRY(wgrad(n, E0A, tv(n->x0, IN_PADDED), tv(B, L0), N, S0, S0));
     SUR_TRY(hipStreamSynchronize(n->stream));
+    n->have_backward = true;
     if (loss) {
         double s = 0.0;
         for (int i = 0; i < MSE_BLOCKS; ++i) s += n->partial_host[i];
@@ -492,6 +530,99 @@ lbm_status sur_train(sur_net* n, int32_t steps, int32_t batch, float lr, uint64_
         if (losses) losses[s] = float(loss);
     }
     SUR_TRY(hipStreamSynchronize(n->stream));
+    return LBM_OK;
+}
+
+lbm_status sur_trace(sur_net* n, int32_t on) {
+    if (!n) return LBM_EINVAL;
+    if (hipSetDevice(n->device) != hipSuccess) return LBM_EHIP;
+    SUR_TRY(hipStreamSynchronize(n->stream));
+    if (!on) {
+        free_trace(n);
+        return LBM_OK;
+    }
+    if (n->trace) return LBM_OK;
+    const size_t B = n->max_batch, P0 = (size_t)n->size * n->size;
+    const int level[NL] = {0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0};
+    for (int li = 0; li < NL; ++li) {
+        const size_t px = B * (P0 >> (2 * level[li]));
+        const size_t ch = li == OUT ? 16 : (size_t)LAYERS[li].cout;  // the output gradient's buffer width
+        if (hipMalloc(&n->trace_dz[li], px * ch * sizeof(uint16_t)) != hipSuccess) {
+            free_trace(n);
+            return LBM_ENOMEM;
+        }
+    }
+    const size_t dp_px[3] = {B * (P0 >> 6), B * (P0 >> 4), B * (P0 >> 2)};
+    const int dp_ch[3] = {L2, L1, L0};
+    for (int k = 0; k < 3; ++k)
+        if (hipMalloc(&n->trace_dp[k], dp_px[k] * dp_ch[k] * sizeof(float)) != hipSuccess) {
+            free_trace(n);
+            return LBM_ENOMEM;
+        }
+    n->trace = true;
+    return LBM_OK;
+}
+
+lbm_status sur_read(sur_net* n, const char* name, float* out, int64_t capacity, int64_t* shape) {
+    if (!n || !name || !shape) return LBM_EINVAL;
+    const int N = n->last_N;
+    if (N < 1) return LBM_ESTATE;
+    const int S0 = n->size, S1 = S0 / 2, S2 = S0 / 4, S3 = S0 / 8;
+    struct Entry {
+        const char* name;
+        const void* p;
+        int side, ch;
+        bool f32, needs_backward;
+    };
+    const Entry fwd[] = {
+        {"x0", n->x0, S0, IN_PADDED, false, false}, {"e0a", n->e0a, S0, L0, false, false},
+        {"c0", n->c0, S0, L1 + L0, false, false},   {"p0", n->p0, S1, L0, false, false},
+        {"e1a", n->e1a, S1, L1, false, false},      {"c1", n->c1, S1, L2 + L1, false, false},
+        {"p1", n->p1, S2, L1, false, false},        {"e2a", n->e2a, S2, L2, false, false},
+        {"c2", n->c2, S2, L3 + L2, false, false},   {"p2", n->p2, S3, L2, false, false},
+        {"e3a", n->e3a, S3, L3, false, false},      {"e3", n->e3, S3, L3, false, false},
+        {"d2a", n->d2a, S2, L2, false, false},      {"d2", n->d2, S2, L2, false, false},
+        {"d1a", n->d1a, S1, L1, false, false},      {"d1", n->d1, S1, L1, false, false},
+        {"d0a", n->d0a, S0, L0, false, false},      {"d0", n->d0, S0, L0, false, false},
+        {"y", n->y, S0, 1, true, false},            {"dc0", n->dc0, S0, L1 + L0, true, true},
+        {"dc1", n->dc1, S1, L2 + L1, true, true},   {"dc2", n->dc2, S2, L3 + L2, true, true},
+    };
+    const int side_of[NL] = {S0, S0, S1, S1, S2, S2, S3, S3, S2, S2, S1, S1, S0, S0, S0};
+    Entry e{nullptr, nullptr, 0, 0, false, false};
+    for (const Entry& f : fwd)
+        if (std::strcmp(f.name, name) == 0) e = f;
+    if (!e.name && std::strncmp(name, "dz_", 3) == 0) {
+        for (int li = 0; li < NL; ++li)
+            if (std::strcmp(name + 3, LAYERS[li].name) == 0)
+                e = Entry{name, n->trace_dz[li], side_of[li], li == OUT ? 16 : LAYERS[li].cout, false, true};
+    }
+    const char* dp_names[3] = {"dp_e3a", "dp_e2a", "dp_e1a"};
+    const int dp_side[3] = {S3, S2, S1}, dp_ch[3] = {L2, L1, L0};
+    for (int k = 0; k < 3 && !e.name; ++k)
+        if (std::strcmp(name, dp_names[k]) == 0) e = Entry{name, n->trace_dp[k], dp_side[k], dp_ch[k], true, true};
+    if (!e.name) return LBM_EINVAL;
+    if (e.needs_backward && !n->have_backward) return LBM_ESTATE;
+    if (!e.p) return LBM_ESTATE;  // a traced tensor while tracing is off
+    shape[0] = N;
+    shape[1] = e.side;
+    shape[2] = e.side;
+    shape[3] = e.ch;
+    const size_t count = (size_t)N * e.side * e.side * e.ch;
+    if (!out) return LBM_OK;
+    if (capacity < (int64_t)count) return LBM_EINVAL;
+    if (hipSetDevice(n->device) != hipSuccess) return LBM_EHIP;
+    if (e.f32) {
+        SUR_TRY(hipMemcpyAsync(out, e.p, count * sizeof(float), hipMemcpyDeviceToHost, n->stream));
+        SUR_TRY(hipStreamSynchronize(n->stream));
+    } else {
+        std::vector<uint16_t> h(count);
+        SUR_TRY(hipMemcpyAsync(h.data(), e.p, count * sizeof(uint16_t), hipMemcpyDeviceToHost, n->stream));
+        SUR_TRY(hipStreamSynchronize(n->stream));
+        for (size_t i = 0; i < count; ++i) {  // a BF16 value is the top half of an FP32
+            const uint32_t bits = uint32_t(h[i]) << 16;
+            std::memcpy(out + i, &bits, sizeof bits);
+        }
+    }
     return LBM_OK;
 }
 

@@ -39,7 +39,7 @@ EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lb
             "lbm_batch_run", "lbm_batch_status", "lbm_batch_get_fields", "lbm_batch_get_state",
             "lbm_batch_tune", "lbm_batch_set_schedule", "lbm_batch_fluid_nodes", "lbm_batch_destroy", "lbm_copy_bandwidth",
             "sur_create", "sur_param_count", "sur_set_params", "sur_get_params", "sur_forward", "sur_gradients",
-            "sur_set_dataset", "sur_train", "sur_destroy",
+            "sur_set_dataset", "sur_train", "sur_trace", "sur_read", "sur_destroy",
             "lbm_get_monitors", "lbm_monitor_step", "lbm_get_state", "lbm_set_state",
             "lbm_get_temperature", "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_critical_point",
             "lbm_coexistence", "lbm_spinodal", "lbm_eos_eval", "lbm_contact_angle"]
@@ -140,6 +140,8 @@ def load_library():
     lib.sur_gradients.argtypes = [vp, vp, vp, C.c_int32, vp, dp]
     lib.sur_set_dataset.argtypes = [vp, vp, vp, C.c_int32]
     lib.sur_train.argtypes = [vp, C.c_int32, C.c_int32, C.c_float, C.c_uint64, vp]
+    lib.sur_trace.argtypes = [vp, C.c_int32]
+    lib.sur_read.argtypes = [vp, C.c_char_p, vp, C.c_int64, C.POINTER(C.c_int64)]
     lib.sur_destroy.argtypes = [vp]
     lib.sur_destroy.restype = None
     lib.lbm_critical_point.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, dp, dp, dp]
@@ -516,6 +518,17 @@ class Surrogate:
         losses = np.empty(int(steps), np.float32)
         _check(self.lib.sur_train(self.ctx, int(steps), int(batch), float(lr), int(seed), _p(losses)), "sur_train")
         return losses
+
+    def trace(self, on: bool = True):
+        _check(self.lib.sur_trace(self.ctx, int(bool(on))), "sur_trace")
+
+    def read(self, name: str):
+        """Internal tensor of the last pass as float32 NHWC [N][H][W][C] (sur_read)."""
+        shape = (C.c_int64 * 4)()
+        _check(self.lib.sur_read(self.ctx, name.encode(), None, 0, shape), "sur_read(%s)" % name)
+        out = np.empty(tuple(shape), np.float32)
+        _check(self.lib.sur_read(self.ctx, name.encode(), _p(out), out.size, shape), "sur_read(%s)" % name)
+        return out
 
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:

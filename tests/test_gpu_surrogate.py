@@ -62,24 +62,43 @@ def test_forward_other_sizes(size):
 
 @pytest.mark.parametrize("size,n", [(32, 2), (24, 3)])
 def test_gradients_match_oracle(size, n):
-    """(24, 3): 1728 pixels per layer-0 map, so the weight-gradient pixel runs end
+    """The whole network against the FP64 network (a secondary check: each kernel
+    is checked element by element on its own BF16 operands in
+    test_gpu_surrogate_layers.py).  Here the GPU's BF16 roundings accumulate along
+    the chain, and a weight gradient sum_p x_p dz_p that cancels magnifies them:
+    per layer the test prints the relative L2 error of the GPU's dz against the FP64
+    chain's and the cancellation factor |sum |x| |dz|| / |sum x dz| of its weight
+    gradient.  Measured: the dz of every layer below the output differs from the
+    FP64 chain's by 8-15 % (relative L2) -- the BF16 forward pass puts some
+    pre-activations that lie within rounding of zero on the other side of their ReLU,
+    and each flipped mask entry changes dz by its full value -- and e0a's weight
+    gradient cancels about 16-fold, hence its cosine of about 0.995 (10 % relative
+    L2), the lowest of all layers.
+    (24, 3): 1728 pixels per layer-0 map, so the weight-gradient pixel runs end
     ragged (the one-output-channel kernel's last block has 192 of its 256 pixels)."""
     net, p32, x, t = _setup(size=size, n=n)
+    net.trace(True)
     g, loss = net.gradients(x.astype(np.float32), t.astype(np.float32))
     yo, cache = S.forward(p32, _oracle_input(x))
     lo, dy = S.mse(yo, t[:, None])
-    go = S.backward(p32, cache, dy)
+    dzs = {}
+    go = S.backward(p32, cache, dy, dzs)
     assert abs(loss - lo) < 0.03 * lo
     gg = lbm.Surrogate.unflatten(g.astype(np.float64))
     rows = []
     for name, _, _ in lbm.Surrogate.LAYERS:
+        dz_gpu = net.read("dz_" + name).transpose(0, 3, 1, 2).astype(np.float64)[:, :dzs[name].shape[1]]
+        dz_err = float(np.linalg.norm(dz_gpu - dzs[name]) / np.linalg.norm(dzs[name]))
+        inp = cache[name][0]
+        cancel = float(np.linalg.norm(S.conv3x3_grad_weight(np.abs(inp), np.abs(dzs[name]))[0])
+                       / np.linalg.norm(go[name][0]))
         for k in (0, 1):
             a, b = gg[name][k].ravel(), go[name][k].ravel()
             cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30))
             ratio = float(np.linalg.norm(a) / (np.linalg.norm(b) + 1e-30))
-            rows.append((name, "wb"[k], round(cos, 5), round(ratio, 4)))
-    print("gradient agreement (layer, w/b, cosine, norm ratio):", rows)
-    for name, k, cos, ratio in rows:
+            rows.append((name, "wb"[k], round(cos, 5), round(ratio, 4), round(dz_err, 4), round(cancel, 1)))
+    print("gradient agreement (layer, w/b, cosine, norm ratio, dz error, cancellation):", rows)
+    for name, k, cos, ratio, _, _ in rows:
         assert cos > 0.99 and abs(ratio - 1) < 0.05, (name, k, cos, ratio)
 
 
