@@ -18,6 +18,9 @@
  *   ->  BGK collision with the equilibrium velocity u + tau F / rho (Eqs 13, 14
  *       and the forcing paragraph after Eq 14)
  *   ->  streaming, with bounce-back for links that enter a solid row (Sec. IV).
+ * Two variants that Sec. II names stand beside it: the force as the divergence
+ * of the full pressure tensor (Eq 5 with P from Eq 9, periodic lattices), and
+ * the TRT and MRT collision operators in place of BGK.
  *
  * Readings where the paper is silent (all listed in the design notes):
  *   D2Q9 with w = 4/9, 1/9, 1/36 (the coefficients of Eq 14 give c_s^2 = 1/3);
@@ -49,11 +52,22 @@ typedef struct {
     int32_t nx, ny;          /* lattice nodes including solid rows          */
     int32_t bottom, top;     /* ORA_PERIODIC (both) or a wall kind          */
     int32_t eos;             /* ORA_VDW ...                                 */
-    int32_t pad_;
+    int32_t scheme;          /* force (bits 0-3) | collision (bits 4-7)     */
     double a, b, R, T;       /* EOS constants and absolute temperature       */
     double alpha;            /* alpha(T) of Eqs 19/22 (1 for VdW and CS)     */
     double tau, kappa;       /* relaxation time (Eq 13), gradient coeff (Eq 1) */
+    double trt_lambda;       /* TRT: (tau+ - 1/2)(tau- - 1/2)                  */
+    double s_e, s_eps, s_q;  /* MRT relaxation rates of e, epsilon, q          */
 } ora_params;
+
+/* Nonideal force: the chemical-potential form of Eq 12 (the paper's method) or
+ * the divergence of the pressure tensor, Eq 5 with P from Eq 9. */
+enum { ORA_FORCE_CP = 0, ORA_FORCE_PTENSOR = 1 };
+/* Collision (Sec. II names BGK, MRT and TRT): BGK of Eq 13; two relaxation
+ * times (even part at 1/tau, odd part at 1/tau- with (tau - 1/2)(tau- - 1/2) =
+ * lambda); multiple relaxation times on the D2Q9 moments of Lallemand and Luo
+ * (Phys. Rev. E 61, 6546, 2000). */
+enum { ORA_COLLIDE_BGK = 0, ORA_COLLIDE_TRT = 16, ORA_COLLIDE_MRT = 32 };
 
 /* D2Q9: 0 rest, 1..4 axis, 5..8 diagonal. */
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -193,6 +207,50 @@ void ora_stencils(const ora_params* p, const double* phi, double* lap, double* g
 }
 
 /* ------------------------------------------------------------------------ */
+/* The pressure-tensor force (Eq 5), the form the paper's Eq 12 replaces       */
+/* ------------------------------------------------------------------------ */
+
+/* F = -div(P) + div(P0) with P0 = c_s^2 rho I and the full pressure tensor of
+ * Eq 9, P_ab = [p0 - kappa rho lap(rho) - kappa/2 |grad rho|^2] d_ab
+ * + kappa d_a rho d_b rho: the three components are formed at every node
+ * with the same isotropic stencils, then differentiated once more.  Periodic
+ * lattices only (the pressure tensor carries no wall wetting condition). */
+static void pressure_tensor_force(const ora_params* p, const double* rho, double* Fx, double* Fy) {
+    const int nx = p->nx, ny = p->ny;
+    const size_t plane = (size_t)nx * ny;
+    double* Pxx = (double*)malloc(3 * plane * sizeof(double));
+    double* Pyy = Pxx + plane;
+    double* Pxy = Pxx + 2 * plane;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const size_t c = (size_t)y * nx + x;
+            double psi, p0, mub, gx, gy;
+            eos_eval(p, rho[c], &psi, &p0, &mub);
+            grad9(p, rho, x, y, &gx, &gy);
+            const double pd = p0 - p->kappa * rho[c] * lap9(p, rho, x, y) - 0.5 * p->kappa * (gx * gx + gy * gy);
+            Pxx[c] = pd + p->kappa * gx * gx;
+            Pyy[c] = pd + p->kappa * gy * gy;
+            Pxy[c] = p->kappa * gx * gy;
+        }
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const size_t c = (size_t)y * nx + x;
+            double dxx, dyx, dxy, dyy, dxn, dyn, grx, gry;
+            grad9(p, Pxx, x, y, &dxx, &dyx);   /* d/dx Pxx (dyx unused) */
+            grad9(p, Pxy, x, y, &dxy, &dyy);   /* d/dx Pxy, d/dy Pxy    */
+            grad9(p, Pyy, x, y, &dxn, &dyn);   /* d/dy Pyy (dxn unused) */
+            grad9(p, rho, x, y, &grx, &gry);
+            (void)dyx;
+            (void)dxn;
+            Fx[c] = -(dxx + dyy) + grx / 3.0;
+            Fy[c] = -(dxy + dyn) + gry / 3.0;
+        }
+    free(Pxx);
+}
+
+/* ------------------------------------------------------------------------ */
 /* The macroscopic fields of one time level                                  */
 /* ------------------------------------------------------------------------ */
 
@@ -264,6 +322,11 @@ static void macro_fields(const ora_params* p, const double* mu_w_bot, const doub
             mu[(size_t)ys * nx + x] = kind == ORA_CPWALL ? mw[x] : mu[(size_t)yf * nx + x];
     }
 
+    if ((p->scheme & 15) == ORA_FORCE_PTENSOR) {
+        pressure_tensor_force(p, rho, Fx, Fy);
+        return;
+    }
+
     /* 4. nonideal force, Eq 12 with div(P0) = c_s^2 grad(rho), c_s^2 = 1/3 */
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y) {
@@ -281,6 +344,78 @@ static void macro_fields(const ora_params* p, const double* mu_w_bot, const doub
             Fy[c] = -rho[c] * gmy + gry / 3.0;
         }
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Collision of one node                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* MRT moments of Lallemand and Luo: rho, e, epsilon, j_x, q_x, j_y, q_y,
+ * p_xx, p_xy, as rows over the directions 0..8.  The rows are orthogonal, so
+ * the inverse transform is M^T diag(1 / |row|^2). */
+static const double MRT_M[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, -2, 0, 2, 0, 1, -1, -1, 1},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1}};
+
+void ora_mrt_matrix(double* out) { memcpy(out, MRT_M, sizeof MRT_M); }
+
+/* Post-collision f* of one fluid node with density r, velocity (ux, uy) and
+ * force (Fx, Fy).  The force enters through the equilibrium velocity (forcing
+ * paragraph after Eq 14), shifted by tau F / rho for BGK.  With several
+ * relaxation times each relaxing part is shifted by its own relaxation time,
+ * F / (rho s): the even part of TRT by tau F / rho and its odd part by
+ * tau- F / rho, each MRT moment k by F / (rho s_k).  Every part then gains from
+ * the force what it gains under BGK (in particular the momentum gains exactly
+ * F), and equal relaxation times give BGK. */
+static void collide_node(const ora_params* p, const double* f, double r, double ux, double uy, double Fx,
+                         double Fy, double* fs) {
+    const double tau = p->tau;
+    const int coll = p->scheme & 0xf0;
+    if (coll == ORA_COLLIDE_TRT) {
+        const double tm = 0.5 + p->trt_lambda / (tau - 0.5);   /* tau- */
+        double fe[9], fo[9];
+        ora_feq(r, ux + tau * Fx / r, uy + tau * Fy / r, fe);   /* even part's equilibrium */
+        ora_feq(r, ux + tm * Fx / r, uy + tm * Fy / r, fo);     /* odd part's equilibrium  */
+        for (int i = 0; i < 9; ++i) {
+            const int o = OPP[i];
+            const double sp = 0.5 * (f[i] + f[o]) - 0.5 * (fe[i] + fe[o]);
+            const double sm = 0.5 * (f[i] - f[o]) - 0.5 * (fo[i] - fo[o]);
+            fs[i] = f[i] - sp / tau - sm / tm;
+        }
+        return;
+    }
+    if (coll == ORA_COLLIDE_MRT) {
+        const double sn = 1.0 / tau;
+        const double S[9] = {sn, p->s_e, p->s_eps, sn, p->s_q, sn, p->s_q, sn, sn};
+        double dm[9];
+        for (int k = 0; k < 9; ++k) {
+            double feq[9];
+            ora_feq(r, ux + Fx / (r * S[k]), uy + Fy / (r * S[k]), feq);
+            double norm = 0.0, m = 0.0, meq = 0.0;
+            for (int i = 0; i < 9; ++i) {
+                norm += MRT_M[k][i] * MRT_M[k][i];
+                m += MRT_M[k][i] * f[i];
+                meq += MRT_M[k][i] * feq[i];
+            }
+            dm[k] = S[k] * (m - meq) / norm;
+        }
+        for (int i = 0; i < 9; ++i) {
+            double d = 0.0;
+            for (int k = 0; k < 9; ++k) d += MRT_M[k][i] * dm[k];
+            fs[i] = f[i] - d;
+        }
+        return;
+    }
+    double feq[9];
+    ora_feq(r, ux + tau * Fx / r, uy + tau * Fy / r, feq);
+    for (int i = 0; i < 9; ++i) fs[i] = f[i] - (f[i] - feq[i]) / tau;  /* BGK, Eq 13 */
 }
 
 /* ------------------------------------------------------------------------ */
@@ -316,21 +451,17 @@ void ora_step(const ora_params* p, const double* mu_w_bot, const double* mu_w_to
     macro_fields(p, mu_w_bot, mu_w_top, f, rho, ux, uy, mu, Fx, Fy);
 
     memset(fnew, 0, 9 * plane * sizeof(double));
-    const double tau = p->tau;
     /* 5-6. collision with the shifted equilibrium velocity, then streaming */
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y) {
         if (is_solid_row(p, y)) continue;
         for (int x = 0; x < nx; ++x) {
             const size_t c = (size_t)y * nx + x;
-            const double r = rho[c];
-            const double uex = ux[c] + tau * Fx[c] / r;
-            const double uey = uy[c] + tau * Fy[c] / r;
-            double feq[9];
-            ora_feq(r, uex, uey, feq);
+            double fin[9], fout[9];
+            for (int i = 0; i < 9; ++i) fin[i] = f[i * plane + c];
+            collide_node(p, fin, rho[c], ux[c], uy[c], Fx[c], Fy[c], fout);
             for (int i = 0; i < 9; ++i) {
-                const double fi = f[i * plane + c];
-                const double fstar = fi - (fi - feq[i]) / tau;
+                const double fstar = fout[i];
                 const int xt = wrap(x + EX[i], nx);
                 const int yt = nb_row(p, y, EY[i]);
                 if (yt < 0 || is_solid_row(p, yt)) {

@@ -38,11 +38,17 @@ def build_library(force: bool = False) -> str:
     return _LIB
 
 
+# nonideal force (Eq 12, or Eq 5 with the pressure tensor of Eq 9) and collision
+FORCE_CP, FORCE_PTENSOR = 0, 1
+COLLIDE_BGK, COLLIDE_TRT, COLLIDE_MRT = 0, 16, 32
+
+
 class _Params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("bottom", C.c_int32), ("top", C.c_int32),
-                ("eos", C.c_int32), ("pad_", C.c_int32), ("a", C.c_double), ("b", C.c_double),
+                ("eos", C.c_int32), ("scheme", C.c_int32), ("a", C.c_double), ("b", C.c_double),
                 ("R", C.c_double), ("T", C.c_double), ("alpha", C.c_double), ("tau", C.c_double),
-                ("kappa", C.c_double)]
+                ("kappa", C.c_double), ("trt_lambda", C.c_double), ("s_e", C.c_double),
+                ("s_eps", C.c_double), ("s_q", C.c_double)]
 
 
 _lib = None
@@ -64,6 +70,7 @@ def load_library():
         lib.ora_mass.argtypes = [P, dp]
         lib.ora_mass.restype = C.c_double
         lib.ora_stencils.argtypes = [P, dp, C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.ora_mrt_matrix.argtypes = [dp]
         lib.ora_max_threads.restype = C.c_int
         lib.ora_set_threads.argtypes = [C.c_int]
         _lib = lib
@@ -93,12 +100,17 @@ class OracleParams:
     kappa: float
     bottom: int = PERIODIC
     top: int = PERIODIC
+    scheme: int = FORCE_CP | COLLIDE_BGK
+    trt_lambda: float = 0.25      # TRT: (tau - 1/2)(tau_minus - 1/2)
+    s_e: float = 1.0              # MRT rates of the energy moments e and epsilon
+    s_eps: float = 1.0
+    s_q: float = -1.0             # MRT rate of the heat-flux moments; < 0: 8 (2 - s) / (8 - s), s = 1/tau
 
     @staticmethod
     def from_reduced(nx, ny, eos, a, b, Tr, tau, kappa, R=1.0, omega=0.0, bottom=PERIODIC,
-                     top=PERIODIC) -> "OracleParams":
+                     top=PERIODIC, **scheme) -> "OracleParams":
         fl = thermo.fluid_at(eos, a, b, R, Tr, omega)
-        return OracleParams(nx, ny, eos, a, b, R, fl.T, fl.alpha, tau, kappa, bottom, top)
+        return OracleParams(nx, ny, eos, a, b, R, fl.T, fl.alpha, tau, kappa, bottom, top, **scheme)
 
     def fluid(self) -> thermo.Fluid:
         return thermo.Fluid(self.eos, self.a, self.b, self.R, self.T, self.alpha)
@@ -106,8 +118,13 @@ class OracleParams:
     def c(self) -> _Params:
         if (self.bottom == PERIODIC) != (self.top == PERIODIC):
             raise ValueError("y is periodic only when both bottom and top are periodic")
-        return _Params(self.nx, self.ny, self.bottom, self.top, self.eos, 0, self.a, self.b,
-                       self.R, self.T, self.alpha, self.tau, self.kappa)
+        if (self.scheme & 15) == FORCE_PTENSOR and self.bottom != PERIODIC:
+            raise ValueError("the pressure-tensor force is defined on periodic lattices only")
+        sn = 1.0 / self.tau
+        s_q = self.s_q if self.s_q > 0 else 8.0 * (2.0 - sn) / (8.0 - sn)
+        return _Params(self.nx, self.ny, self.bottom, self.top, self.eos, self.scheme, self.a, self.b,
+                       self.R, self.T, self.alpha, self.tau, self.kappa, self.trt_lambda, self.s_e,
+                       self.s_eps, s_q)
 
     def solid_rows(self):
         rows = []
@@ -148,6 +165,14 @@ def stencils_c(p: OracleParams, phi):
     q = OracleParams(**{**p.__dict__, "bottom": PERIODIC, "top": PERIODIC})
     lib.ora_stencils(C.byref(q.c()), phi, _ptr(lap), _ptr(gx), _ptr(gy))
     return lap, gx, gy
+
+
+def mrt_matrix():
+    """The D2Q9 moment matrix the oracle's MRT collision uses (rows: rho, e, eps,
+    j_x, q_x, j_y, q_y, p_xx, p_xy)."""
+    out = np.empty(81)
+    load_library().ora_mrt_matrix(out)
+    return out.reshape(9, 9)
 
 
 def set_threads(n: int):

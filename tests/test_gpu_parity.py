@@ -11,7 +11,7 @@ is carried by the contracting map.
 import numpy as np
 import pytest
 
-from cases import C1, C1_TAU13, C2, C3, WALLED_PR, Case, rel_err
+from cases import C1, C1_TAU13, C2, C3, C3_512, WALLED_PR, Case, rel_err
 from oracle import thermo
 from oracle.lattice import CPWALL, NEUTRAL, PERIODIC, OracleLattice
 
@@ -271,6 +271,41 @@ def test_reduced_storage_one_and_ten_steps(prec, u):
     lat.step(9)
     ora.step(9)
     _compare_state(lat, ora, 12 * u)
+
+
+@pytest.fixture(scope="module")
+def spinodal_separated():
+    """The 512^2 VdW spinodal lattice (rho = 2.6 (1 + 0.01 U)) after 1500 oracle
+    steps: phase-separated, densities from about 1.1 to 6.4, so that deviations from
+    w_i 2.6 are as large as on the benchmarked 4096^2 lattice."""
+    ora = C3_512.oracle()
+    ora.step(1500)
+    return ora
+
+
+@pytest.mark.parametrize("prec,u", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+@pytest.mark.parametrize("start", ["initial", "separated"])
+def test_reduced_storage_rho_ref_26(prec, u, start, spinodal_separated):
+    """The 16-bit storage the benchmark runs: deviations from w_i 2.6 (rho_ref =
+    2.6) on the spinodal lattice, one and ten steps against the oracle, from the
+    initial field and from a phase-separated state (set as the checkpoint, one
+    rounding), with the bounds of the literal base (3u, 12u of max |f|)."""
+    p = {"f16": lbm.LBM_F16DEV, "bf16": lbm.LBM_BF16DEV}[prec]
+    lat = lbm.Lattice(C3_512.lbm_params(p, rho_ref=2.6), C3_512.rho0())
+    if start == "initial":
+        ora = C3_512.oracle()
+    else:
+        ora = OracleLattice(spinodal_separated.p, C3_512.rho0())
+        ora.f[:] = spinodal_separated.f
+        lat.set_state(ora.f, 0)
+    lat.step(1)
+    ora.step(1)
+    e1 = _compare_state(lat, ora, 3 * u)
+    lat.step(9)
+    ora.step(9)
+    e10 = _compare_state(lat, ora, 12 * u)
+    print("%s rho_ref 2.6 from the %s state: %.2f u after 1 step, %.2f u after 10" % (prec, start, e1 / u,
+                                                                                     e10 / u))
 
 
 @pytest.mark.parametrize("prec,u", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
