@@ -89,8 +89,34 @@ typedef struct {
     double kappa;           /* gradient coefficient of Eq 1, >= 0                                */
     double rho_ref;         /* deviation base of the FP16/BF16 storage (ignored otherwise)       */
     int32_t monitor_every;  /* evaluate mass / residual / divergence every m steps; 0 = never    */
-    int32_t reserved;       /* must be 0                                                         */
+    int32_t scheme;         /* LBM_FORCE_* | LBM_COLLIDE_*; 0 = the paper's method (Eq 12, BGK) */
+    double trt_lambda;      /* LBM_COLLIDE_TRT: (tau - 1/2)(tau_minus - 1/2); 0 = 1/4             */
+    double mrt_s_e;         /* LBM_COLLIDE_MRT: rate of the energy moment e; 0 = 1                */
+    double mrt_s_eps;       /* rate of the energy-square moment epsilon; 0 = 1                   */
+    double mrt_s_q;         /* rate of the heat-flux moments; 0 = 8 (2 - 1/tau) / (8 - 1/tau)   */
 } lbm_params;
+
+/* Variants of the step that Sec. II names beside the paper's method, selected by
+ * lbm_params.scheme (force | collision).  The force: the chemical-potential form
+ * F = -rho grad(mu) + c_s^2 grad(rho) of Eq 12 (the paper's), or the divergence of
+ * the full pressure tensor, F = -div P + c_s^2 grad(rho) with P from Eq 9 (the
+ * form Eq 12 replaces; periodic lattices only, since P carries no surface
+ * chemical potential).  The collision: BGK (Eq 13), two relaxation times (the
+ * even part of f relaxes at 1/tau, the odd part at 1/tau_minus), or multiple
+ * relaxation times on the D2Q9 moments of Lallemand and Luo (rho, e, epsilon,
+ * j_x, q_x, j_y, q_y, p_xx, p_xy; the stress moments and j relax at 1/tau).  The
+ * force enters every collision through the equilibrium velocity as in the
+ * forcing paragraph after Eq 14, each relaxing part shifted by F / (rho s) with
+ * its own rate s, so the momentum gains exactly F per step and equal rates give
+ * BGK.  Schemes other than 0 need FP64 or FP32 storage, run the 64 x 16 tile
+ * shape only, and are not offered for batches (LBM_EINVAL otherwise). */
+enum {
+    LBM_FORCE_CP = 0,        /* Eq 12, the paper's method                    */
+    LBM_FORCE_PTENSOR = 1,   /* Eq 5 with the pressure tensor of Eq 9         */
+    LBM_COLLIDE_BGK = 0,
+    LBM_COLLIDE_TRT = 16,
+    LBM_COLLIDE_MRT = 32
+};
 
 /* Bytes of device workspace that lbm_init needs for these parameters (0 if invalid). */
 size_t lbm_workspace_bytes(const lbm_params* p);

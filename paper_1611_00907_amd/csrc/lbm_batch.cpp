@@ -101,6 +101,7 @@ lbm_status validate_batch(const lbm_params* cases, int n) {
         const lbm_status st = validate(&cases[i]);
         if (st != LBM_OK) return st;
         if (cases[i].prec != cases[0].prec) return LBM_EINVAL;
+        if (cases[i].scheme != 0) return LBM_EINVAL;  // the variants run on single lattices only
     }
     return LBM_OK;
 }

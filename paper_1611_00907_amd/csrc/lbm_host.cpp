@@ -66,7 +66,16 @@ lbm_status validate(const lbm_params* p) {
     for (double v : vals)
         if (!std::isfinite(v)) return LBM_EINVAL;
     if (p->a < 0 || p->b <= 0 || p->R <= 0 || p->Tr <= 0 || p->tau <= 0.5 || p->kappa < 0) return LBM_EINVAL;
-    if (p->monitor_every < 0 || p->reserved != 0) return LBM_EINVAL;
+    if (p->monitor_every < 0) return LBM_EINVAL;
+    const int force = p->scheme & 15, coll = p->scheme & ~15;
+    if (force > LBM_FORCE_PTENSOR || (coll != LBM_COLLIDE_BGK && coll != LBM_COLLIDE_TRT && coll != LBM_COLLIDE_MRT))
+        return LBM_EINVAL;
+    if (p->scheme != 0 && p->prec != LBM_F64 && p->prec != LBM_F32) return LBM_EINVAL;
+    if (force == LBM_FORCE_PTENSOR && walled(*p)) return LBM_EINVAL;
+    const double rates[] = {p->trt_lambda, p->mrt_s_e, p->mrt_s_eps, p->mrt_s_q};
+    for (double v : rates)
+        if (!std::isfinite(v) || v < 0) return LBM_EINVAL;
+    if (p->mrt_s_e >= 2 || p->mrt_s_eps >= 2 || p->mrt_s_q >= 2) return LBM_EINVAL;  // rates in (0, 2)
     const long long pitch = ((long long)p->nx + PITCH_ALIGN - 1) / PITCH_ALIGN * PITCH_ALIGN;
     if (pitch * (long long)p->ny > INT_MAX) return LBM_EINVAL;  // in-plane offsets are 32-bit
     // kernels address each direction plane with a 32-bit byte offset
@@ -107,6 +116,16 @@ LatticeArgs lattice_args(const lbm_params& p, const thermo::Fluid& fl, const Lay
     // 128 x 16 tiles where a lattice is at least that wide: the fastest tile at the
     // sizes measured, before any tuning
     A.tile_y = p.nx >= 128 ? 12816 : TILE_Y_DEFAULT;
+    A.scheme = p.scheme;
+    if (p.scheme != 0) A.tile_y = SCHEME_TILE_Y;  // the one shape the variants run
+    {
+        const double lambda = p.trt_lambda > 0 ? p.trt_lambda : 0.25;
+        A.tau_minus = 0.5 + lambda / (p.tau - 0.5);
+        const double sn = 1.0 / p.tau;
+        A.s_e = p.mrt_s_e > 0 ? p.mrt_s_e : 1.0;
+        A.s_eps = p.mrt_s_eps > 0 ? p.mrt_s_eps : 1.0;
+        A.s_q = p.mrt_s_q > 0 ? p.mrt_s_q : 8.0 * (2.0 - sn) / (8.0 - sn);
+    }
     A.plane = L.plane;
     A.tau = p.tau;
     A.inv_tau = 1.0 / p.tau;
@@ -479,11 +498,15 @@ lbm_status lbm_tune(lbm_ctx* c, int32_t trial_steps, int32_t* tile_y, double* be
     constexpr size_t MAX_SHAPES = std::size(TILE_Y_CHOICES) + std::size(WIDE_TILE_CODES) + std::size(HOIST_CODES) +
                                   MARCH_K_MAX;
     int shapes[MAX_SHAPES], nshapes = 0;
-    for (int ty : TILE_Y_CHOICES) shapes[nshapes++] = ty;
-    for (int code : WIDE_TILE_CODES) shapes[nshapes++] = code;
-    for (int code : HOIST_CODES) shapes[nshapes++] = code;
-    if (march_allowed(c->A, c->p.prec))
-        for (int k = 1; k <= MARCH_K_MAX; ++k) shapes[nshapes++] = -k;
+    if (c->A.scheme != 0) {
+        shapes[nshapes++] = SCHEME_TILE_Y;
+    } else {
+        for (int ty : TILE_Y_CHOICES) shapes[nshapes++] = ty;
+        for (int code : WIDE_TILE_CODES) shapes[nshapes++] = code;
+        for (int code : HOIST_CODES) shapes[nshapes++] = code;
+        if (march_allowed(c->A, c->p.prec))
+            for (int k = 1; k <= MARCH_K_MAX; ++k) shapes[nshapes++] = -k;
+    }
     for (int k = 0; k < nshapes; ++k) {
         const int ty = shapes[k];
         LatticeArgs A = c->A;
@@ -521,6 +544,10 @@ lbm_status lbm_tune(lbm_ctx* c, int32_t trial_steps, int32_t* tile_y, double* be
 lbm_status lbm_set_tile(lbm_ctx* c, int32_t tile_y) {
     if (!c) return LBM_EINVAL;
     bool ok = false;
+    if (c->A.scheme != 0) {
+        if (tile_y != SCHEME_TILE_Y) return LBM_EINVAL;
+        return LBM_OK;
+    }
     for (int ty : TILE_Y_CHOICES) ok = ok || ty == tile_y;
     for (int code : WIDE_TILE_CODES) ok = ok || code == tile_y;
     for (int code : HOIST_CODES) ok = ok || code == tile_y;

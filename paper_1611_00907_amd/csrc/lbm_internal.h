@@ -60,7 +60,15 @@ struct LatticeArgs {
     double sp_lo, sp_hi;  // spinodal band: the 16-bit storage types evaluate psi' in FP64
                           // for sp_lo < rho < sp_hi (empty band: both 0)
     EosConst eos;
+    int scheme;           // force (bits 0-3) | collision (bits 4-7); 0 = Eq 12 with BGK
+    int pad_;
+    double tau_minus;     // TRT: relaxation time of the odd part
+    double s_e, s_eps, s_q;  // MRT rates of e, epsilon and the heat-flux moments
 };
+
+enum Scheme : int { FORCE_CP = 0, FORCE_PTENSOR = 1, COLLIDE_BGK = 0, COLLIDE_TRT = 16, COLLIDE_MRT = 32 };
+// The tile shape that runs the schemes other than 0.
+constexpr int SCHEME_TILE_Y = 16;
 
 enum StepMode : int { MODE_STEP = 0, MODE_FIELDS = 1 };
 

@@ -220,6 +220,27 @@ __device__ __forceinline__ typename Codec<ST>::CT mu_node(const LatticeArgs& A, 
     return mu_bulk<EOS, CT>(A.eos, rho);
 }
 
+// Bulk pressure p0(rho) of the EOS: Eq 16 (VdW), Eq 25 (CS), Eq 22 (PR), Eq 19 (RK,
+// RKS); it enters the pressure tensor of Eq 9.
+template <int EOS, typename CT>
+__device__ __forceinline__ CT p_bulk(const EosConst& E, CT rho) {
+    const CT RT = CT(E.RT), a = CT(E.a), b = CT(E.b), c1 = CT(E.c1);
+    if constexpr (EOS == EOS_CS) {
+        const CT q = c1 * rho, om = CT(1) - q;
+        return rho * RT * (((CT(1) + q) + q * q) - q * q * q) * rcp(om * om * om) - a * rho * rho;
+    } else {
+        const CT rep = rho * RT * rcp(CT(1) - b * rho);
+        if constexpr (EOS == EOS_VDW) {
+            return rep - a * rho * rho;
+        } else if constexpr (EOS == EOS_PR) {
+            const CT br = b * rho;
+            return rep - a * rho * rho * rcp(CT(1) + CT(2) * br - br * br);
+        } else {  // RK, RKS
+            return rep - a * rho * rho * rcp(CT(1) + b * rho);
+        }
+    }
+}
+
 // Isotropic Laplacian 6 sum_i w_i (phi_i - phi_0) on an LDS tile.
 template <typename CT, int W>
 __device__ __forceinline__ CT lap9(const CT (*s)[W], int r, int c) {
@@ -276,6 +297,85 @@ __device__ __forceinline__ void collide(const CT f[9], CT rho, CT jx, CT jy, CT 
     for (int i = 0; i < 9; ++i) fs[i] = f[i] - (f[i] - feq[i]) * inv_tau;
 }
 
+// Eq 14 at density rho and velocity (ux, uy).
+template <typename CT>
+__device__ __forceinline__ void feq9(CT rho, CT ux, CT uy, CT fe[9]) {
+    const CT usq = CT(1.5) * (ux * ux + uy * uy);
+    const CT r0 = Wt<CT>::w0 * rho, r1 = Wt<CT>::w1 * rho, r2 = Wt<CT>::w2 * rho;
+    const CT d5 = ux + uy, d6 = uy - ux;
+    fe[0] = r0 * (CT(1) - usq);
+    fe[1] = r1 * (CT(1) + CT(3) * ux + CT(4.5) * ux * ux - usq);
+    fe[3] = r1 * (CT(1) - CT(3) * ux + CT(4.5) * ux * ux - usq);
+    fe[2] = r1 * (CT(1) + CT(3) * uy + CT(4.5) * uy * uy - usq);
+    fe[4] = r1 * (CT(1) - CT(3) * uy + CT(4.5) * uy * uy - usq);
+    fe[5] = r2 * (CT(1) + CT(3) * d5 + CT(4.5) * d5 * d5 - usq);
+    fe[7] = r2 * (CT(1) - CT(3) * d5 + CT(4.5) * d5 * d5 - usq);
+    fe[6] = r2 * (CT(1) + CT(3) * d6 + CT(4.5) * d6 * d6 - usq);
+    fe[8] = r2 * (CT(1) - CT(3) * d6 + CT(4.5) * d6 * d6 - usq);
+}
+
+// Collision of the variants with a given force F: BGK (Eq 13), TRT or MRT, each
+// relaxing part towards the equilibrium at u + F / (rho s) for its own rate s.
+template <typename CT, int COLL>
+__device__ __forceinline__ void collide_with_force(const LatticeArgs& A, const CT f[9], CT rho, CT jx, CT jy,
+                                                   CT Fx, CT Fy, CT fs[9]) {
+    const CT inv_rho = rcp(rho);
+    const CT ux = jx * inv_rho, uy = jy * inv_rho, gx = Fx * inv_rho, gy = Fy * inv_rho;
+    const CT tau = CT(A.tau), inv_tau = CT(A.inv_tau);
+    if constexpr (COLL == COLLIDE_BGK) {
+        CT fe[9];
+        feq9<CT>(rho, ux + tau * gx, uy + tau * gy, fe);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fs[i] = f[i] - (f[i] - fe[i]) * inv_tau;
+    } else if constexpr (COLL == COLLIDE_TRT) {
+        const CT tm = CT(A.tau_minus), inv_tm = rcp(tm);
+        CT fe[9], fo[9];
+        feq9<CT>(rho, ux + tau * gx, uy + tau * gy, fe);  // the even part's equilibrium
+        feq9<CT>(rho, ux + tm * gx, uy + tm * gy, fo);    // the odd part's
+        constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int o = opp[i];
+            const CT ev = CT(0.5) * ((f[i] + f[o]) - (fe[i] + fe[o]));
+            const CT od = CT(0.5) * ((f[i] - f[o]) - (fo[i] - fo[o]));
+            fs[i] = f[i] - ev * inv_tau - od * inv_tm;
+        }
+    } else {  // MRT, Lallemand-Luo moments; equilibrium moments in closed form
+        const CT se = CT(A.s_e), sp = CT(A.s_eps), sq = CT(A.s_q);
+        // velocities shifted for each rate: 1/tau (j, stress), s_e, s_eps, s_q
+        const CT vx = ux + tau * gx, vy = uy + tau * gy;
+        const CT ex = ux + gx * rcp(se), ey = uy + gy * rcp(se);
+        const CT px = ux + gx * rcp(sp), py = uy + gy * rcp(sp);
+        const CT qx = ux + gx * rcp(sq), qy = uy + gy * rcp(sq);
+        const CT axis = (f[1] + f[2]) + (f[3] + f[4]), diag = (f[5] + f[6]) + (f[7] + f[8]);
+        const CT m_e = CT(-4) * f[0] - axis + CT(2) * diag;
+        const CT m_p = CT(4) * f[0] - CT(2) * axis + diag;
+        const CT m_qx = CT(-2) * (f[1] - f[3]) + ((f[5] - f[6]) - (f[7] - f[8]));
+        const CT m_qy = CT(-2) * (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
+        const CT m_xx = (f[1] + f[3]) - (f[2] + f[4]);
+        const CT m_xy = (f[5] + f[7]) - (f[6] + f[8]);
+        // s_k (m_k - m_k^eq) / |row k|^2
+        const CT de = se * (m_e - rho * (CT(-2) + CT(3) * (ex * ex + ey * ey))) * CT(1.0 / 36.0);
+        const CT dp = sp * (m_p - rho * (CT(1) - CT(3) * (px * px + py * py))) * CT(1.0 / 36.0);
+        const CT djx = -Fx * CT(1.0 / 6.0), djy = -Fy * CT(1.0 / 6.0);  // (1/tau)(j - rho (u + tau F/rho)) / 6
+        const CT dqx = sq * (m_qx + rho * qx) * CT(1.0 / 12.0);
+        const CT dqy = sq * (m_qy + rho * qy) * CT(1.0 / 12.0);
+        const CT dxx = inv_tau * (m_xx - rho * (vx * vx - vy * vy)) * CT(0.25);
+        const CT dxy = inv_tau * (m_xy - rho * vx * vy) * CT(0.25);
+        // f* = f - M^T d, column by column of M
+        fs[0] = f[0] - (CT(-4) * de + CT(4) * dp);
+        fs[1] = f[1] - (((-de - CT(2) * dp) + (djx - CT(2) * dqx)) + dxx);
+        fs[2] = f[2] - (((-de - CT(2) * dp) + (djy - CT(2) * dqy)) - dxx);
+        fs[3] = f[3] - (((-de - CT(2) * dp) - (djx - CT(2) * dqx)) + dxx);
+        fs[4] = f[4] - (((-de - CT(2) * dp) - (djy - CT(2) * dqy)) - dxx);
+        const CT c = CT(2) * de + dp;
+        fs[5] = f[5] - (c + ((djx + dqx) + (djy + dqy)) + dxy);
+        fs[6] = f[6] - (c + (-(djx + dqx) + (djy + dqy)) - dxy);
+        fs[7] = f[7] - (c - ((djx + dqx) + (djy + dqy)) + dxy);
+        fs[8] = f[8] - (c + ((djx + dqx) - (djy + dqy)) - dxy);
+    }
+}
+
 __device__ __forceinline__ int tile_of_block(int b, int nblk) {
     // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
     // band of tiles so that halos shared by neighbouring tiles stay in its L2.
@@ -284,10 +384,17 @@ __device__ __forceinline__ int tile_of_block(int b, int nblk) {
 }
 
 // ---------------------------------------------------------------- the fused step
-template <typename CT, int TY, int TX = TILE_X>
+template <typename CT, int TY, int TX = TILE_X, bool PT = false>
 struct TileLds {
     CT rs[TY + 4][TX + 4];  // density, tile + 2-node ring
     CT ms[TY + 2][TX + 2];  // chemical potential, tile + 1-node ring
+};
+// The pressure-tensor force also keeps P_xx, P_yy, P_xy on the tile + 1-node ring.
+template <typename CT, int TY, int TX>
+struct TileLds<CT, TY, TX, true> {
+    CT rs[TY + 4][TX + 4];
+    CT ms[TY + 2][TX + 2];
+    CT ps[3][TY + 2][TX + 2];
 };
 
 // Ring slot q of a TX x TY tile's two-node density ring (2 (TX + 4) + 2 (TX + 4) +
@@ -337,12 +444,13 @@ __device__ __forceinline__ void tile_pull(const LatticeArgs& A, const Planes<ST>
 // tile and its ring into LDS, chemical potential, force, collision and store.
 // HOIST: the ring's pulls go out right after the own pulls, before the first wait
 // (one memory round trip instead of two, at the cost of registers).
-template <typename ST, int EOS, int MODE, int TY, int TX, int RPT, bool HOIST = false>
+template <typename ST, int EOS, int MODE, int TY, int TX, int RPT, bool HOIST = false, int FORCE = FORCE_CP,
+          int COLL = COLLIDE_BGK>
 __device__ __forceinline__ void tile_rest(const LatticeArgs& A, const Planes<ST>& F, ST* __restrict__ fout,
                                           const typename Codec<ST>::CT* __restrict__ mu_w,
                                           double* __restrict__ out, int x0, int y0,
                                           typename Codec<ST>::CT f[RPT][9],
-                                          TileLds<typename Codec<ST>::CT, TY, TX>& L) {
+                                          TileLds<typename Codec<ST>::CT, TY, TX, FORCE == FORCE_PTENSOR>& L) {
     using CT = typename Codec<ST>::CT;
     using C = Codec<ST>;
     constexpr int RW = TX + 4, MW = TX + 2;
@@ -451,6 +559,22 @@ __device__ __forceinline__ void tile_rest(const LatticeArgs& A, const Planes<ST>
 
     // 3. chemical potential, Eq 8, on the tile and a one-node ring
     const CT kappa = CT(A.kappa);
+    if constexpr (FORCE == FORCE_PTENSOR) {
+        // the pressure tensor of Eq 9 on the tile and a one-node ring (periodic
+        // lattices only), and the chemical potential for the field output
+        for (int q = threadIdx.x; q < (TY + 2) * MW; q += NT) {
+            const int r = q / MW, c = q % MW;
+            const CT rho = rs[r + 1][c + 1];
+            const CT lap = lap9<CT, RW>(rs, r + 1, c + 1);
+            CT gx, gy;
+            grad9<CT, RW>(rs, r + 1, c + 1, gx, gy);
+            const CT pd = p_bulk<EOS, CT>(A.eos, rho) - kappa * rho * lap - CT(0.5) * kappa * (gx * gx + gy * gy);
+            L.ps[0][r][c] = pd + kappa * gx * gx;
+            L.ps[1][r][c] = pd + kappa * gy * gy;
+            L.ps[2][r][c] = kappa * gx * gy;
+            if (MODE == MODE_FIELDS) ms[r][c] = mu_node<EOS, ST>(A, rho) - kappa * lap;
+        }
+    } else
     for (int q = threadIdx.x; q < (TY + 2) * MW; q += NT) {
         const int r = q / MW, c = q % MW;
         const int y = y0 - 1 + r;
@@ -501,12 +625,32 @@ __device__ __forceinline__ void tile_rest(const LatticeArgs& A, const Planes<ST>
             continue;
         }
         CT gmx, gmy, grx, gry;
-        grad9<CT, MW>(ms, ry + 1, lx + 1, gmx, gmy);
         grad9<CT, RW>(rs, ry + 2, lx + 2, grx, gry);
+        if constexpr (FORCE == FORCE_PTENSOR) {
+            // F = -div P + c_s^2 grad(rho), Eq 5; (gmx, gmy) carry div P
+            CT dxx, dyx, dxy, dyy, dxn, dyn;
+            grad9<CT, MW>(L.ps[0], ry + 1, lx + 1, dxx, dyx);
+            grad9<CT, MW>(L.ps[2], ry + 1, lx + 1, dxy, dyy);
+            grad9<CT, MW>(L.ps[1], ry + 1, lx + 1, dxn, dyn);
+            gmx = dxx + dyy;
+            gmy = dxy + dyn;
+        } else {
+            grad9<CT, MW>(ms, ry + 1, lx + 1, gmx, gmy);
+        }
+        constexpr CT third = CT(1) / CT(3);
+        // the force: Eq 12 (-rho grad mu) or Eq 5 (-div P), plus c_s^2 grad(rho)
+        auto force = [&](CT& Fx, CT& Fy) {
+            if constexpr (FORCE == FORCE_PTENSOR) {
+                Fx = -gmx + grx * third;
+                Fy = -gmy + gry * third;
+            } else {
+                Fx = -rho * gmx + grx * third;
+                Fy = -rho * gmy + gry * third;
+            }
+        };
         if (MODE == MODE_FIELDS) {
-            constexpr CT third = CT(1) / CT(3);
-            const CT Fx = -rho * gmx + grx * third;
-            const CT Fy = -rho * gmy + gry * third;
+            CT Fx, Fy;
+            force(Fx, Fy);
             const CT inv_rho = rcp(rho);
             const long long o = (long long)gy * A.nx + gx_raw;
             const long long P = (long long)A.nx * A.ny;
@@ -517,7 +661,13 @@ __device__ __forceinline__ void tile_rest(const LatticeArgs& A, const Planes<ST>
             continue;
         }
         CT fs[9];
-        collide<CT>(f[k], rho, jx[k], jy[k], gmx, gmy, grx, gry, tau, inv_tau, fs);
+        if constexpr (FORCE == FORCE_CP && COLL == COLLIDE_BGK) {
+            collide<CT>(f[k], rho, jx[k], jy[k], gmx, gmy, grx, gry, tau, inv_tau, fs);
+        } else {
+            CT Fx, Fy;
+            force(Fx, Fy);
+            collide_with_force<CT, COLL>(A, f[k], rho, jx[k], jy[k], Fx, Fy, fs);
+        }
         const unsigned o = unsigned(gy) * unsigned(A.pitch) + unsigned(gx_raw);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -529,31 +679,34 @@ __device__ __forceinline__ void tile_rest(const LatticeArgs& A, const Planes<ST>
 
 // One TX x TY tile of the step or of the field output, run by a workgroup of
 // TX * TY / RPT threads, RPT nodes of one column per thread.
-template <typename ST, int EOS, int MODE, int TY, int TX = TILE_X, int RPT = ROWS_PER_THREAD, bool HOIST = false>
+template <typename ST, int EOS, int MODE, int TY, int TX = TILE_X, int RPT = ROWS_PER_THREAD, bool HOIST = false,
+          int FORCE = FORCE_CP, int COLL = COLLIDE_BGK>
 __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __restrict__ fin,
                                           ST* __restrict__ fout,
                                           const typename Codec<ST>::CT* __restrict__ mu_w,
                                           double* __restrict__ out, int x0, int y0,
-                                          TileLds<typename Codec<ST>::CT, TY, TX>& L) {
+                                          TileLds<typename Codec<ST>::CT, TY, TX, FORCE == FORCE_PTENSOR>& L) {
     using CT = typename Codec<ST>::CT;
     Planes<ST> F;
 #pragma unroll
     for (int i = 0; i < 9; ++i) F.p[i] = fin + (long long)i * A.plane;
     CT f[RPT][9];
     tile_pull<ST, TY, TX, RPT>(A, F, x0, y0, f);
-    tile_rest<ST, EOS, MODE, TY, TX, RPT, HOIST>(A, F, fout, mu_w, out, x0, y0, f, L);
+    tile_rest<ST, EOS, MODE, TY, TX, RPT, HOIST, FORCE, COLL>(A, F, fout, mu_w, out, x0, y0, f, L);
 }
 
 // One lattice: one workgroup per tile.
-template <typename ST, int EOS, int MODE, int TY, int TX = TILE_X, int RPT = ROWS_PER_THREAD, bool HOIST = false>
+template <typename ST, int EOS, int MODE, int TY, int TX = TILE_X, int RPT = ROWS_PER_THREAD, bool HOIST = false,
+          int FORCE = FORCE_CP, int COLL = COLLIDE_BGK>
 __global__ __launch_bounds__(TX * TY / RPT) void step_kernel(LatticeArgs A, const ST* __restrict__ fin,
                                                             ST* __restrict__ fout,
                                                             const typename Codec<ST>::CT* __restrict__ mu_w,
                                                             double* __restrict__ out) {
-    __shared__ TileLds<typename Codec<ST>::CT, TY, TX> L;
+    __shared__ TileLds<typename Codec<ST>::CT, TY, TX, FORCE == FORCE_PTENSOR> L;
     const int t = tile_of_block(blockIdx.x, gridDim.x);
     const int tiles_x = (A.nx + TX - 1) / TX;
-    step_tile<ST, EOS, MODE, TY, TX, RPT, HOIST>(A, fin, fout, mu_w, out, (t % tiles_x) * TX, (t / tiles_x) * TY, L);
+    step_tile<ST, EOS, MODE, TY, TX, RPT, HOIST, FORCE, COLL>(A, fin, fout, mu_w, out, (t % tiles_x) * TX,
+                                                              (t / tiles_x) * TY, L);
 }
 
 // Many lattices in one persistent launch: each workgroup walks a contiguous range
@@ -1206,15 +1359,44 @@ __global__ void get_state_kernel(LatticeArgs A, const ST* __restrict__ fstore, d
     for (int i = 0; i < 9; ++i) f_out[(long long)i * n + c] = double(f[i]);
 }
 
-template <typename ST, int EOS, int MODE, int TY, int TX, int RPT, bool HOIST = false>
+template <typename ST, int EOS, int MODE, int TY, int TX, int RPT, bool HOIST = false, int FORCE = FORCE_CP,
+          int COLL = COLLIDE_BGK>
 hipError_t step_launch(const LatticeArgs& A, const void* fin, void* fout, const void* mu_w, double* out,
                        hipStream_t s) {
     using CT = typename Codec<ST>::CT;
     const int tiles = ((A.nx + TX - 1) / TX) * ((A.ny + TY - 1) / TY);
     (void)hipGetLastError();  // drop any error left by earlier runtime calls
-    hipLaunchKernelGGL((step_kernel<ST, EOS, MODE, TY, TX, RPT, HOIST>), dim3(tiles), dim3(TX * TY / RPT), 0, s, A,
-                       (const ST*)fin, (ST*)fout, (const CT*)mu_w, out);
+    hipLaunchKernelGGL((step_kernel<ST, EOS, MODE, TY, TX, RPT, HOIST, FORCE, COLL>), dim3(tiles),
+                       dim3(TX * TY / RPT), 0, s, A, (const ST*)fin, (ST*)fout, (const CT*)mu_w, out);
     return hipGetLastError();
+}
+
+// The variants of the step (force of Eq 5, TRT / MRT collision): 64 x 16 tiles,
+// FP64 and FP32 storage.
+template <typename ST, int EOS, int MODE>
+hipError_t step_scheme(const LatticeArgs& A, const void* fin, void* fout, const void* mu_w, double* out,
+                       hipStream_t s) {
+    if constexpr (sizeof(ST) < 4) {
+        return hipErrorInvalidValue;
+    } else {
+        static_assert(SCHEME_TILE_Y == 16, "the variants are instantiated for 64 x 16 tiles");
+        switch (A.scheme) {
+        case FORCE_CP | COLLIDE_TRT:
+            return step_launch<ST, EOS, MODE, 16, 64, 4, false, FORCE_CP, COLLIDE_TRT>(A, fin, fout, mu_w, out, s);
+        case FORCE_CP | COLLIDE_MRT:
+            return step_launch<ST, EOS, MODE, 16, 64, 4, false, FORCE_CP, COLLIDE_MRT>(A, fin, fout, mu_w, out, s);
+        case FORCE_PTENSOR | COLLIDE_BGK:
+            return step_launch<ST, EOS, MODE, 16, 64, 4, false, FORCE_PTENSOR, COLLIDE_BGK>(A, fin, fout, mu_w, out,
+                                                                                           s);
+        case FORCE_PTENSOR | COLLIDE_TRT:
+            return step_launch<ST, EOS, MODE, 16, 64, 4, false, FORCE_PTENSOR, COLLIDE_TRT>(A, fin, fout, mu_w, out,
+                                                                                           s);
+        case FORCE_PTENSOR | COLLIDE_MRT:
+            return step_launch<ST, EOS, MODE, 16, 64, 4, false, FORCE_PTENSOR, COLLIDE_MRT>(A, fin, fout, mu_w, out,
+                                                                                           s);
+        default: return hipErrorInvalidValue;
+        }
+    }
 }
 
 template <typename ST, int EOS, int MODE>
@@ -1257,6 +1439,9 @@ hipError_t march_launch(int k, const LatticeArgs& A, const void* fin, void* fout
 template <typename ST, int EOS>
 hipError_t step_eos(int mode, int tile_y, const LatticeArgs& A, const void* fin, void* fout, const void* mu_w,
                     double* out, hipStream_t s) {
+    if (A.scheme != 0)
+        return mode == MODE_STEP ? step_scheme<ST, EOS, MODE_STEP>(A, fin, fout, mu_w, out, s)
+                                 : step_scheme<ST, EOS, MODE_FIELDS>(A, fin, fout, mu_w, out, s);
     if (mode == MODE_STEP && tile_y < 0) return march_launch<ST, EOS>(-tile_y, A, fin, fout, mu_w, s);
     if (mode == MODE_STEP) return step_ty<ST, EOS, MODE_STEP>(tile_y, A, fin, fout, mu_w, out, s);
     return step_ty<ST, EOS, MODE_FIELDS>(16, A, fin, fout, mu_w, out, s);  // output uses one shape

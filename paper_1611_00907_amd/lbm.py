@@ -52,15 +52,23 @@ class LbmParams(C.Structure):
                 ("eos", C.c_int32), ("prec", C.c_int32), ("a", C.c_double), ("b", C.c_double),
                 ("R", C.c_double), ("omega", C.c_double), ("Tr", C.c_double), ("tau", C.c_double),
                 ("kappa", C.c_double), ("rho_ref", C.c_double), ("monitor_every", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("scheme", C.c_int32), ("trt_lambda", C.c_double), ("mrt_s_e", C.c_double),
+                ("mrt_s_eps", C.c_double), ("mrt_s_q", C.c_double)]
+
+
+# lbm_params.scheme: force | collision
+LBM_FORCE_CP, LBM_FORCE_PTENSOR = 0, 1
+LBM_COLLIDE_BGK, LBM_COLLIDE_TRT, LBM_COLLIDE_MRT = 0, 16, 32
 
 
 def make_params(nx, ny, eos, a, b, Tr, tau, kappa, R=1.0, omega=0.0, prec=LBM_F32,
                 bc_bottom=LBM_BC_PERIODIC, bc_top=LBM_BC_PERIODIC, rho_ref=1.0,
-                monitor_every=0) -> LbmParams:
+                monitor_every=0, scheme=0, trt_lambda=0.0, mrt_s_e=0.0, mrt_s_eps=0.0,
+                mrt_s_q=0.0) -> LbmParams:
     return LbmParams(int(nx), int(ny), int(bc_bottom), int(bc_top), int(eos), int(prec), float(a),
                      float(b), float(R), float(omega), float(Tr), float(tau), float(kappa),
-                     float(rho_ref), int(monitor_every), 0)
+                     float(rho_ref), int(monitor_every), int(scheme), float(trt_lambda), float(mrt_s_e),
+                     float(mrt_s_eps), float(mrt_s_q))
 
 
 class LbmError(RuntimeError):

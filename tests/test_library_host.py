@@ -162,3 +162,24 @@ def test_null_handles_are_rejected(lbm):
     lib = lbm.load_library()
     assert lib.lbm_batch_set_schedule(None, 16, 0) == lbm.LBM_EINVAL
     assert lib.lbm_set_tile(None, 16) == lbm.LBM_EINVAL
+
+
+def test_scheme_validation(lbm):
+    """The variants of the step are validated on the host: the pressure-tensor force
+    needs a periodic lattice, the variants need FP64 or FP32 storage, the scheme
+    bits and the relaxation rates must be valid, and batches take scheme 0 only."""
+    ok = _params(lbm, scheme=lbm.LBM_FORCE_PTENSOR | lbm.LBM_COLLIDE_MRT)
+    assert lbm.lbm_workspace_bytes(ok) > 0
+    assert lbm.lbm_workspace_bytes(_params(lbm, scheme=lbm.LBM_COLLIDE_TRT, trt_lambda=0.1)) > 0
+    bad = [_params(lbm, scheme=lbm.LBM_FORCE_PTENSOR, bc_bottom=lbm.LBM_BC_CPWALL, bc_top=lbm.LBM_BC_NEUTRAL),
+           _params(lbm, scheme=lbm.LBM_COLLIDE_TRT, prec=lbm.LBM_F16DEV),
+           _params(lbm, scheme=lbm.LBM_COLLIDE_MRT, prec=lbm.LBM_BF16DEV),
+           _params(lbm, scheme=2), _params(lbm, scheme=48), _params(lbm, scheme=8),
+           _params(lbm, scheme=lbm.LBM_COLLIDE_MRT, mrt_s_e=2.0),
+           _params(lbm, scheme=lbm.LBM_COLLIDE_MRT, mrt_s_q=-0.5),
+           _params(lbm, scheme=lbm.LBM_COLLIDE_TRT, trt_lambda=float("nan"))]
+    for p in bad:
+        assert lbm.lbm_workspace_bytes(p) == 0, p.scheme
+    L = lbm.load_library()
+    arr = (lbm.LbmParams * 1)(_params(lbm, scheme=lbm.LBM_COLLIDE_TRT))
+    assert L.lbm_batch_workspace_bytes(arr, 1) == 0
