@@ -51,9 +51,11 @@ def parse():
     ap.add_argument("--warmstart", action="store_true",
                     help="also run the learned warm-start experiment live (2000 cases at 256^2: "
                          "equilibria, training, cold vs warm sweep; several minutes)")
-    ap.add_argument("--workload", choices=("spinodal4096", "wetting1024"), default="spinodal4096",
-                    help="main measurement: the 4096^2 FP32 spinodal lattice (default, HBM-bound) or the "
-                         "1024^2 FP32 wetting configuration (cache-resident; for profiling)")
+    ap.add_argument("--workload", choices=("spinodal4096", "wetting1024", "spinodal4096_f16dev",
+                                           "spinodal4096_bf16dev", "batch256"), default="spinodal4096",
+                    help="main measurement: the 4096^2 FP32 spinodal lattice (default, HBM-bound); the others "
+                         "(the 1024^2 FP32 wetting lattice, the 16-bit storage types, the 256-case batch) "
+                         "are reported under aux and can be run alone as the main line for profiling")
     return ap.parse_args()
 
 
@@ -121,7 +123,29 @@ def measure_batch(lbm, inputs, steps):
             "grid": "one workgroup per (case, tile) entry" if bpc < 0 else "%d workgroups per CU, persistent" % bpc,
             "roofline": {"bound": "hbm", "achieved": round(nodes * 72.0 * n / t / 1e9, 1), "peak": PEAK_HBM_GBS,
                          "unit": "GB/s", "frac": round(nodes * 72.0 * n / t / 1e9 / PEAK_HBM_GBS, 4),
-                         "traffic": None}}
+                         "traffic": traffic_for("step_f32_batch256", ty)}}
+
+
+def measure_variants(lbm, inputs, steps=100):
+    """The force of Eq 5 (pressure tensor) against Eq 12 (chemical potential), and
+    the TRT / MRT collisions against BGK, on the 4096^2 FP32 spinodal lattice with
+    the one tile shape every variant runs (64 x 16): kernel time per step."""
+    variants = [("eq12_bgk", 0), ("eq5_bgk", lbm.LBM_FORCE_PTENSOR), ("eq12_trt", lbm.LBM_COLLIDE_TRT),
+                ("eq12_mrt", lbm.LBM_COLLIDE_MRT), ("eq5_mrt", lbm.LBM_FORCE_PTENSOR | lbm.LBM_COLLIDE_MRT)]
+    p0, rho0, _, fluid = spinodal_workload(lbm, inputs, lbm.LBM_F32)
+    out = {"workload": "force and collision variants, spinodal 4096x4096 VdW Tr=0.85, f32 storage, 64x16 tiles",
+           "kernel_us": {}, "achieved_gbs": {}}
+    for name, scheme in variants:
+        p = _with_monitor(p0, 0)
+        p.scheme = scheme
+        lat = lbm.Lattice(p, rho0)
+        lat.set_tile(16)
+        lat.step(32)
+        t = lat.step_timed(steps) / 1e3 / steps
+        lat.close()
+        out["kernel_us"][name] = round(t * 1e6, 2)
+        out["achieved_gbs"][name] = round(fluid * 72.0 / t / 1e9, 1)
+    return out
 
 
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
@@ -321,13 +345,25 @@ def main():
 
     copy_gbs = lbm.lbm_copy_bandwidth(args.copy_bytes, 20)
     print("copy: %.1f GB/s over %d bytes" % (copy_gbs, args.copy_bytes), file=sys.stderr, flush=True)
+    dtype = "f32"
+    if args.workload == "batch256":
+        res = measure_batch(lbm, inputs, args.steps)
+        print(json.dumps({"workload": "batch256", "aux": [res]}), flush=True)
+        return
     if args.workload == "spinodal4096":
         p, rho0, mu_w, fluid = spinodal_workload(lbm, inputs, lbm.LBM_F32)
-        config = dict(SPINODAL_CONFIG)
-    else:
+        config, bpl, wname = dict(SPINODAL_CONFIG), 72.0, "step_f32_spinodal4096"
+    elif args.workload == "wetting1024":
         p, rho0, mu_w, fluid = wetting_workload(lbm, inputs, lbm.LBM_F32)
-        config = dict(WETTING_CONFIG)
-    main_res = measure(lbm, p, rho0, mu_w, fluid, args.steps, args.warmup, 72.0, "step_f32_" + args.workload)
+        config, bpl, wname = dict(WETTING_CONFIG), 72.0, "step_f32_wetting1024"
+    else:
+        dtype = args.workload.split("_")[1]
+        prec = lbm.LBM_F16DEV if dtype == "f16dev" else lbm.LBM_BF16DEV
+        p, rho0, mu_w, fluid = spinodal_workload(lbm, inputs, prec)
+        config = dict(SPINODAL_CONFIG, storage=dtype,
+                      workload=SPINODAL_CONFIG["workload"].replace("FP32 storage", "%s storage" % dtype))
+        bpl, wname = 36.0, "step_%s_spinodal4096" % dtype
+    main_res = measure(lbm, p, rho0, mu_w, fluid, args.steps, args.warmup, bpl, wname)
     config["monitor_every"] = main_res["monitor_every"]
     print("main: %.1f MLUPS, step %.2f us, kernel %.2f us, %.1f GB/s" % (
         main_res["mlups"], main_res["ms_per_step"] * 1e3, main_res["kernel_us"], main_res["roofline"]["achieved"]),
@@ -335,7 +371,7 @@ def main():
 
     aux = []
     if not args.no_aux:
-        if args.workload == "spinodal4096":
+        if args.workload != "wetting1024":
             pp, r0, mw, fl = wetting_workload(lbm, inputs, lbm.LBM_F32)
             res = measure(lbm, pp, r0, mw, fl, 1000, 100, 72.0, "step_f32_wetting1024")
             aux.append({"workload": WETTING_CONFIG["workload"], "mlups": round(res["mlups"], 1),
@@ -344,6 +380,8 @@ def main():
             print("aux f32 wetting1024: %.1f MLUPS %.1f GB/s" % (res["mlups"], res["roofline"]["achieved"]),
                   file=sys.stderr, flush=True)
         for prec, name, b in ((lbm.LBM_F16DEV, "f16dev", 36.0), (lbm.LBM_BF16DEV, "bf16dev", 36.0)):
+            if args.workload.endswith(name):
+                continue
             pp, r0, _, fl = spinodal_workload(lbm, inputs, prec)
             res = measure(lbm, pp, r0, None, fl, 300, 20, b, "step_%s_spinodal4096" % name)
             aux.append({"workload": "spinodal 4096x4096 VdW Tr=0.85, %s storage (deviations from w_i 2.6)" % name,
@@ -351,6 +389,9 @@ def main():
                         "shape": res["shape"], "roofline": res["roofline"]})
             print("aux %s: %.1f MLUPS %.1f GB/s" % (name, res["mlups"], res["roofline"]["achieved"]),
                   file=sys.stderr, flush=True)
+        res = measure_variants(lbm, inputs)
+        aux.append(res)
+        print("aux variants: %s us" % res["kernel_us"], file=sys.stderr, flush=True)
         res = measure_batch(lbm, inputs, 320)
         aux.append(res)
         print("aux batch: %.1f MLUPS %.1f GB/s (tile %d, %s)" % (res["mlups"], res["roofline"]["achieved"],
@@ -372,7 +413,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype,
         "data": "synthetic",
         "config": config,
         "roofline": main_res["roofline"],
@@ -387,7 +428,8 @@ def main():
     if ws is not None:
         line["warm_start"] = ws
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.workload)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, "wetting1024" if args.workload == "wetting1024"
+                                            else "spinodal4096")
     print(json.dumps(line), flush=True)
 
 

@@ -11,6 +11,7 @@ Pieces:
                            equal-area coexistence, surface tension.
   * ``contact``         -- contact angle from a density field (Sec. V formula).
   * ``lattice``         -- ctypes binding of the C step and a small driver class.
+  * ``cplbm3d_oracle.c`` / ``lattice3d`` -- the same step on D3Q19, periodic box.
 
 Each function is pinned by ``tests/test_oracle_*.py`` against closed forms,
 invariants or brute force; anything not pinned says "parity unpinned".
