@@ -148,6 +148,23 @@ def measure_variants(lbm, inputs, steps=100):
     return out
 
 
+def measure_d3q19(lbm, inputs, n=256, steps=50):
+    """The D3Q19 step on a periodic n^3 box of the spinodal workload (VdW, Tr =
+    0.85, tau = 1, kappa = 0.01, rho = 2.6 (1 + 0.01 U)), FP32 storage: 152
+    algorithmic bytes per node update (19 loads and 19 stores)."""
+    p = lbm.make_params(n, n, lbm.LBM_EOS_VDW, 9 / 49, 2 / 21, 0.85, 1.0, 0.01, prec=lbm.LBM_F32)
+    rho0 = inputs.with_relative_noise(np.full((n, n, n), 2.6), 0.01, 3)
+    lat = lbm.Lattice3(p, n, rho0)
+    lat.step(5)
+    t = lat.step_timed(steps) / 1e3 / steps
+    lat.close()
+    nodes = n ** 3
+    return {"workload": "D3Q19 spinodal %d^3 periodic VdW Tr=0.85, f32 storage (density pass + fused step pass)" % n,
+            "mlups": round(nodes / t / 1e6, 1), "ms_per_step": round(t * 1e3, 4),
+            "roofline": {"bound": "hbm", "achieved": round(nodes * 152.0 / t / 1e9, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(nodes * 152.0 / t / 1e9 / PEAK_HBM_GBS, 4), "traffic": None}}
+
+
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
 
 
@@ -392,6 +409,10 @@ def main():
         res = measure_variants(lbm, inputs)
         aux.append(res)
         print("aux variants: %s us" % res["kernel_us"], file=sys.stderr, flush=True)
+        res = measure_d3q19(lbm, inputs)
+        aux.append(res)
+        print("aux d3q19: %.1f MLUPS %.1f GB/s" % (res["mlups"], res["roofline"]["achieved"]), file=sys.stderr,
+              flush=True)
         res = measure_batch(lbm, inputs, 320)
         aux.append(res)
         print("aux batch: %.1f MLUPS %.1f GB/s (tile %d, %s)" % (res["mlups"], res["roofline"]["achieved"],

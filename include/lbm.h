@@ -216,6 +216,37 @@ const char* lbm_strerror(lbm_status s);
  * the failing call and the HIP error name.  Owned by the library. */
 const char* lbm_last_error(void);
 
+/* ---- three dimensions: D3Q19 ------------------------------------------- */
+
+/* The same method (Eqs 8, 12, 13, 14) on the D3Q19 velocity set, w = 1/3 (rest),
+ * 1/18 (axis), 1/36 (edge), c_s^2 = 1/3, with the isotropic stencils of those
+ * weights (lap = 6 sum_i w_i (phi_i - phi_0), grad = 3 sum_i w_i e_i phi_i), on a
+ * box periodic in x, y and z.  Sec. II notes that the chemical-potential force
+ * avoids storing the pressure tensor, which in 3-D has six components.
+ * Direction order (the layout of lbm3d_get_state): 0 rest; 1 +x, 2 -x, 3 +y,
+ * 4 -y, 5 +z, 6 -z; 7 (+x+y), 8 (-x-y), 9 (+x-y), 10 (-x+y), 11 (+x+z),
+ * 12 (-x-z), 13 (+x-z), 14 (-x+z), 15 (+y+z), 16 (-y-z), 17 (+y-z), 18 (-y+z).
+ * Fields are [nz][ny][nx] doubles, x fastest. */
+typedef struct lbm3d lbm3d;
+
+/* p gives nx, ny, the EOS, Tr, tau, kappa and the storage (LBM_F64 or LBM_F32);
+ * both boundaries must be LBM_BC_PERIODIC and scheme 0; nz >= 1; nx ny nz < 2^31.
+ * The fluid starts at rest, f = f_eq(rho0, 0).  The library allocates the device
+ * memory (two 19-plane buffers and one density plane) and its own stream.
+ * Errors: LBM_EINVAL, LBM_EDOMAIN (rho0 outside the EOS domain), LBM_ENOMEM, LBM_EHIP. */
+lbm_status lbm3d_init(const lbm_params* p, int32_t nz, const double* rho0, lbm3d** out);
+/* n steps; each is two launches (a density pass, then the fused chemical
+ * potential, force, collision and streaming pass).  Asynchronous. */
+lbm_status lbm3d_step(lbm3d* c, int64_t n);
+/* lbm3d_step between HIP events on the box's stream; *ms is the device time. */
+lbm_status lbm3d_step_timed(lbm3d* c, int64_t n, double* ms);
+/* Density, physical velocity v = u + F / (2 rho) and chemical potential (any
+ * pointer may be NULL).  Synchronises. */
+lbm_status lbm3d_get_fields(lbm3d* c, double* rho, double* vx, double* vy, double* vz, double* mu);
+/* Post-streaming distributions f_i(x, t), [19][nz][ny][nx], and the step count. */
+lbm_status lbm3d_get_state(lbm3d* c, double* f, int64_t* step);
+void lbm3d_destroy(lbm3d* c);
+
 /* ---- many lattices in one launch ---------------------------------------- */
 
 /* A batch of independent lattices (sizes, EOS, temperature, tau, kappa, walls may

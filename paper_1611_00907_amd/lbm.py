@@ -33,7 +33,8 @@ LBM_BC_PERIODIC, LBM_BC_CPWALL, LBM_BC_NEUTRAL = 0, 1, 2
 NOALLOC_MAX_NODES = 2097152
 
 EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lbm_get_fields",
-            "lbm_get_fields_noalloc",
+            "lbm_get_fields_noalloc", "lbm3d_init", "lbm3d_step", "lbm3d_step_timed", "lbm3d_get_fields",
+            "lbm3d_get_state", "lbm3d_destroy",
             "lbm_set_wall_mu", "lbm_tune", "lbm_set_tile",
             "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_step_timed",
             "lbm_batch_run", "lbm_batch_status", "lbm_batch_get_fields", "lbm_batch_get_state",
@@ -152,6 +153,13 @@ def load_library():
     lib.sur_read.argtypes = [vp, C.c_char_p, vp, C.c_int64, C.POINTER(C.c_int64)]
     lib.sur_destroy.argtypes = [vp]
     lib.sur_destroy.restype = None
+    lib.lbm3d_init.argtypes = [P, C.c_int32, vp, C.POINTER(vp)]
+    lib.lbm3d_step.argtypes = [vp, C.c_int64]
+    lib.lbm3d_step_timed.argtypes = [vp, C.c_int64, dp]
+    lib.lbm3d_get_fields.argtypes = [vp] + [vp] * 5
+    lib.lbm3d_get_state.argtypes = [vp, vp, C.POINTER(C.c_int64)]
+    lib.lbm3d_destroy.argtypes = [vp]
+    lib.lbm3d_destroy.restype = None
     lib.lbm_critical_point.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, dp, dp, dp]
     lib.lbm_coexistence.argtypes = [P, dp, dp, dp, dp]
     lib.lbm_spinodal.argtypes = [P, dp, dp]
@@ -161,7 +169,7 @@ def load_library():
     for name in EXPORTED:
         if name not in ("lbm_workspace_bytes", "lbm_destroy", "lbm_strerror", "lbm_last_error",
                         "lbm_batch_workspace_bytes", "lbm_batch_fluid_nodes", "lbm_batch_destroy",
-                        "sur_param_count", "sur_destroy"):
+                        "sur_param_count", "sur_destroy", "lbm3d_destroy"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -448,6 +456,54 @@ class Batch:
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:
             self.lib.lbm_batch_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- D3Q19
+class Lattice3:
+    """A periodic D3Q19 box (``lbm3d_*``); fields [nz][ny][nx], distributions
+    [19][nz][ny][nx] in the direction order of lbm.h."""
+
+    def __init__(self, p: LbmParams, nz: int, rho0):
+        self.lib = load_library()
+        self.p, self.nz = p, int(nz)
+        self.shape = (self.nz, p.ny, p.nx)
+        rho0 = _f64(rho0)
+        if rho0.shape != self.shape:
+            raise ValueError("rho0 shape %s, expected %s" % (rho0.shape, self.shape))
+        ctx = C.c_void_p()
+        _check(self.lib.lbm3d_init(C.byref(p), self.nz, _p(rho0), C.byref(ctx)), "lbm3d_init")
+        self.ctx = ctx
+
+    def step(self, n: int):
+        _check(self.lib.lbm3d_step(self.ctx, int(n)), "lbm3d_step")
+
+    def step_timed(self, n: int) -> float:
+        ms = C.c_double()
+        _check(self.lib.lbm3d_step_timed(self.ctx, int(n), C.byref(ms)), "lbm3d_step_timed")
+        return ms.value
+
+    def fields(self):
+        out = {k: np.empty(self.shape) for k in ("rho", "vx", "vy", "vz", "mu")}
+        _check(self.lib.lbm3d_get_fields(self.ctx, *[_p(out[k]) for k in ("rho", "vx", "vy", "vz", "mu")]),
+               "lbm3d_get_fields")
+        return out
+
+    def get_state(self):
+        f = np.empty((19,) + self.shape)
+        s = C.c_int64()
+        _check(self.lib.lbm3d_get_state(self.ctx, _p(f), C.byref(s)), "lbm3d_get_state")
+        return f, s.value
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self.lib.lbm3d_destroy(self.ctx)
             self.ctx = C.c_void_p()
 
     def __del__(self):

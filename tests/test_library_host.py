@@ -24,7 +24,7 @@ def lbm():
 
 def test_exports_every_declared_symbol(lbm):
     header = open(os.path.join(ROOT, "include", "lbm.h")).read()
-    declared = set(re.findall(r"\b((?:lbm|sur)_[a-z_]+)\s*\(", header))
+    declared = set(re.findall(r"\b((?:lbm3d|lbm|sur)_[a-z_0-9]+)\s*\(", header))
     lib = lbm.load_library()
     for name in declared:
         assert hasattr(lib, name), name
