@@ -290,7 +290,7 @@ lbm_status lbm_batch_get_fields(lbm_batch* b, int32_t i, double* rho, double* vx
                                 double* mu);
 lbm_status lbm_batch_get_state(lbm_batch* b, int32_t i, double* f);
 
-/* Tunes the tile height and the grid of the batched launch on the active cases
+/* Tunes the tile shape (as lbm_batch_set_schedule) and the grid of the batched launch on the active cases
  * without changing their state; keeps and returns the fastest.  The grid is k
  * workgroups per compute unit, each walking a contiguous run of the (case, tile)
  * list (*blocks_per_cu = k), or one workgroup per list entry (*blocks_per_cu = -1,
@@ -298,7 +298,8 @@ lbm_status lbm_batch_get_state(lbm_batch* b, int32_t i, double* f);
 lbm_status lbm_batch_tune(lbm_batch* b, int32_t trial_steps, int32_t* tile_y,
                           int32_t* blocks_per_cu, double* best_ms);
 
-/* Sets the tile height (8, 16 or 32) and the grid of the batched launch directly:
+/* Sets the tile shape (64-wide tiles of height 8, 16 or 32, or the wide shape codes
+ * 12816 and 25608: 128 x 16 and 256 x 8 tiles) and the grid of the batched launch directly:
  * blocks_per_cu = k > 0 workgroups per compute unit, 0 as many as fit, -1 one
  * workgroup per (case, tile) entry (the schedule of a new batch, with tile height
  * 16).  LBM_EINVAL for other values.  Every schedule computes the same step. */

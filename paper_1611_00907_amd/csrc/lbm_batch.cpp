@@ -2,6 +2,8 @@
 // chemical potential) advanced together by one persistent launch per step.
 #include <hip/hip_runtime.h>
 
+#include <iterator>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -58,8 +60,10 @@ struct BatchLayout {
     int total_tiles;
 };
 
-int tiles_for(const lbm_params& p, int tile_y) {
-    return ((p.nx + TILE_X - 1) / TILE_X) * ((p.ny + tile_y - 1) / tile_y);
+// Tiles of one case for the tile shape code (a 64-wide height or a wide code).
+int tiles_for(const lbm_params& p, int code) {
+    const int tx = tile_tx(code), ty = tile_ty(code);
+    return ((p.nx + tx - 1) / tx) * ((p.ny + ty - 1) / ty);
 }
 
 // Tile lists are sized for the smallest tile height, so that any tuned shape fits.
@@ -461,7 +465,11 @@ lbm_status lbm_batch_tune(lbm_batch* b, int32_t trial_steps, int32_t* tile_y, in
     HIP_TRY(hipEventCreate(&ev.a));
     HIP_TRY(hipEventCreate(&ev.b));
     hipEvent_t e0 = ev.a, e1 = ev.b;
-    for (int ty : TILE_Y_CHOICES) {
+    constexpr int NCODES = int(std::size(TILE_Y_CHOICES) + std::size(BATCH_WIDE_CODES));
+    int codes[NCODES], nc = 0;
+    for (int ty : TILE_Y_CHOICES) codes[nc++] = ty;
+    for (int code : BATCH_WIDE_CODES) codes[nc++] = code;
+    for (int ty : codes) {
         for (int bpc : {0, 1, 2, 4, -1}) {
             lbm_status st = set_schedule(b, ty, bpc);
             if (st != LBM_OK) return st;
@@ -496,6 +504,7 @@ lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t tile_y, int32_t blocks_p
     if (!b || blocks_per_cu < -1 || blocks_per_cu > 64) return LBM_EINVAL;
     bool ok = false;
     for (int ty : TILE_Y_CHOICES) ok = ok || ty == tile_y;
+    for (int code : BATCH_WIDE_CODES) ok = ok || code == tile_y;
     if (!ok) return LBM_EINVAL;
     if (hipSetDevice(b->device) != hipSuccess) return LBM_EHIP;
     return set_schedule(b, tile_y, blocks_per_cu);

@@ -23,6 +23,12 @@ constexpr int TILE_Y_CHOICES[3] = {8, 16, 32};
 // thread), each run by 512 threads.  A wider tile pulls a smaller fraction of
 // redundant ring nodes.
 constexpr int WIDE_TILE_CODES[4] = {12816, 12832, 25608, 25616};
+// Batches take the 64-wide heights of TILE_Y_CHOICES and these wide shape codes
+// (128 x 16 and 256 x 8, 4 rows per thread, 512 threads).
+constexpr int BATCH_WIDE_CODES[2] = {12816, 25608};
+// Columns and rows of a tile with shape code `code` (a 64-wide height or 100 * width + height).
+constexpr int tile_tx(int code) { return code >= 10000 ? code / 100 : TILE_X; }
+constexpr int tile_ty(int code) { return code >= 10000 ? code % 100 : code; }
 // 64-wide tiles whose ring pulls go out with the own pulls (one memory round trip
 // instead of two, more registers), as shape codes 1000000 + height.
 constexpr int HOIST_BASE = 1000000;

@@ -711,27 +711,27 @@ __global__ __launch_bounds__(TX * TY / RPT) void step_kernel(LatticeArgs A, cons
 
 // Many lattices in one persistent launch: each workgroup walks a contiguous range
 // of the (case, tile) list; the ranges of the workgroups on one XCD are adjacent.
-template <typename ST, int TY>
-__global__ __launch_bounds__(TILE_X * TY / ROWS_PER_THREAD) void batch_step_kernel(
+template <typename ST, int TY, int TX = TILE_X>
+__global__ __launch_bounds__(TX * TY / ROWS_PER_THREAD) void batch_step_kernel(
     const CaseDesc* __restrict__ cases, const int2* __restrict__ tiles, int ntiles, int parity) {
     using CT = typename Codec<ST>::CT;
-    __shared__ TileLds<CT, TY> L;
+    __shared__ TileLds<CT, TY, TX> L;
     const int chunk = tile_of_block(blockIdx.x, gridDim.x);
     const int begin = int((long long)ntiles * chunk / gridDim.x);
     const int end = int((long long)ntiles * (chunk + 1) / gridDim.x);
     for (int t = begin; t < end; ++t) {
         const int2 w = tiles[t];
         const CaseDesc& C = cases[w.x];
-        const int tiles_x = (C.A.nx + TILE_X - 1) / TILE_X;
-        const int x0 = (w.y % tiles_x) * TILE_X, y0 = (w.y / tiles_x) * TY;
+        const int tiles_x = (C.A.nx + TX - 1) / TX;
+        const int x0 = (w.y % tiles_x) * TX, y0 = (w.y / tiles_x) * TY;
         const ST* fin = static_cast<const ST*>(C.f[parity]);
         ST* fout = static_cast<ST*>(C.f[parity ^ 1]);
         const CT* mw = static_cast<const CT*>(C.mu_w);
         switch (C.eos) {
-        case EOS_VDW: step_tile<ST, EOS_VDW, MODE_STEP, TY>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
-        case EOS_CS: step_tile<ST, EOS_CS, MODE_STEP, TY>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
-        case EOS_PR: step_tile<ST, EOS_PR, MODE_STEP, TY>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
-        default: step_tile<ST, EOS_RK, MODE_STEP, TY>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
+        case EOS_VDW: step_tile<ST, EOS_VDW, MODE_STEP, TY, TX>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
+        case EOS_CS: step_tile<ST, EOS_CS, MODE_STEP, TY, TX>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
+        case EOS_PR: step_tile<ST, EOS_PR, MODE_STEP, TY, TX>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
+        default: step_tile<ST, EOS_RK, MODE_STEP, TY, TX>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
         }
         __syncthreads();  // the next tile reuses the LDS
     }
@@ -1207,7 +1207,7 @@ __global__ __launch_bounds__(64) void monitor_reduce(const double* __restrict__ 
 
 // Monitors of many lattices: one workgroup per (case, tile); per-tile partials, then
 // one workgroup per case reduces its contiguous tile range in a fixed order.
-template <typename ST, int COMPARE, int TY>
+template <typename ST, int COMPARE, int TY, int TX = TILE_X>
 __global__ __launch_bounds__(MON_THREADS) void batch_monitor_kernel(const CaseDesc* __restrict__ cases,
                                                                     const int2* __restrict__ tiles, int parity,
                                                                     double* __restrict__ partials) {
@@ -1220,12 +1220,12 @@ __global__ __launch_bounds__(MON_THREADS) void batch_monitor_kernel(const CaseDe
 #pragma unroll
     for (int i = 0; i < 9; ++i) F.p[i] = fin + (long long)i * A.plane;
     CT* rho_mon = static_cast<CT*>(C.rho_mon);
-    const int tiles_x = (A.nx + TILE_X - 1) / TILE_X;
-    const int x0 = (w.y % tiles_x) * TILE_X, y0 = (w.y / tiles_x) * TY;
+    const int tiles_x = (A.nx + TX - 1) / TX;
+    const int x0 = (w.y % tiles_x) * TX, y0 = (w.y / tiles_x) * TY;
     double mass = 0.0, res = 0.0;
     int flags = 0;
-    for (int i = threadIdx.x; i < TILE_X * TY; i += MON_THREADS) {
-        const int x = x0 + i % TILE_X, y = y0 + i / TILE_X;
+    for (int i = threadIdx.x; i < TX * TY; i += MON_THREADS) {
+        const int x = x0 + i % TX, y = y0 + i / TX;
         if (x >= A.nx || y >= A.ny || solid_row(A, y)) continue;
         const CT r = fluid_rho<ST, CT>(A, F, x, y);
         const unsigned o = unsigned(y) * unsigned(A.pitch) + unsigned(x);
@@ -1479,44 +1479,44 @@ hipError_t monitor_prec(int compare, const LatticeArgs& A, const void* fin, void
     return hipGetLastError();
 }
 
+template <typename ST, int TY, int TX>
+void batch_step_one(int grid, const CaseDesc* cases, const int2* tiles, int ntiles, int parity, hipStream_t s) {
+    hipLaunchKernelGGL((batch_step_kernel<ST, TY, TX>), dim3(grid), dim3(TX * TY / ROWS_PER_THREAD), 0, s, cases,
+                       tiles, ntiles, parity);
+}
+
+// code: a 64-wide tile height (8, 16, 32) or a wide shape code (12816, 25608)
 template <typename ST>
-hipError_t batch_step_prec(int tile_y, const CaseDesc* cases, const int2* tiles, int ntiles, int parity, int grid,
+hipError_t batch_step_prec(int code, const CaseDesc* cases, const int2* tiles, int ntiles, int parity, int grid,
                            hipStream_t s) {
     (void)hipGetLastError();
-    switch (tile_y) {
-    case 8:
-        hipLaunchKernelGGL((batch_step_kernel<ST, 8>), dim3(grid), dim3(TILE_X * 8 / ROWS_PER_THREAD), 0, s, cases,
-                           tiles, ntiles, parity);
-        break;
-    case 16:
-        hipLaunchKernelGGL((batch_step_kernel<ST, 16>), dim3(grid), dim3(TILE_X * 16 / ROWS_PER_THREAD), 0, s,
-                           cases, tiles, ntiles, parity);
-        break;
-    case 32:
-        hipLaunchKernelGGL((batch_step_kernel<ST, 32>), dim3(grid), dim3(TILE_X * 32 / ROWS_PER_THREAD), 0, s,
-                           cases, tiles, ntiles, parity);
-        break;
+    switch (code) {
+    case 8: batch_step_one<ST, 8, 64>(grid, cases, tiles, ntiles, parity, s); break;
+    case 16: batch_step_one<ST, 16, 64>(grid, cases, tiles, ntiles, parity, s); break;
+    case 32: batch_step_one<ST, 32, 64>(grid, cases, tiles, ntiles, parity, s); break;
+    case 12816: batch_step_one<ST, 16, 128>(grid, cases, tiles, ntiles, parity, s); break;
+    case 25608: batch_step_one<ST, 8, 256>(grid, cases, tiles, ntiles, parity, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <typename ST, int COMPARE, int TY, int TX>
+void batch_monitor_one(int ntiles, const CaseDesc* cases, const int2* tiles, int parity, double* partials,
+                       hipStream_t s) {
+    hipLaunchKernelGGL((batch_monitor_kernel<ST, COMPARE, TY, TX>), dim3(ntiles), dim3(MON_THREADS), 0, s, cases,
+                       tiles, parity, partials);
+}
+
 template <typename ST, int COMPARE>
-hipError_t batch_monitor_ty(int tile_y, const CaseDesc* cases, const int2* tiles, int ntiles, int parity,
+hipError_t batch_monitor_ty(int code, const CaseDesc* cases, const int2* tiles, int ntiles, int parity,
                             double* partials, hipStream_t s) {
-    switch (tile_y) {
-    case 8:
-        hipLaunchKernelGGL((batch_monitor_kernel<ST, COMPARE, 8>), dim3(ntiles), dim3(MON_THREADS), 0, s, cases,
-                           tiles, parity, partials);
-        break;
-    case 16:
-        hipLaunchKernelGGL((batch_monitor_kernel<ST, COMPARE, 16>), dim3(ntiles), dim3(MON_THREADS), 0, s, cases,
-                           tiles, parity, partials);
-        break;
-    case 32:
-        hipLaunchKernelGGL((batch_monitor_kernel<ST, COMPARE, 32>), dim3(ntiles), dim3(MON_THREADS), 0, s, cases,
-                           tiles, parity, partials);
-        break;
+    switch (code) {
+    case 8: batch_monitor_one<ST, COMPARE, 8, 64>(ntiles, cases, tiles, parity, partials, s); break;
+    case 16: batch_monitor_one<ST, COMPARE, 16, 64>(ntiles, cases, tiles, parity, partials, s); break;
+    case 32: batch_monitor_one<ST, COMPARE, 32, 64>(ntiles, cases, tiles, parity, partials, s); break;
+    case 12816: batch_monitor_one<ST, COMPARE, 16, 128>(ntiles, cases, tiles, parity, partials, s); break;
+    case 25608: batch_monitor_one<ST, COMPARE, 8, 256>(ntiles, cases, tiles, parity, partials, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1536,11 +1536,17 @@ hipError_t batch_monitor_prec(int compare, int tile_y, const CaseDesc* cases, co
 }
 
 template <typename ST>
-int batch_occupancy(int tile_y) {
+int batch_occupancy(int code) {
     int n = 0;
-    const int threads = TILE_X * tile_y / ROWS_PER_THREAD;
-    const void* k = tile_y == 8 ? (const void*)batch_step_kernel<ST, 8>
-                  : (tile_y == 16 ? (const void*)batch_step_kernel<ST, 16> : (const void*)batch_step_kernel<ST, 32>);
+    const int threads = tile_tx(code) * tile_ty(code) / ROWS_PER_THREAD;
+    const void* k = nullptr;
+    switch (code) {
+    case 8: k = (const void*)batch_step_kernel<ST, 8, 64>; break;
+    case 16: k = (const void*)batch_step_kernel<ST, 16, 64>; break;
+    case 32: k = (const void*)batch_step_kernel<ST, 32, 64>; break;
+    case 12816: k = (const void*)batch_step_kernel<ST, 16, 128>; break;
+    default: k = (const void*)batch_step_kernel<ST, 8, 256>; break;
+    }
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, 0) != hipSuccess || n < 1) n = 1;
     return n;
 }

@@ -69,6 +69,25 @@ def test_batch_schedules_agree(bpc):
         assert np.array_equal(b.get_state(i), f), "case %d" % i
 
 
+@pytest.mark.parametrize("code", [12816, 25608])
+@pytest.mark.parametrize("bpc", [-1, 0])
+def test_batch_wide_tiles_agree(code, bpc):
+    """The wide tiles (128 x 16, 256 x 8) in a batch give the single runs' FP32
+    result with the same shape bit for bit, and their monitors sum the same mass."""
+    cases = _cases(4)
+    b = _batch(cases, lbm.LBM_F32)
+    b.set_schedule(code, bpc)
+    b.run(40, check_every=20, window=1, tol=0.0)
+    st = b.status()
+    for i, c in enumerate(cases):
+        lat = _single(c, lbm.LBM_F32, tile_y=code)
+        lat.step(40)
+        f, _ = lat.get_state()
+        assert np.array_equal(b.get_state(i), f), "case %d" % i
+        rho = lat.fields()["rho"][1:-1]
+        assert abs(st["mass"][i] - rho.sum()) < 1e-9 * rho.sum(), i
+
+
 def test_batch_schedule_rejects_bad_values():
     b = _batch(_cases(1), lbm.LBM_F32)
     for ty, bpc in ((12, 0), (16, -2), (16, 65)):
@@ -188,7 +207,7 @@ def test_batch_tune_keeps_state_and_results():
     b.step(20)
     before = [b.get_state(i) for i in range(3)]
     ty, bpc, ms = b.tune(trial_steps=5)
-    assert ty in (8, 16, 32) and ms > 0
+    assert ty in (8, 16, 32, 12816, 25608) and ms > 0
     for i in range(3):
         assert np.array_equal(b.get_state(i), before[i])
     b.step(30)
