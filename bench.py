@@ -282,8 +282,9 @@ def measure(lbm, p, rho0, mu_w, fluid_nodes, steps, warmup, bytes_per_lu, worklo
 
 WARMSTART_RECORD = os.path.join(ROOT, "profiles", "warmstart_c5.json")
 WARMSTART_KEYS = ("n_cases", "side", "usable", "loss_first", "loss_last", "val_mse", "sweep_s_cold", "sweep_s_warm",
-                  "inference_s", "speedup", "steps_saved_median", "theta_pred_abs_err_median", "training_s",
-                  "generation_s")
+                  "inference_s", "speedup", "speedup_calibration_only", "masked_sweep_s_cold", "masked_sweep_s_warm",
+                  "speedup_masked", "speedup_masked_calibration_only", "steps_saved_median",
+                  "theta_pred_abs_err_median", "training_s", "generation_s")
 
 
 def warmstart_summary(live: bool):

@@ -280,8 +280,15 @@ lbm_status lbm_batch_step_timed(lbm_batch* b, int64_t n, double* ms);
 lbm_status lbm_batch_run(lbm_batch* b, int64_t max_steps, int32_t check_every, int32_t window,
                          double tol, int64_t* steps_run);
 
+/* Stops the listed cases for good (the caller's own criterion, e.g. a contact angle
+ * that has settled): they keep their state and step count and are masked out of
+ * every later step, as converged cases are.  Cases already stopped, converged or
+ * diverged are left as they are.  LBM_EINVAL for an index outside [0, n). */
+lbm_status lbm_batch_stop(lbm_batch* b, const int32_t* cases, int32_t count);
+
 /* Per-case arrays of n entries (any may be NULL): state 0 active, 1 converged,
- * 2 diverged; steps taken; last residual; last mass; last divergence flags. */
+ * 2 diverged, 3 stopped by lbm_batch_stop; steps taken; last residual; last mass;
+ * last divergence flags. */
 lbm_status lbm_batch_status(lbm_batch* b, int32_t* state, int64_t* steps, double* residual,
                             double* mass, int32_t* flags);
 

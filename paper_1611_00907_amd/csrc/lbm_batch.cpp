@@ -403,6 +403,21 @@ lbm_status lbm_batch_run(lbm_batch* b, int64_t max_steps, int32_t check_every, i
     return LBM_OK;
 }
 
+lbm_status lbm_batch_stop(lbm_batch* b, const int32_t* cases, int32_t count) {
+    if (!b || count < 0 || (count > 0 && !cases)) return LBM_EINVAL;
+    for (int32_t k = 0; k < count; ++k)
+        if (cases[k] < 0 || cases[k] >= b->n) return LBM_EINVAL;
+    if (hipSetDevice(b->device) != hipSuccess) return LBM_EHIP;
+    bool changed = false;
+    for (int32_t k = 0; k < count; ++k) {
+        if (b->state[cases[k]] != 0) continue;  // converged, diverged or stopped already
+        b->state[cases[k]] = 3;
+        changed = true;
+    }
+    // the list of active cases shrinks: rebuild it (and drop the captured graph)
+    return changed ? upload_tiles(b) : LBM_OK;
+}
+
 lbm_status lbm_batch_status(lbm_batch* b, int32_t* state, int64_t* steps, double* residual, double* mass,
                             int32_t* flags) {
     if (!b) return LBM_EINVAL;

@@ -37,7 +37,7 @@ EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lb
             "lbm3d_get_state", "lbm3d_destroy",
             "lbm_set_wall_mu", "lbm_tune", "lbm_set_tile",
             "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_step_timed",
-            "lbm_batch_run", "lbm_batch_status", "lbm_batch_get_fields", "lbm_batch_get_state",
+            "lbm_batch_run", "lbm_batch_stop", "lbm_batch_status", "lbm_batch_get_fields", "lbm_batch_get_state",
             "lbm_batch_tune", "lbm_batch_set_schedule", "lbm_batch_fluid_nodes", "lbm_batch_destroy", "lbm_copy_bandwidth",
             "sur_create", "sur_param_count", "sur_set_params", "sur_get_params", "sur_forward", "sur_gradients",
             "sur_set_dataset", "sur_train", "sur_trace", "sur_read", "sur_destroy",
@@ -130,6 +130,7 @@ def load_library():
     lib.lbm_batch_step.argtypes = [vp, C.c_int64]
     lib.lbm_batch_step_timed.argtypes = [vp, C.c_int64, dp]
     lib.lbm_batch_run.argtypes = [vp, C.c_int64, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.c_int64)]
+    lib.lbm_batch_stop.argtypes = [vp, vp, C.c_int32]
     lib.lbm_batch_status.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.lbm_batch_get_fields.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     lib.lbm_batch_get_state.argtypes = [vp, C.c_int32, vp]
@@ -411,6 +412,11 @@ class Batch:
         _check(self.lib.lbm_batch_run(self.ctx, int(max_steps), int(check_every), int(window), float(tol),
                                       C.byref(s)), "lbm_batch_run")
         return s.value
+
+    def stop(self, cases):
+        """Masks the given cases out of every later step (lbm_batch_stop)."""
+        idx = np.ascontiguousarray(np.atleast_1d(np.asarray(cases, dtype=np.int32)))
+        _check(self.lib.lbm_batch_stop(self.ctx, _p(idx), int(idx.size)), "lbm_batch_stop")
 
     def status(self):
         st = np.zeros(self.n, np.int32)

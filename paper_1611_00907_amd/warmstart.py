@@ -13,9 +13,11 @@ Pipeline, all through the C ABI (every numerical step runs in liblbm.so):
    T/Tc, wall chemical potential as a fraction of the wetting range) and targets
    (equilibrium density / liquid density).
 4. ``Surrogate`` training on the GPU (BF16 MFMA forward and backward, Adam).
-5. ``time_to_angle``: steps and device time until the contact angle stays within
-   a tolerance of the plain method's equilibrium angle, from the cold start (the
-   semicircle) and from the network's prediction.
+5. ``time_to_angle``: steps until the contact angle stays within a tolerance of
+   the plain method's equilibrium angle, from the cold start (the semicircle), from
+   the calibration's angle alone and from the network's prediction; cases that have
+   settled are stopped, so the sweep's device time is what a batch that drops its
+   finished cases spends.
 """
 from __future__ import annotations
 
@@ -233,30 +235,39 @@ def he_init(seed):
 def time_to_angle(specs, rho_starts, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000, hold=4,
                   log=None):
     """Per case, the step from which the contact angle stays within tol of theta_eq
-    (checked every check_every steps, -1 if never), running all cases as one batch
-    until every case has stayed inside for `hold` checks; also the device time per
-    batched step."""
+    (checked every check_every steps, -1 if never).  All cases start as one batch;
+    a case that has stayed inside for `hold` checks is stopped (masked out of the
+    batch, lbm_batch_stop), so the batch shrinks as cases settle.  Returns the
+    per-case steps, the device time per step of the full batch (first check
+    interval), and the device time of the whole masked sweep."""
     b = lbm.Batch([s.params() for s in specs], rho_starts, mu_w_bottom=[s.mu_w for s in specs])
     n = len(specs)
     first_in = np.full(n, -1, np.int64)
-    t_dev = 0.0
+    done = np.zeros(n, bool)
+    t_dev, t_full = 0.0, None
     steps = 0
     while True:
-        th = np.array([measure_angle(b.rho(i)) for i in range(n)])
-        inside = np.abs(th - theta_eq) <= tol_deg
-        first_in[~inside] = -1
-        first_in[inside & (first_in < 0)] = steps
-        if (first_in >= 0).all() and steps - first_in.max() >= hold * check_every:
+        act = np.flatnonzero(~done)
+        th = np.array([measure_angle(b.rho(i)) for i in act])
+        inside = np.abs(th - theta_eq[act]) <= tol_deg
+        first_in[act[~inside]] = -1
+        first_in[act[inside & (first_in[act] < 0)]] = steps
+        settled = act[(first_in[act] >= 0) & (steps - first_in[act] >= hold * check_every)]
+        if settled.size:
+            b.stop(settled)
+            done[settled] = True
+        if done.all() or steps >= max_steps:
             break
-        if steps >= max_steps:
-            break
-        t_dev += b.step_timed(check_every) / 1e3
+        dt = b.step_timed(check_every) / 1e3
+        if t_full is None:
+            t_full = dt / check_every
+        t_dev += dt
         steps += check_every
         if log and steps % (25 * check_every) == 0:
-            log("  step %d: %d of %d cases within %.1f deg" % (steps, int((first_in >= 0).sum()), n, tol_deg))
+            log("  step %d: %d of %d cases settled within %.1f deg" % (steps, int(done.sum()), n, tol_deg))
     b.close()
-    step_time = t_dev / max(steps, 1)
-    return first_in, step_time
+    first_in[~done] = -1
+    return first_in, (t_full if t_full is not None else 0.0), t_dev
 
 
 def _smooth(a):
@@ -392,30 +403,37 @@ def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000
     equilibrium angle, and the sweep's device time until its last case is there
     (for the warm start plus the network inference and the warm-field set-up)."""
     cold0 = [initial_density(s) for s in specs]
-    steps_cold, dt_cold = time_to_angle(specs, cold0, theta_eq, tol_deg, check_every, max_steps, log=log)
+    steps_cold, dt_cold, dev_cold = time_to_angle(specs, cold0, theta_eq, tol_deg, check_every, max_steps, log=log)
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as pool:  # numpy releases the GIL (more threads contend)
         x = np.stack(list(pool.map(features, specs)))
         pred = net.forward(x)
         warm0 = list(pool.map(lambda sp: warm_field(sp[0], sp[1], pinned), zip(specs, pred)))
     t_inf = time.perf_counter() - t0
-    steps_warm, dt_warm = time_to_angle(specs, warm0, theta_eq, tol_deg, check_every, max_steps, log=log)
+    steps_warm, dt_warm, dev_warm = time_to_angle(specs, warm0, theta_eq, tol_deg, check_every, max_steps, log=log)
     done = (steps_cold >= 0).all() and (steps_warm >= 0).all()
+    # sweep time, two ways: every case charged until the last one settles (the slowest
+    # case times the full batch), and the device time of the batch with settled cases
+    # masked out (what a sweep that stops its finished cases spends)
     t_cold = float(steps_cold.max() * dt_cold) if done else float("nan")
     t_warm = float(steps_warm.max() * dt_warm + t_inf) if done else float("nan")
     out = {"steps_cold": steps_cold, "steps_warm": steps_warm, "step_time_cold": dt_cold,
            "step_time_warm": dt_warm, "inference_s": t_inf, "pred": pred,
            "sweep_s_cold": t_cold, "sweep_s_warm": t_warm,
-           "speedup": t_cold / t_warm if done else float("nan")}
+           "speedup": t_cold / t_warm if done else float("nan"),
+           "masked_sweep_s_cold": dev_cold, "masked_sweep_s_warm": dev_warm + t_inf,
+           "speedup_masked": dev_cold / (dev_warm + t_inf) if done else float("nan")}
     if calibration_arm:
         # the same sweep started from the calibration's angle alone (no network):
         # what the trained network adds over the method without it
         cal0 = [cap_field(s, s.theta0) for s in specs]
-        steps_cal, dt_cal = time_to_angle(specs, cal0, theta_eq, tol_deg, check_every, max_steps, log=log)
+        steps_cal, dt_cal, dev_cal = time_to_angle(specs, cal0, theta_eq, tol_deg, check_every, max_steps, log=log)
         ok = (steps_cold >= 0).all() and (steps_cal >= 0).all()
         out["steps_calibration_only"] = steps_cal
         out["sweep_s_calibration_only"] = float(steps_cal.max() * dt_cal) if ok else float("nan")
         out["speedup_calibration_only"] = t_cold / out["sweep_s_calibration_only"] if ok else float("nan")
+        out["masked_sweep_s_calibration_only"] = dev_cal
+        out["speedup_masked_calibration_only"] = dev_cold / dev_cal if ok else float("nan")
     return out
 
 
@@ -500,6 +518,9 @@ def run_experiment(n_cases=2000, side=256, seed=11, n_val=100, n_test=100, train
     log("sweep to 0.5 deg: cold %.3f s, warm %.3f s (inference %.3f s): %.2fx; calibration angle alone %.2fx" %
         (out["sweep_s_cold"], out["sweep_s_warm"], out["inference_s"], out["speedup"],
          out.get("speedup_calibration_only", float("nan"))))
+    log("masked sweep (settled cases stopped): cold %.3f s, warm %.3f s: %.2fx; calibration angle alone %.2fx" %
+        (out["masked_sweep_s_cold"], out["masked_sweep_s_warm"], out["speedup_masked"],
+         out.get("speedup_masked_calibration_only", float("nan"))))
     net.close()
     return out
 

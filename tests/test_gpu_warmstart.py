@@ -22,24 +22,38 @@ def test_calibration_orders_wetting_range(table):
         assert lo < hi, (eos, Tr, lo, hi)
 
 
-def test_warm_start_beats_cold_start(table):
-    specs = W.draw_cases(72, seed=5, table=table, side=64, Tr_range=(0.7, 0.9))
-    rho_eq, state, steps, _ = W.generate(specs, max_steps=20000, check_every=1000, window=500, tol=1e-7)
-    ok = [i for i in range(len(specs)) if state[i] != 2 and np.isfinite(rho_eq[i]).all()]
-    theta = np.array([W.measure_angle(rho_eq[i]) for i in ok])
-    ok = [i for i, t in zip(ok, theta) if 35 < t < 160]
-    assert len(ok) >= 40
-    train, test = ok[:-8], ok[-8:]
+def test_warm_start_beats_cold_start_and_calibration(table):
+    """The learned warm start against the cold start and against the same sweep
+    started from the calibration's angle alone (the method without the network):
+    200 cases at 64^2, Tr in [0.7, 0.9], 176 to train (2000 Adam steps), 24 held out.
+    Measured: steps to within 0.5 degree of the plain equilibrium, median / mean / max,
+    cold 900 / 1046 / 1800, calibration only 700 / 688 / 1400, network 500-550 /
+    496-592 / 1100 (training is not bit-reproducible: its gradient sums are atomic).  The network's gain over the calibration is its prediction of the
+    equilibrium's bulk densities (the calibration arm starts from Maxwell's).  At
+    64^2 a whole sweep takes milliseconds, less than the features and inference, so
+    steps and not seconds are compared here; the 256^2 record compares times."""
+    specs = W.draw_cases(200, seed=5, table=table, side=64, Tr_range=(0.7, 0.9))
+    rho_eq, state, steps, drift = W.generate(specs, max_steps=30000, check_every=1000, window=500, tol=1e-7,
+                                             confirm_steps=5000)
+    theta = np.array([W.measure_angle(r) if np.isfinite(r).all() else np.nan for r in rho_eq])
+    ok = [i for i in range(len(specs)) if state[i] != 2 and 35 < theta[i] < 160 and drift[i] < 0.1]
+    assert len(ok) >= 150
+    train, test = ok[:-24], ok[-24:]
     net = lbm.Surrogate(64, max_batch=16)
     net.set_params(W.he_init(1))
-    x = np.stack([W.features(specs[i]) for i in train])
-    t = np.stack([W.target(specs[i], rho_eq[i]) for i in train])
-    net.set_dataset(x, t)
-    losses = net.train(400, 16, 1e-3, seed=2)
-    assert losses[-20:].mean() < 0.5 * losses[:10].mean()
+    net.set_dataset(np.stack([W.features(specs[i]) for i in train]),
+                    np.stack([W.target(specs[i], rho_eq[i]) for i in train]))
+    losses = net.train(2000, 16, 1e-3, seed=2)
+    assert losses[-20:].mean() < 0.01 * losses[:10].mean()
     tspecs = [specs[i] for i in test]
-    theta_eq = np.array([W.measure_angle(rho_eq[i]) for i in test])
-    res = W.evaluate(net, tspecs, theta_eq, tol_deg=0.5, check_every=100, max_steps=20000)
-    cold, warm = res["steps_cold"], res["steps_warm"]
-    assert (cold >= 0).all() and (warm >= 0).all(), (cold, warm)
-    assert np.median(warm) < np.median(cold), (cold, warm)
+    res = W.evaluate(net, tspecs, theta[test], tol_deg=0.5, check_every=100, max_steps=20000, calibration_arm=True)
+    cold, warm, cal = (np.asarray(res[k]) for k in ("steps_cold", "steps_warm", "steps_calibration_only"))
+    print("steps median / mean / max: cold %d / %.0f / %d, calibration %d / %.0f / %d, network %d / %.0f / %d" % (
+        np.median(cold), cold.mean(), cold.max(), np.median(cal), cal.mean(), cal.max(), np.median(warm),
+        warm.mean(), warm.max()))
+    print("masked sweep device time: cold %.4f s, calibration %.4f s, network %.4f s (incl. %.4f s inference)" % (
+        res["masked_sweep_s_cold"], res["masked_sweep_s_calibration_only"], res["masked_sweep_s_warm"],
+        res["inference_s"]))
+    assert (cold >= 0).all() and (warm >= 0).all() and (cal >= 0).all(), (cold, warm, cal)
+    assert np.median(warm) < np.median(cold)
+    assert warm.mean() < cal.mean() and warm.max() <= cal.max(), (warm, cal)
