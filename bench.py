@@ -52,10 +52,13 @@ def parse():
                     help="also run the learned warm-start experiment live (2000 cases at 256^2: "
                          "equilibria, training, cold vs warm sweep; several minutes)")
     ap.add_argument("--workload", choices=("spinodal4096", "wetting1024", "spinodal4096_f16dev",
-                                           "spinodal4096_bf16dev", "batch256"), default="spinodal4096",
+                                           "spinodal4096_bf16dev", "batch256", "batch256_residual"),
+                    default="spinodal4096",
                     help="main measurement: the 4096^2 FP32 spinodal lattice (default, HBM-bound); the others "
                          "(the 1024^2 FP32 wetting lattice, the 16-bit storage types, the 256-case batch) "
-                         "are reported under aux and can be run alone as the main line for profiling")
+                         "are reported under aux and can be run alone as the main line for profiling; "
+                         "batch256_residual runs the 256-case batch in FP64 storage to the residual "
+                         "max|drho| < 1e-9 per step (about two minutes) and reports how many cases get there")
     return ap.parse_args()
 
 
@@ -124,6 +127,52 @@ def measure_batch(lbm, inputs, steps):
             "roofline": {"bound": "hbm", "achieved": round(nodes * 72.0 * n / t / 1e9, 1), "peak": PEAK_HBM_GBS,
                          "unit": "GB/s", "frac": round(nodes * 72.0 * n / t / 1e9 / PEAK_HBM_GBS, 4),
                          "traffic": traffic_for("step_f32_batch256", ty)}}
+
+
+def measure_batch_residual(lbm, inputs, max_steps=200000, check_every=2000, window=1000, tol=1e-9):
+    """The batching configuration run to its stopping rule: every case in FP64
+    storage until max|rho(t) - rho(t - window)| / window < tol (the case then stops),
+    diverges, or max_steps pass.  FP32 storage cannot get there: its rounding keeps
+    the field moving at a few 1e-8 per step."""
+    params, rhos, muw = batch_workload(lbm, inputs)
+    for p in params:
+        p.prec = lbm.LBM_F64
+    b = lbm.Batch(params, rhos, mu_w_bottom=muw)
+    nodes = b.fluid_nodes()
+    t0 = time.perf_counter()
+    done = 0
+    while done < max_steps:
+        n = min(20000, max_steps - done)
+        b.run(n, check_every=check_every, window=window, tol=tol)
+        done += n
+        st = b.status()["state"]
+        print("batch256 FP64 to %.0e: %d steps, %d converged, %d diverged" % (tol, done, (st == 1).sum(),
+                                                                               (st == 2).sum()),
+              file=sys.stderr, flush=True)
+        if (st != 0).all():
+            break
+    wall = time.perf_counter() - t0
+    st = b.status()
+    b.close()
+    state, steps = st["state"], st["steps"]
+    pr = np.array([p.eos == lbm.LBM_EOS_PR for p in params])
+    Tr = np.array([p.Tr for p in params])
+    conv = state == 1
+
+    def rng(m):
+        return [round(float(Tr[m].min()), 3), round(float(Tr[m].max()), 3)] if m.any() else None
+
+    return {"workload": "batch of 256 droplet-on-wall cases, side 128-512, CS/PR, Tr 0.6-0.9, f64 storage, "
+                        "run to max|drho| < %.0e per step (window %d, checked every %d steps)" % (tol, window,
+                                                                                                check_every),
+            "fluid_nodes": nodes, "max_steps": max_steps, "wall_s": round(wall, 1),
+            "converged": int(conv.sum()), "diverged": int((state == 2).sum()), "still_running": int((state == 0).sum()),
+            "steps_converged_median": float(np.median(steps[conv])) if conv.any() else None,
+            "steps_converged_max": int(steps[conv].max()) if conv.any() else None,
+            "converged_cs_pr": [int((conv & ~pr).sum()), int((conv & pr).sum())],
+            "cases_cs_pr": [int((~pr).sum()), int(pr.sum())],
+            "diverged_pr_Tr": rng((state == 2) & pr), "diverged_cs": int(((state == 2) & ~pr).sum()),
+            "running_pr_Tr": rng((state == 0) & pr), "running_cs": int(((state == 0) & ~pr).sum())}
 
 
 def measure_variants(lbm, inputs, steps=100):
@@ -367,6 +416,9 @@ def main():
     if args.workload == "batch256":
         res = measure_batch(lbm, inputs, args.steps)
         print(json.dumps({"workload": "batch256", "aux": [res]}), flush=True)
+        return
+    if args.workload == "batch256_residual":
+        print(json.dumps(measure_batch_residual(lbm, inputs)), flush=True)
         return
     if args.workload == "spinodal4096":
         p, rho0, mu_w, fluid = spinodal_workload(lbm, inputs, lbm.LBM_F32)

@@ -167,7 +167,7 @@ lbm_status set_schedule(lbm_batch* b, int tile_y, int blocks_per_cu) {
 }
 
 lbm_status one_step(lbm_batch* b) {
-    HIP_TRY(launch_batch_step(b->prec, b->tile_y, b->d_cases, b->d_tiles, b->ntiles, int(b->step & 1), b->grid,
+    HIP_TRY(launch_batch_step(b->prec, b->tile_y, b->A[0].nt_store, b->d_cases, b->d_tiles, b->ntiles, int(b->step & 1), b->grid,
                               b->stream));
     ++b->step;
     for (int i = 0; i < b->n; ++i)
@@ -183,7 +183,7 @@ lbm_status capture_graph(lbm_batch* b) {
         HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
         for (int s = 0; s < BATCH_GRAPH_STEPS && e == hipSuccess; ++s)
-            e = launch_batch_step(b->prec, b->tile_y, b->d_cases, b->d_tiles, b->ntiles, s & 1, b->grid, b->stream);
+            e = launch_batch_step(b->prec, b->tile_y, b->A[0].nt_store, b->d_cases, b->d_tiles, b->ntiles, s & 1, b->grid, b->stream);
         hipError_t e2 = hipStreamEndCapture(b->stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
@@ -319,9 +319,13 @@ lbm_status lbm_batch_init(const lbm_params* cases, int32_t n, const double* cons
     b->residual.assign(n, NAN);
     b->mass.assign(n, NAN);
     b->flags.assign(n, 0);
+    // non-temporal stores when the batch's distributions together exceed the caches
+    long long fbytes_all = 0;
+    for (int i = 0; i < n; ++i) fbytes_all += 2 * 9 * layout_of(cases[i]).plane * (long long)storage_bytes(cases[i].prec);
     for (int i = 0; i < n; ++i) {
         const Layout L = layout_of(cases[i]);
         b->A[i] = lattice_args(cases[i], fl[i], L);
+        b->A[i].nt_store = nt_store_for(fbytes_all);
         CaseDesc& d = b->desc[i];
         d.A = b->A[i];
         d.eos = cases[i].eos;
@@ -491,10 +495,10 @@ lbm_status lbm_batch_tune(lbm_batch* b, int32_t trial_steps, int32_t* tile_y, in
             if (b->ntiles == 0) break;
             // the state is only read: every trial launch maps f[parity] -> f[parity ^ 1]
             for (int w = 0; w < 2; ++w)
-                HIP_TRY(launch_batch_step(b->prec, ty, b->d_cases, b->d_tiles, b->ntiles, parity, b->grid, b->stream));
+                HIP_TRY(launch_batch_step(b->prec, ty, b->A[0].nt_store, b->d_cases, b->d_tiles, b->ntiles, parity, b->grid, b->stream));
             HIP_TRY(hipEventRecord(e0, b->stream));
             for (int s = 0; s < trial_steps; ++s)
-                HIP_TRY(launch_batch_step(b->prec, ty, b->d_cases, b->d_tiles, b->ntiles, parity, b->grid, b->stream));
+                HIP_TRY(launch_batch_step(b->prec, ty, b->A[0].nt_store, b->d_cases, b->d_tiles, b->ntiles, parity, b->grid, b->stream));
             HIP_TRY(hipEventRecord(e1, b->stream));
             HIP_TRY(hipEventSynchronize(e1));
             float ms = 0.0f;

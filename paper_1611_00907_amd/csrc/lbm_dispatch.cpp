@@ -8,7 +8,7 @@ namespace cplbm {
     hipError_t launch_step_##sfx(int, int, const LatticeArgs&, const void*, void*, const void*, double*,       \
                                  hipStream_t);                                                                 \
     hipError_t launch_monitor_##sfx(int, const LatticeArgs&, const void*, void*, double*, double*, hipStream_t); \
-    hipError_t launch_batch_step_##sfx(int, const CaseDesc*, const int2*, int, int, int, hipStream_t);          \
+    hipError_t launch_batch_step_##sfx(int, int, const CaseDesc*, const int2*, int, int, int, hipStream_t);     \
     hipError_t launch_batch_monitor_##sfx(int, int, const CaseDesc*, const int2*, int, int, double*, const int*, \
                                           int, double*, hipStream_t);                                          \
     int batch_blocks_per_cu_##sfx(int);                                                                        \
@@ -47,13 +47,13 @@ hipError_t launch_monitor(int prec, int eos, int compare, const LatticeArgs& A, 
     }
 }
 
-hipError_t launch_batch_step(int prec, int tile_y, const CaseDesc* cases, const int2* tiles, int ntiles, int parity,
-                             int grid, hipStream_t s) {
+hipError_t launch_batch_step(int prec, int tile_y, int nt, const CaseDesc* cases, const int2* tiles, int ntiles,
+                             int parity, int grid, hipStream_t s) {
     switch (prec) {
-    case PREC_F64: return launch_batch_step_f64(tile_y, cases, tiles, ntiles, parity, grid, s);
-    case PREC_F32: return launch_batch_step_f32(tile_y, cases, tiles, ntiles, parity, grid, s);
-    case PREC_F16DEV: return launch_batch_step_f16dev(tile_y, cases, tiles, ntiles, parity, grid, s);
-    case PREC_BF16DEV: return launch_batch_step_bf16dev(tile_y, cases, tiles, ntiles, parity, grid, s);
+    case PREC_F64: return launch_batch_step_f64(tile_y, nt, cases, tiles, ntiles, parity, grid, s);
+    case PREC_F32: return launch_batch_step_f32(tile_y, nt, cases, tiles, ntiles, parity, grid, s);
+    case PREC_F16DEV: return launch_batch_step_f16dev(tile_y, nt, cases, tiles, ntiles, parity, grid, s);
+    case PREC_BF16DEV: return launch_batch_step_bf16dev(tile_y, nt, cases, tiles, ntiles, parity, grid, s);
     default: return hipErrorInvalidValue;
     }
 }

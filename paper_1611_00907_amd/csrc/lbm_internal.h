@@ -57,16 +57,20 @@ struct EosConst {
 // Everything a kernel needs about one lattice; passed by value.
 struct LatticeArgs {
     int nx, ny;
-    int pitch;            // elements per row (>= nx)
+    int pitch;            // elements per row of the density-shaped arrays (>= nx)
     int bottom, top;      // Bc of rows 0 and ny-1
     int tile_y;           // shape code: tile height (64-wide tiles), a wide-tile code, or -k (marching)
-    long long plane;      // elements per direction plane = ny * pitch
+    long long plane;      // distributions: elements from direction i to direction i + 1 of one node
+                          // (pitch in the row-interleaved layout, ny * pitch in the plane layout)
     double tau, inv_tau, kappa;
     double rho_ref;       // deviation base of the half/bf16 storage
     double sp_lo, sp_hi;  // spinodal band: the 16-bit storage types evaluate psi' in FP64
                           // for sp_lo < rho < sp_hi (empty band: both 0)
     EosConst eos;
     int scheme;           // force (bits 0-3) | collision (bits 4-7); 0 = Eq 12 with BGK
+    int fpitch;           // distributions: elements from row y to row y + 1 of one direction
+                          // (9 * pitch row-interleaved, pitch in the plane layout)
+    int nt_store;         // 1: the step stores f*(t) non-temporally (working sets beyond the caches)
     int pad_;
     double tau_minus;     // TRT: relaxation time of the odd part
     double s_e, s_eps, s_q;  // MRT rates of e, epsilon and the heat-flux moments
@@ -102,9 +106,10 @@ hipError_t launch_monitor(int prec, int eos, int compare, const LatticeArgs& A, 
                           void* rho_mon, double* partials, double* mon, hipStream_t s);
 
 // All cases of a batch advance one step: tiles is the (case, tile) list of the active
-// cases, grid the number of persistent workgroups, parity selects f[parity] -> f[parity^1].
-hipError_t launch_batch_step(int prec, int tile_y, const CaseDesc* cases, const int2* tiles, int ntiles, int parity,
-                             int grid, hipStream_t s);
+// cases, grid the number of persistent workgroups, parity selects f[parity] -> f[parity^1],
+// nt: non-temporal stores of f*(t) (a batch larger than the caches).
+hipError_t launch_batch_step(int prec, int tile_y, int nt, const CaseDesc* cases, const int2* tiles, int ntiles,
+                             int parity, int grid, hipStream_t s);
 // Batched monitors over the same tile list: partials [3][ntiles]; compare == 1 reduces each
 // case's tile range [case_tile_begin[c], case_tile_begin[c+1]) into case_mon[3 c .. 3 c + 2].
 hipError_t launch_batch_monitor(int prec, int compare, int tile_y, const CaseDesc* cases, const int2* tiles,
@@ -131,7 +136,7 @@ size_t compute_bytes(int prec);
 
 // Whether the column-marching shapes may run on this lattice and storage type.
 inline bool march_allowed(const LatticeArgs& A, int prec) {
-    return 9 * A.plane * (long long)storage_bytes(prec) <= MARCH_MAX_BYTES;
+    return 9LL * A.ny * A.pitch * (long long)storage_bytes(prec) <= MARCH_MAX_BYTES;
 }
 
 }  // namespace cplbm

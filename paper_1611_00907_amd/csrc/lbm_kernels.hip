@@ -1,7 +1,9 @@
 // HIP kernels of the chemical-potential lattice Boltzmann step for CDNA4 (gfx950).
 //
-// Storage: nine direction planes f[i][y][x] (SoA, row pitch a multiple of 64
-// elements) holding the post-collision distributions f*(t-1).  A step pulls
+// Storage: the post-collision distributions f*(t-1) as nine rows of one direction
+// each per lattice row, f[y][i][x] (row pitch a multiple of 64 elements), or as
+// nine direction planes f[i][y][x] where a buffer is too large for 32-bit byte
+// offsets; the kernels see either through two strides (direction and row).  A step pulls
 // f_i(x, t) = f*_i(x - e_i, t-1), or the reflected f*_opp(i)(x, t-1) when x - e_i
 // lies in a solid row (halfway bounce-back, Sec. IV), so reads are the shifted
 // ones and every write is aligned and coalesced.  Two such buffers alternate.
@@ -43,20 +45,41 @@ __device__ __forceinline__ T* at(T* p, unsigned o) {
     return reinterpret_cast<T*>(reinterpret_cast<char*>(p) + (o * unsigned(sizeof(T))));
 }
 
+// A pointer read from memory (a batch's case descriptors) is generic to the
+// compiler, which then emits flat accesses (counted against both the vector-memory
+// and the LDS counters, so every LDS wait also waits for memory).  Rebuilding it
+// from its bits as a global-address-space pointer lets the compiler use global
+// accesses again (a plain cast pair folds away).
+template <typename T>
+__device__ __forceinline__ T* in_global(T* p) {
+    typedef __attribute__((address_space(1))) T* GP;
+    return (T*)(GP)__builtin_bit_cast(unsigned long long, p);
+}
+
 template <typename ST>
 struct Codec;
 
+// stn: the step's stores of f*(t), marked non-temporal, for lattices larger than the
+// caches (read back only in the next step, after the whole lattice has streamed
+// through, they need not displace the lines that neighbouring tiles are about to
+// re-read); a lattice that stays in the Infinity Cache keeps plain stores.
 template <>
 struct Codec<double> {
     using CT = double;
     static __device__ __forceinline__ double ld(const double* p, unsigned o, double) { return *at(p, o); }
     static __device__ __forceinline__ void st(double* p, unsigned o, double v, double) { *at(p, o) = v; }
+    static __device__ __forceinline__ void stn(double* p, unsigned o, double v, double) {
+        __builtin_nontemporal_store(v, at(p, o));
+    }
 };
 template <>
 struct Codec<float> {
     using CT = float;
     static __device__ __forceinline__ float ld(const float* p, unsigned o, float) { return *at(p, o); }
     static __device__ __forceinline__ void st(float* p, unsigned o, float v, float) { *at(p, o) = v; }
+    static __device__ __forceinline__ void stn(float* p, unsigned o, float v, float) {
+        __builtin_nontemporal_store(v, at(p, o));
+    }
 };
 // Deviation storage: h = f - w_i rho_ref, rounded to nearest even on store.
 template <>
@@ -68,6 +91,10 @@ struct Codec<__half> {
     static __device__ __forceinline__ void st(__half* p, unsigned o, float v, float base) {
         *at(p, o) = __float2half_rn(v - base);
     }
+    static __device__ __forceinline__ void stn(__half* p, unsigned o, float v, float base) {
+        __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v - base)),
+                                    reinterpret_cast<unsigned short*>(at(p, o)));
+    }
 };
 template <>
 struct Codec<__hip_bfloat16> {
@@ -77,6 +104,10 @@ struct Codec<__hip_bfloat16> {
     }
     static __device__ __forceinline__ void st(__hip_bfloat16* p, unsigned o, float v, float base) {
         *at(p, o) = __float2bfloat16(v - base);
+    }
+    static __device__ __forceinline__ void stn(__hip_bfloat16* p, unsigned o, float v, float base) {
+        __builtin_nontemporal_store(__bfloat16_as_ushort(__float2bfloat16(v - base)),
+                                    reinterpret_cast<unsigned short*>(at(p, o)));
     }
 };
 
@@ -134,7 +165,7 @@ __device__ __forceinline__ void pull9(const LatticeArgs& A, const Planes<ST>& F,
         sm = ym == 0;
         sp = yp == A.ny - 1;
     }
-    const unsigned pitch = unsigned(A.pitch), ux = unsigned(gx), uxm = unsigned(xm), uxp = unsigned(xp);
+    const unsigned pitch = unsigned(A.fpitch), ux = unsigned(gx), uxm = unsigned(xm), uxp = unsigned(xp);
     const unsigned rc = unsigned(gy) * pitch, rm = unsigned(ym) * pitch, rp = unsigned(yp) * pitch;
     // Links that would come from a solid row return reversed from the node itself
     // (halfway bounce-back).  The source plane and offset are selected, not
@@ -443,9 +474,10 @@ __device__ __forceinline__ void tile_pull(const LatticeArgs& A, const Planes<ST>
 // (MODE_FIELDS), from the own nodes' pulled distributions f: densities of the
 // tile and its ring into LDS, chemical potential, force, collision and store.
 // HOIST: the ring's pulls go out right after the own pulls, before the first wait
-// (one memory round trip instead of two, at the cost of registers).
+// (one memory round trip instead of two, at the cost of registers).  NTS: the
+// stores of f*(t) are non-temporal (lattices larger than the caches).
 template <typename ST, int EOS, int MODE, int TY, int TX, int RPT, bool HOIST = false, int FORCE = FORCE_CP,
-          int COLL = COLLIDE_BGK>
+          int COLL = COLLIDE_BGK, bool NTS = false>
 __device__ __forceinline__ void tile_rest(const LatticeArgs& A, const Planes<ST>& F, ST* __restrict__ fout,
                                           const typename Codec<ST>::CT* __restrict__ mu_w,
                                           double* __restrict__ out, int x0, int y0,
@@ -668,11 +700,14 @@ __device__ __forceinline__ void tile_rest(const LatticeArgs& A, const Planes<ST>
             force(Fx, Fy);
             collide_with_force<CT, COLL>(A, f[k], rho, jx[k], jy[k], Fx, Fy, fs);
         }
-        const unsigned o = unsigned(gy) * unsigned(A.pitch) + unsigned(gx_raw);
+        const unsigned o = unsigned(gy) * unsigned(A.fpitch) + unsigned(gx_raw);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const CT base = i == 0 ? b0 : (i < 5 ? b1 : b2);
-            C::st(fout + (long long)i * A.plane, o, fs[i], base);
+            if constexpr (NTS)
+                C::stn(fout + (long long)i * A.plane, o, fs[i], base);
+            else
+                C::st(fout + (long long)i * A.plane, o, fs[i], base);
         }
     }
 }
@@ -680,7 +715,7 @@ __device__ __forceinline__ void tile_rest(const LatticeArgs& A, const Planes<ST>
 // One TX x TY tile of the step or of the field output, run by a workgroup of
 // TX * TY / RPT threads, RPT nodes of one column per thread.
 template <typename ST, int EOS, int MODE, int TY, int TX = TILE_X, int RPT = ROWS_PER_THREAD, bool HOIST = false,
-          int FORCE = FORCE_CP, int COLL = COLLIDE_BGK>
+          int FORCE = FORCE_CP, int COLL = COLLIDE_BGK, bool NTS = false>
 __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __restrict__ fin,
                                           ST* __restrict__ fout,
                                           const typename Codec<ST>::CT* __restrict__ mu_w,
@@ -692,12 +727,12 @@ __device__ __forceinline__ void step_tile(const LatticeArgs& A, const ST* __rest
     for (int i = 0; i < 9; ++i) F.p[i] = fin + (long long)i * A.plane;
     CT f[RPT][9];
     tile_pull<ST, TY, TX, RPT>(A, F, x0, y0, f);
-    tile_rest<ST, EOS, MODE, TY, TX, RPT, HOIST, FORCE, COLL>(A, F, fout, mu_w, out, x0, y0, f, L);
+    tile_rest<ST, EOS, MODE, TY, TX, RPT, HOIST, FORCE, COLL, NTS>(A, F, fout, mu_w, out, x0, y0, f, L);
 }
 
 // One lattice: one workgroup per tile.
 template <typename ST, int EOS, int MODE, int TY, int TX = TILE_X, int RPT = ROWS_PER_THREAD, bool HOIST = false,
-          int FORCE = FORCE_CP, int COLL = COLLIDE_BGK>
+          int FORCE = FORCE_CP, int COLL = COLLIDE_BGK, bool NTS = false>
 __global__ __launch_bounds__(TX * TY / RPT) void step_kernel(LatticeArgs A, const ST* __restrict__ fin,
                                                             ST* __restrict__ fout,
                                                             const typename Codec<ST>::CT* __restrict__ mu_w,
@@ -705,13 +740,13 @@ __global__ __launch_bounds__(TX * TY / RPT) void step_kernel(LatticeArgs A, cons
     __shared__ TileLds<typename Codec<ST>::CT, TY, TX, FORCE == FORCE_PTENSOR> L;
     const int t = tile_of_block(blockIdx.x, gridDim.x);
     const int tiles_x = (A.nx + TX - 1) / TX;
-    step_tile<ST, EOS, MODE, TY, TX, RPT, HOIST, FORCE, COLL>(A, fin, fout, mu_w, out, (t % tiles_x) * TX,
+    step_tile<ST, EOS, MODE, TY, TX, RPT, HOIST, FORCE, COLL, NTS>(A, fin, fout, mu_w, out, (t % tiles_x) * TX,
                                                               (t / tiles_x) * TY, L);
 }
 
 // Many lattices in one persistent launch: each workgroup walks a contiguous range
 // of the (case, tile) list; the ranges of the workgroups on one XCD are adjacent.
-template <typename ST, int TY, int TX = TILE_X>
+template <typename ST, int TY, int TX = TILE_X, bool NTS = false>
 __global__ __launch_bounds__(TX * TY / ROWS_PER_THREAD) void batch_step_kernel(
     const CaseDesc* __restrict__ cases, const int2* __restrict__ tiles, int ntiles, int parity) {
     using CT = typename Codec<ST>::CT;
@@ -724,14 +759,27 @@ __global__ __launch_bounds__(TX * TY / ROWS_PER_THREAD) void batch_step_kernel(
         const CaseDesc& C = cases[w.x];
         const int tiles_x = (C.A.nx + TX - 1) / TX;
         const int x0 = (w.y % tiles_x) * TX, y0 = (w.y / tiles_x) * TY;
-        const ST* fin = static_cast<const ST*>(C.f[parity]);
-        ST* fout = static_cast<ST*>(C.f[parity ^ 1]);
-        const CT* mw = static_cast<const CT*>(C.mu_w);
+        const ST* fin = in_global(static_cast<const ST*>(C.f[parity]));
+        ST* fout = in_global(static_cast<ST*>(C.f[parity ^ 1]));
+        const CT* mw = in_global(static_cast<const CT*>(C.mu_w));
+        constexpr int R = ROWS_PER_THREAD;
         switch (C.eos) {
-        case EOS_VDW: step_tile<ST, EOS_VDW, MODE_STEP, TY, TX>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
-        case EOS_CS: step_tile<ST, EOS_CS, MODE_STEP, TY, TX>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
-        case EOS_PR: step_tile<ST, EOS_PR, MODE_STEP, TY, TX>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
-        default: step_tile<ST, EOS_RK, MODE_STEP, TY, TX>(C.A, fin, fout, mw, nullptr, x0, y0, L); break;
+        case EOS_VDW:
+            step_tile<ST, EOS_VDW, MODE_STEP, TY, TX, R, false, FORCE_CP, COLLIDE_BGK, NTS>(C.A, fin, fout, mw, nullptr,
+                                                                                         x0, y0, L);
+            break;
+        case EOS_CS:
+            step_tile<ST, EOS_CS, MODE_STEP, TY, TX, R, false, FORCE_CP, COLLIDE_BGK, NTS>(C.A, fin, fout, mw, nullptr,
+                                                                                        x0, y0, L);
+            break;
+        case EOS_PR:
+            step_tile<ST, EOS_PR, MODE_STEP, TY, TX, R, false, FORCE_CP, COLLIDE_BGK, NTS>(C.A, fin, fout, mw, nullptr,
+                                                                                        x0, y0, L);
+            break;
+        default:
+            step_tile<ST, EOS_RK, MODE_STEP, TY, TX, R, false, FORCE_CP, COLLIDE_BGK, NTS>(C.A, fin, fout, mw, nullptr,
+                                                                                        x0, y0, L);
+            break;
         }
         __syncthreads();  // the next tile reuses the LDS
     }
@@ -935,6 +983,8 @@ struct March {
         CT fs[9];
         collide<CT>(g, rrow(c)[l], jx, jy, gmx, gmy, grx, gry, tau, inv_tau, fs);
         const int oc = c * RB;
+        // plain stores: non-temporal ones slowed the marching step down (FP16 at
+        // 4096^2: 173 -> 200 us), unlike the tiles
 #pragma unroll
         for (int i = 0; i < 9; ++i) IO::st(rout, v, i * PB + oc, fs[i], base(i));
     }
@@ -1067,8 +1117,8 @@ __global__ __launch_bounds__(MARCH_NT) __attribute__((amdgpu_waves_per_eu(MARCH_
     M_t M{A};
     M.rs = rs;
     M.ms = ms;
-    M.mu_w = mu_w;
-    const int bytes = int(9 * A.plane * (long long)sizeof(ST));
+    M.mu_w = in_global(mu_w);
+    const int bytes = int(9LL * A.ny * A.pitch * (long long)sizeof(ST));
     M.rin = buffer_of(fin, bytes);
     M.rout = buffer_of(fout, bytes);
     M.l = threadIdx.x;
@@ -1089,7 +1139,7 @@ __global__ __launch_bounds__(MARCH_NT) __attribute__((amdgpu_waves_per_eu(MARCH_
     M.vp = M.live ? wrap_col(xr + 1, A.nx) * int(sizeof(ST)) : M_t::NOWHERE;
     M.vs = M.owned ? M.vc : M_t::NOWHERE;
     M.PB = int(A.plane * (long long)sizeof(ST));
-    M.RB = A.pitch * int(sizeof(ST));
+    M.RB = A.fpitch * int(sizeof(ST));
     M.b0 = CT(A.rho_ref) * Wt<CT>::w0;
     M.b1 = CT(A.rho_ref) * Wt<CT>::w1;
     M.b2 = CT(A.rho_ref) * Wt<CT>::w2;
@@ -1216,10 +1266,10 @@ __global__ __launch_bounds__(MON_THREADS) void batch_monitor_kernel(const CaseDe
     const CaseDesc& C = cases[w.x];
     const LatticeArgs& A = C.A;
     Planes<ST> F;
-    const ST* fin = static_cast<const ST*>(C.f[parity]);
+    const ST* fin = in_global(static_cast<const ST*>(C.f[parity]));
 #pragma unroll
     for (int i = 0; i < 9; ++i) F.p[i] = fin + (long long)i * A.plane;
-    CT* rho_mon = static_cast<CT*>(C.rho_mon);
+    CT* rho_mon = in_global(static_cast<CT*>(C.rho_mon));
     const int tiles_x = (A.nx + TX - 1) / TX;
     const int x0 = (w.y % tiles_x) * TX, y0 = (w.y / tiles_x) * TY;
     double mass = 0.0, res = 0.0;
@@ -1314,7 +1364,7 @@ __global__ void init_kernel(LatticeArgs A, const double* __restrict__ rho0, cons
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
     const int y = int(c / A.nx), x = int(c % A.nx);
-    const int o = y * A.pitch + x;
+    const unsigned o = unsigned(y) * unsigned(A.fpitch) + unsigned(x);
     if (solid_row(A, y)) {
         for (int j = 0; j < 9; ++j) Codec<ST>::st(fstore + (long long)j * A.plane, o, CT(0), CT(0));
         return;
@@ -1360,13 +1410,13 @@ __global__ void get_state_kernel(LatticeArgs A, const ST* __restrict__ fstore, d
 }
 
 template <typename ST, int EOS, int MODE, int TY, int TX, int RPT, bool HOIST = false, int FORCE = FORCE_CP,
-          int COLL = COLLIDE_BGK>
+          int COLL = COLLIDE_BGK, bool NTS = false>
 hipError_t step_launch(const LatticeArgs& A, const void* fin, void* fout, const void* mu_w, double* out,
                        hipStream_t s) {
     using CT = typename Codec<ST>::CT;
     const int tiles = ((A.nx + TX - 1) / TX) * ((A.ny + TY - 1) / TY);
     (void)hipGetLastError();  // drop any error left by earlier runtime calls
-    hipLaunchKernelGGL((step_kernel<ST, EOS, MODE, TY, TX, RPT, HOIST, FORCE, COLL>), dim3(tiles),
+    hipLaunchKernelGGL((step_kernel<ST, EOS, MODE, TY, TX, RPT, HOIST, FORCE, COLL, NTS>), dim3(tiles),
                        dim3(TX * TY / RPT), 0, s, A, (const ST*)fin, (ST*)fout, (const CT*)mu_w, out);
     return hipGetLastError();
 }
@@ -1399,21 +1449,32 @@ hipError_t step_scheme(const LatticeArgs& A, const void* fin, void* fout, const 
     }
 }
 
+template <typename ST, int EOS, int MODE, bool NTS>
+hipError_t step_ty_nt(int tile_y, const LatticeArgs& A, const void* fin, void* fout, const void* mu_w, double* out,
+                      hipStream_t s) {
+    constexpr int F = FORCE_CP, B = COLLIDE_BGK;
+    switch (tile_y) {
+    case 8: return step_launch<ST, EOS, MODE, 8, 64, 4, false, F, B, NTS>(A, fin, fout, mu_w, out, s);
+    case 16: return step_launch<ST, EOS, MODE, 16, 64, 4, false, F, B, NTS>(A, fin, fout, mu_w, out, s);
+    case 32: return step_launch<ST, EOS, MODE, 32, 64, 4, false, F, B, NTS>(A, fin, fout, mu_w, out, s);
+    case 12816: return step_launch<ST, EOS, MODE, 16, 128, 4, false, F, B, NTS>(A, fin, fout, mu_w, out, s);
+    case 12832: return step_launch<ST, EOS, MODE, 32, 128, 8, false, F, B, NTS>(A, fin, fout, mu_w, out, s);
+    case 25608: return step_launch<ST, EOS, MODE, 8, 256, 4, false, F, B, NTS>(A, fin, fout, mu_w, out, s);
+    case 25616: return step_launch<ST, EOS, MODE, 16, 256, 8, false, F, B, NTS>(A, fin, fout, mu_w, out, s);
+    case HOIST_BASE + 16: return step_launch<ST, EOS, MODE, 16, 64, 4, true, F, B, NTS>(A, fin, fout, mu_w, out, s);
+    case HOIST_BASE + 32: return step_launch<ST, EOS, MODE, 32, 64, 4, true, F, B, NTS>(A, fin, fout, mu_w, out, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Field output stores no distributions: one form.
 template <typename ST, int EOS, int MODE>
 hipError_t step_ty(int tile_y, const LatticeArgs& A, const void* fin, void* fout, const void* mu_w, double* out,
                    hipStream_t s) {
-    switch (tile_y) {
-    case 8: return step_launch<ST, EOS, MODE, 8, 64, 4>(A, fin, fout, mu_w, out, s);
-    case 16: return step_launch<ST, EOS, MODE, 16, 64, 4>(A, fin, fout, mu_w, out, s);
-    case 32: return step_launch<ST, EOS, MODE, 32, 64, 4>(A, fin, fout, mu_w, out, s);
-    case 12816: return step_launch<ST, EOS, MODE, 16, 128, 4>(A, fin, fout, mu_w, out, s);
-    case 12832: return step_launch<ST, EOS, MODE, 32, 128, 8>(A, fin, fout, mu_w, out, s);
-    case 25608: return step_launch<ST, EOS, MODE, 8, 256, 4>(A, fin, fout, mu_w, out, s);
-    case 25616: return step_launch<ST, EOS, MODE, 16, 256, 8>(A, fin, fout, mu_w, out, s);
-    case HOIST_BASE + 16: return step_launch<ST, EOS, MODE, 16, 64, 4, true>(A, fin, fout, mu_w, out, s);
-    case HOIST_BASE + 32: return step_launch<ST, EOS, MODE, 32, 64, 4, true>(A, fin, fout, mu_w, out, s);
-    default: return hipErrorInvalidValue;
+    if constexpr (MODE == MODE_STEP) {
+        if (A.nt_store) return step_ty_nt<ST, EOS, MODE, true>(tile_y, A, fin, fout, mu_w, out, s);
     }
+    return step_ty_nt<ST, EOS, MODE, false>(tile_y, A, fin, fout, mu_w, out, s);
 }
 
 // Column-marching launch with k resident workgroups per CU: the rows are split
@@ -1421,7 +1482,7 @@ hipError_t step_ty(int tile_y, const LatticeArgs& A, const void* fin, void* fout
 template <typename ST, int EOS>
 hipError_t march_launch(int k, const LatticeArgs& A, const void* fin, void* fout, const void* mu_w, hipStream_t s) {
     using CT = typename Codec<ST>::CT;
-    if (k < 1 || k > MARCH_K_MAX || 9 * A.plane * (long long)sizeof(ST) > MARCH_MAX_BYTES)
+    if (k < 1 || k > MARCH_K_MAX || 9LL * A.ny * A.pitch * (long long)sizeof(ST) > MARCH_MAX_BYTES)
         return hipErrorInvalidValue;
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
@@ -1480,22 +1541,27 @@ hipError_t monitor_prec(int compare, const LatticeArgs& A, const void* fin, void
 }
 
 template <typename ST, int TY, int TX>
-void batch_step_one(int grid, const CaseDesc* cases, const int2* tiles, int ntiles, int parity, hipStream_t s) {
-    hipLaunchKernelGGL((batch_step_kernel<ST, TY, TX>), dim3(grid), dim3(TX * TY / ROWS_PER_THREAD), 0, s, cases,
-                       tiles, ntiles, parity);
+void batch_step_one(int grid, bool nt, const CaseDesc* cases, const int2* tiles, int ntiles, int parity,
+                    hipStream_t s) {
+    if (nt)
+        hipLaunchKernelGGL((batch_step_kernel<ST, TY, TX, true>), dim3(grid), dim3(TX * TY / ROWS_PER_THREAD), 0, s,
+                           cases, tiles, ntiles, parity);
+    else
+        hipLaunchKernelGGL((batch_step_kernel<ST, TY, TX, false>), dim3(grid), dim3(TX * TY / ROWS_PER_THREAD), 0, s,
+                           cases, tiles, ntiles, parity);
 }
 
 // code: a 64-wide tile height (8, 16, 32) or a wide shape code (12816, 25608)
 template <typename ST>
-hipError_t batch_step_prec(int code, const CaseDesc* cases, const int2* tiles, int ntiles, int parity, int grid,
-                           hipStream_t s) {
+hipError_t batch_step_prec(int code, int nt, const CaseDesc* cases, const int2* tiles, int ntiles, int parity,
+                           int grid, hipStream_t s) {
     (void)hipGetLastError();
     switch (code) {
-    case 8: batch_step_one<ST, 8, 64>(grid, cases, tiles, ntiles, parity, s); break;
-    case 16: batch_step_one<ST, 16, 64>(grid, cases, tiles, ntiles, parity, s); break;
-    case 32: batch_step_one<ST, 32, 64>(grid, cases, tiles, ntiles, parity, s); break;
-    case 12816: batch_step_one<ST, 16, 128>(grid, cases, tiles, ntiles, parity, s); break;
-    case 25608: batch_step_one<ST, 8, 256>(grid, cases, tiles, ntiles, parity, s); break;
+    case 8: batch_step_one<ST, 8, 64>(grid, nt, cases, tiles, ntiles, parity, s); break;
+    case 16: batch_step_one<ST, 16, 64>(grid, nt, cases, tiles, ntiles, parity, s); break;
+    case 32: batch_step_one<ST, 32, 64>(grid, nt, cases, tiles, ntiles, parity, s); break;
+    case 12816: batch_step_one<ST, 16, 128>(grid, nt, cases, tiles, ntiles, parity, s); break;
+    case 25608: batch_step_one<ST, 8, 256>(grid, nt, cases, tiles, ntiles, parity, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1588,10 +1654,10 @@ hipError_t CPLBM_FN(launch_monitor)(int compare, const LatticeArgs& A, const voi
     return monitor_prec<CPLBM_ST>(compare, A, fin, rho_mon, partials, mon, s);
 }
 
-hipError_t CPLBM_FN(launch_batch_step)(int tile_y, const CaseDesc* cases, const int2* tiles, int ntiles,
+hipError_t CPLBM_FN(launch_batch_step)(int tile_y, int nt, const CaseDesc* cases, const int2* tiles, int ntiles,
                                        int parity, int grid, hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
-    return batch_step_prec<CPLBM_ST>(tile_y, cases, tiles, ntiles, parity, grid, s);
+    return batch_step_prec<CPLBM_ST>(tile_y, nt, cases, tiles, ntiles, parity, grid, s);
 }
 
 hipError_t CPLBM_FN(launch_batch_monitor)(int compare, int tile_y, const CaseDesc* cases, const int2* tiles,
