@@ -13,6 +13,8 @@
 // with k = (tap, ci): A rows are pixels, B columns output channels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sur_internal.h"
 
 namespace cplbm {
@@ -497,6 +499,172 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_c1_kernel(WgradArgs a) {
     }
 }
 
+// Weight gradient through LDS, for 32, 64, 96 or 128 output channels (WCO = cout / 32)
+// and a block of 32 input channels: 2 WCO waves, each owning 32 output by 16 input
+// channels (few enough registers for two waves per SIMD, so that one wave's staging
+// overlaps another's MFMAs).  The tap offset
+// (du, dv) is split between the operands: dW[du, dv] = sum_q dZ[q - (du, 0)] X[q + (0, dv)]
+// over the pixels q of the image (dZ and X zero outside it), so that for each pixel
+// tile the workgroup stages dZ once, with one halo row above and below, and X in three
+// copies shifted by dv = -1, 0, +1, all transposed to channel-major rows of 32 pixels
+// (an MFMA operand lane reads 8 consecutive pixels of one channel with one 16-byte LDS
+// read).  Per row of the tile a wave reads 3 x 2 A blocks and 3 B blocks and issues
+// 18 MFMAs, one per (tap, 16 x 16 block).  A workgroup walks a run of tiles of
+// WG_TH x 32 pixels and adds its sums to dW atomically once; the waves of the first
+// input-channel block also sum dZ for the bias gradient.  Needs W % 32 == 0,
+// H % WG_TH == 0, channel counts, strides and offsets that are multiples of 8.
+constexpr int WG_TH = 4;
+constexpr int WG_DZ_CH = (WG_TH + 2) * 32 + 8;  // LDS elements per channel: dZ rows y0-1 .. y0+TH, padded
+constexpr int WG_X_CH = WG_TH * 32 + 8;         // LDS elements per channel of one shifted X copy
+
+// 8 x 8 transpose of BF16 values: v[j] holds channels 0..7 of pixel j; o[c] gets pixels
+// 0..7 of channel c.
+__device__ __forceinline__ void transpose8(const uint4* v, uint4* o) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const uint32_t sel = (c & 1) ? 0x07060302u : 0x05040100u;
+        uint32_t d[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint4 lo = v[2 * k], hi = v[2 * k + 1];
+            const uint32_t a = (c >> 1) == 0 ? lo.x : (c >> 1) == 1 ? lo.y : (c >> 1) == 2 ? lo.z : lo.w;
+            const uint32_t b = (c >> 1) == 0 ? hi.x : (c >> 1) == 1 ? hi.y : (c >> 1) == 2 ? hi.z : hi.w;
+            d[k] = __builtin_amdgcn_perm(b, a, sel);  // low half: pixel 2k, high half: pixel 2k + 1
+        }
+        o[c] = make_uint4(d[0], d[1], d[2], d[3]);
+    }
+}
+
+template <int WCO>
+__global__ __launch_bounds__(128 * WCO) void conv3x3_wgrad_lds_kernel(WgradArgs a, int ci_blocks, int tiles_per_run) {
+    constexpr int NT = 128 * WCO, CO_B = 32 * WCO, CG = CO_B / 8;
+    __shared__ __attribute__((aligned(16))) uint16_t dzs[CO_B * WG_DZ_CH];
+    __shared__ __attribute__((aligned(16))) uint16_t xs[3 * 32 * WG_X_CH];
+    const int cib = blockIdx.x % ci_blocks, run = blockIdx.x / ci_blocks;
+    const int ci0 = 32 * cib;
+    const int tiles_x = a.W / 32, tiles_img = tiles_x * (a.H / WG_TH), tiles = a.N * tiles_img;
+    const int t_begin = run * tiles_per_run;
+    if (t_begin >= tiles) return;  // the whole workgroup
+    const int t_end = min(t_begin + tiles_per_run, tiles);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+    const int wco = wave >> 1, wci = wave & 1;  // 32 output channels 32 wco.., 16 input channels 16 wci..
+    const bool bias = cib == 0;  // workgroup-uniform
+    f32x4 acc[3][3][2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int m = 0; m < 2; ++m) acc[i][j][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum[8];  // channels 8 (threadIdx.x % CG) .. + 7: the same for every dZ unit of this thread
+#pragma unroll
+    for (int c = 0; c < 8; ++c) bsum[c] = 0.f;
+
+    for (int t = t_begin; t < t_end; ++t) {
+        const int img = t / tiles_img, tt = t - img * tiles_img;
+        const int y0 = (tt / tiles_x) * WG_TH, x0 = (tt % tiles_x) * 32;
+        // dZ rows y0 - 1 .. y0 + TH, channel-major; units of 8 channels x 8 pixels
+        for (int u = threadIdx.x; u < CG * (WG_TH + 2) * 4; u += NT) {
+            const int cg = u % CG, rb = u / CG, row = rb >> 2, b = rb & 3;
+            const int y = y0 - 1 + row;
+            const bool rin = y >= 0 && y < a.H;
+            uint4 v[8], o[8];
+            const long long p0 = ((long long)img * a.H + y) * a.W + x0 + 8 * b;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                v[j] = rin ? *reinterpret_cast<const uint4*>(a.dz.p + (p0 + j) * a.dz.cs + a.dz.co + 8 * cg)
+                           : make_uint4(0, 0, 0, 0);
+            transpose8(v, o);
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                *reinterpret_cast<uint4*>(dzs + (8 * cg + c) * WG_DZ_CH + row * 32 + 8 * b) = o[c];
+            if (bias && row >= 1 && row <= WG_TH) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const uint32_t w[4] = {o[c].x, o[c].y, o[c].z, o[c].w};
+                    float sum = 0.f;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) sum += bf2f(uint16_t(w[k])) + bf2f(uint16_t(w[k] >> 16));
+                    bsum[c] += sum;
+                }
+            }
+        }
+        // X rows y0 .. y0 + TH - 1 in three copies: copy s holds X[y][x0 + i + s - 1], i = 0..31
+        for (int u = threadIdx.x; u < 4 * WG_TH * 4; u += NT) {
+            const int cg = u & 3, rb = u >> 2, row = rb >> 2, b = rb & 3;
+            const int y = y0 + row, ci = ci0 + 8 * cg;
+            const bool cin_ok = ci < a.cin;
+            uint4 w[10], o[8];
+            const long long prow = ((long long)img * a.H + y) * a.W;
+#pragma unroll
+            for (int j = 0; j < 10; ++j) {
+                const int x = x0 + 8 * b - 1 + j;
+                w[j] = (cin_ok && x >= 0 && x < a.W)
+                           ? *reinterpret_cast<const uint4*>(a.x.p + (prow + x) * a.x.cs + a.x.co + ci)
+                           : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int sft = 0; sft < 3; ++sft) {
+                transpose8(w + sft, o);
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    *reinterpret_cast<uint4*>(xs + (sft * 32 + 8 * cg + c) * WG_X_CH + row * 32 + 8 * b) = o[c];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < WG_TH; ++k) {
+            bf16x8 A[3][2], B[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)  // du = i - 1: dZ row k - du of the tile, staged row k - du + 1
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+                    A[i][m] = as_bf16x8(*reinterpret_cast<const uint4*>(
+                        dzs + (32 * wco + 16 * m + r) * WG_DZ_CH + (k + 2 - i) * 32 + 8 * g));
+#pragma unroll
+            for (int j = 0; j < 3; ++j)  // dv = j - 1: copy j
+                B[j] = as_bf16x8(
+                    *reinterpret_cast<const uint4*>(xs + (j * 32 + 16 * wci + r) * WG_X_CH + k * 32 + 8 * g));
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int m = 0; m < 2; ++m)
+                        acc[i][j][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i][m], B[j], acc[i][j][m], 0, 0, 0);
+        }
+        __syncthreads();  // the next tile overwrites the LDS
+    }
+    // lane holds D[4 g + q][r] of block m: output channel 32 wco + 16 m + 4 g + q, input
+    // channel ci0 + 16 wci + r, tap (i, j)
+    const int ci = ci0 + 16 * wci + r;
+    if (ci < a.cin) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int co = 32 * wco + 16 * m + 4 * g + q;
+                        atomicAdd(&a.dw[((size_t)(3 * i + j) * a.cout_p + co) * a.cin_p + ci], acc[i][j][m][q]);
+                    }
+    }
+    if (bias) {  // the CO_B / 8 groups of 16 threads meet in LDS (free after the last barrier)
+        float* red = reinterpret_cast<float*>(dzs);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) red[threadIdx.x * 8 + c] = bsum[c];
+        __syncthreads();
+        if (threadIdx.x < CO_B) {
+            const int co = threadIdx.x, cg = co >> 3;
+            float v = 0.f;
+            for (int k = 0; k < NT / CG; ++k) v += red[(cg + k * CG) * 8 + (co & 7)];
+            if (co < a.cout) atomicAdd(&a.db[co], v);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- elementwise
 __global__ void avgpool2_kernel(TView in, TView out, int N, int H, int W, int C) {
     const int Ho = H / 2, Wo = W / 2;
@@ -866,6 +1034,34 @@ hipError_t conv3x3_wgrad(const WgradArgs& a, hipStream_t s) {
         (void)hipGetLastError();
         hipLaunchKernelGGL(conv3x3_wgrad_c1_kernel, dim3(unsigned((npx + b.chunk_px - 1) / b.chunk_px)), dim3(256),
                            0, s, b);
+        return hipGetLastError();
+    }
+    // the LDS kernel: 32 to 128 output channels in steps of 32, rows of whole 32-pixel
+    // segments, 8-channel-aligned views
+    const bool lds_ok = a.cout % 32 == 0 && a.cout <= 128 && a.cout_p == a.cout && a.W % 32 == 0 &&
+                        a.H % WG_TH == 0 && a.cin % 8 == 0 && a.dz.cs % 8 == 0 && a.dz.co % 8 == 0 &&
+                        a.x.cs % 8 == 0 && a.x.co % 8 == 0;
+    if (lds_ok) {
+        const int ci_blocks = (a.cin + 31) / 32;
+        const long long tiles = (long long)a.N * (a.H / WG_TH) * (a.W / 32);
+        // about 512 workgroups over all input-channel blocks, but runs of at least 8 tiles:
+        // each run ends in 9 x cout x 32 atomic additions, which would outweigh the MFMA
+        // work of shorter runs on the small lower levels (measured: 64^2 and 32^2 layers
+        // at 66-170 TFLOP/s with runs of 1-7 tiles)
+        long long runs = std::min<long long>(512 / ci_blocks, (tiles + 7) / 8);
+        runs = runs < 1 ? 1 : runs;
+        const int per_run = int((tiles + runs - 1) / runs);
+        runs = (tiles + per_run - 1) / per_run;
+        const dim3 grid(unsigned(runs * ci_blocks));
+        (void)hipGetLastError();
+        switch (a.cout / 32) {
+        case 1: hipLaunchKernelGGL(conv3x3_wgrad_lds_kernel<1>, grid, dim3(128), 0, s, a, ci_blocks, per_run); break;
+        case 2: hipLaunchKernelGGL(conv3x3_wgrad_lds_kernel<2>, grid, dim3(256), 0, s, a, ci_blocks, per_run); break;
+        case 3: hipLaunchKernelGGL(conv3x3_wgrad_lds_kernel<3>, grid, dim3(384), 0, s, a, ci_blocks, per_run); break;
+        default:
+            hipLaunchKernelGGL(conv3x3_wgrad_lds_kernel<4>, grid, dim3(512), 0, s, a, ci_blocks, per_run);
+            break;
+        }
         return hipGetLastError();
     }
     if (even_a && even_b) return wgrad_launch<2, 2, true, true>(b, s);

@@ -401,6 +401,14 @@ def warm_field(spec: CaseSpec, pred, pinned="cap"):
     return cap_field(spec, theta, rl, rg)
 
 
+def sub_grid_interface(spec: CaseSpec, pred):
+    """Whether a prediction marks the case's interface as thinner than the lattice
+    spacing (predicted vapour above VAPOUR_PINNING times Maxwell's), where the contact
+    line is pinned by the lattice and the equilibrium depends on the path."""
+    _, rl, rg = read_prediction(spec, pred)
+    return bool(rl > rg and rg > VAPOUR_PINNING * spec.coexistence()[0])
+
+
 def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000, log=None, calibration_arm=False,
              pinned="cap"):
     """Cold versus warm start of one batched sweep: per-case steps to the plain
@@ -421,7 +429,8 @@ def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000
     # masked out (what a sweep that stops its finished cases spends)
     t_cold = float(steps_cold.max() * dt_cold) if done else float("nan")
     t_warm = float(steps_warm.max() * dt_warm + t_inf) if done else float("nan")
-    out = {"steps_cold": steps_cold, "steps_warm": steps_warm, "step_time_cold": dt_cold,
+    sub_grid = np.array([sub_grid_interface(sp, pr) for sp, pr in zip(specs, pred)])
+    out = {"steps_cold": steps_cold, "steps_warm": steps_warm, "step_time_cold": dt_cold, "sub_grid": sub_grid,
            "step_time_warm": dt_warm, "inference_s": t_inf, "pred": pred,
            "sweep_s_cold": t_cold, "sweep_s_warm": t_warm,
            "speedup": t_cold / t_warm if done else float("nan"),
@@ -522,6 +531,15 @@ def run_experiment(n_cases=2000, side=256, seed=11, n_val=100, n_test=100, train
     out["theta_pred"] = pred_theta.tolist()
     out["theta_pred_abs_err_median"] = float(np.nanmedian(np.abs(pred_theta - theta[test])))
     out["steps_saved_median"] = float(np.median(res["steps_cold"] - res["steps_warm"]))
+    # mean steps to the plain equilibrium angle per arm, over all test cases and over
+    # the two classes the prediction tells apart: resolved interfaces, and interfaces
+    # thinner than the lattice spacing (path-dependent, pinned contact lines)
+    sg = np.asarray(res["sub_grid"], bool)
+    arms = [k for k in ("steps_cold", "steps_calibration_only", "steps_warm") if k in res]
+    for cls, m in (("all", np.ones_like(sg)), ("resolved", ~sg), ("sub_grid", sg)):
+        if m.any():
+            out["steps_mean_" + cls] = {k[6:]: float(np.mean(np.asarray(res[k])[m])) for k in arms}
+            out["steps_mean_" + cls]["cases"] = int(m.sum())
     log("sweep to 0.5 deg: cold %.3f s, warm %.3f s (inference %.3f s): %.2fx; calibration angle alone %.2fx" %
         (out["sweep_s_cold"], out["sweep_s_warm"], out["inference_s"], out["speedup"],
          out.get("speedup_calibration_only", float("nan"))))

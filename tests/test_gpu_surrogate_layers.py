@@ -13,8 +13,8 @@ are the kernel's own FP32 accumulation and its output rounding.  Per element:
 with 2^-24 and 2^-8 the unit roundoffs of FP32 and of BF16 (8-bit significand),
 S the same sum over absolute values (sum |w| |x| + |b|) and K the number of
 FP32 additions behind the element: 9 c_in (padded) for a convolution, 9 c_out
-(padded) for its input gradient, a pixel run plus the runs' atomic additions for a
-weight gradient, 3 for pooling and the upsampling gradient.  Copies (upsampling
+(padded) for its input gradient, a workgroup's run of pixels plus the runs' atomic
+additions for a weight gradient, 3 for pooling and the upsampling gradient.  Copies (upsampling
 into the concatenations) must be exact.  A misplaced tile, halo column, channel
 pair or pixel run changes elements by the size of the values themselves, far
 beyond these bounds.
@@ -33,17 +33,22 @@ U32 = 2.0 ** -24
 U16 = 2.0 ** -8          # unit roundoff of BF16 (8-bit significand, round to nearest)
 
 
-def wgrad_terms(px, cin, cout):
-    """FP32 additions behind one weight-gradient element in the library's schedule:
-    a pixel run, the reduction across the block (at most 16 partials), then one
-    atomic addition per run.  Runs are 512-8192 pixels sized for about 16384 waves,
-    or 256-8192 pixels in 16 groups for the one-output-channel layer."""
+def wgrad_terms(n, h, w, cin, cout):
+    """FP32 additions behind one weight-gradient element in the library's schedule.
+    Layers of 32-128 output channels (the LDS kernel): runs of at least 8 tiles of
+    4 x 32 pixels, at most about 512 workgroups over all 32-channel input blocks, one
+    atomic addition per run; counted as every pixel of a run plus the runs.  The one-output-channel layer:
+    runs of 256-8192 pixels in 16 groups, the reduction across the block, one atomic
+    addition per run."""
+    px = n * h * w
     if cout == 1:
         run = min(max((px // 2048 + 15) // 16 * 16, 256), 8192)
-    else:
-        tiles = 9 * ((cout + 31) // 32) * ((cin + 31) // 32)
-        run = min(max(px * tiles // 16384, 512), 8192) // 32 * 32
-    return run + 16 + (px + run - 1) // run
+        return run + 16 + (px + run - 1) // run
+    tiles = n * (h // 4) * (w // 32)
+    runs = max(min(512 // ((cin + 31) // 32), (tiles + 7) // 8), 1)
+    per_run = (tiles + runs - 1) // runs
+    runs = (tiles + per_run - 1) // per_run
+    return 128 * per_run + 16 + runs
 
 
 def bf16(a):
@@ -133,7 +138,7 @@ def test_weight_and_bias_gradients(run, layer, src):
         dz = dz[:, :1]
     dw, db = S.conv3x3_grad_weight(x, dz)
     sw, sb = S.conv3x3_grad_weight(np.abs(x), np.abs(dz))
-    K = wgrad_terms(x.shape[0] * x.shape[2] * x.shape[3], x.shape[1], dz.shape[1])
+    K = wgrad_terms(x.shape[0], x.shape[2], x.shape[3], x.shape[1], dz.shape[1])
     check("weight gradient " + layer, grads[layer][0], dw, sw, K, bf16_out=False)
     check("bias gradient " + layer, grads[layer][1], db, sb, K, bf16_out=False)
 
