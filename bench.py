@@ -333,7 +333,9 @@ WARMSTART_RECORD = os.path.join(ROOT, "profiles", "warmstart_c5.json")
 WARMSTART_KEYS = ("n_cases", "side", "usable", "loss_first", "loss_last", "val_mse", "sweep_s_cold", "sweep_s_warm",
                   "inference_s", "speedup", "speedup_calibration_only", "masked_sweep_s_cold", "masked_sweep_s_warm",
                   "speedup_masked", "speedup_masked_calibration_only", "steps_saved_median",
-                  "theta_pred_abs_err_median", "training_s", "generation_s")
+                  "theta_pred_abs_err_median", "training_s", "generation_s", "converged", "generation_storage",
+                  "steps_mean_all", "steps_mean_resolved", "steps_mean_sub_grid", "sweep_resolved",
+                  "sweep_sub_grid")
 
 
 def warmstart_summary(live: bool):

@@ -195,6 +195,8 @@ lbm_status capture_graph(lbm_batch* b) {
             b->graph = nullptr;
             return hip_status(e, "hipGraphInstantiate(batch)");
         }
+        // uploaded now, so that the first replay does not carry the upload
+        HIP_TRY(hipGraphUpload(b->graph, b->stream));
     }
     return LBM_OK;
 }

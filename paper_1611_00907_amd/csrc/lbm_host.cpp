@@ -274,6 +274,9 @@ lbm_status capture_graph(lbm_ctx* c) {
             c->graph = nullptr;
             return hip_status(e, "hipGraphInstantiate");
         }
+        // the graph's first launch would otherwise carry its upload to the device
+        // (about 1 ms), inside whatever interval is being timed
+        HIP_TRY(hipGraphUpload(c->graph, c->stream));
     }
     return LBM_OK;
 }

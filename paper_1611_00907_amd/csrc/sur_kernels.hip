@@ -136,17 +136,30 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     }
 }
 
-// LDS-staged convolution for output channels in blocks of 32: a workgroup computes
-// an 8 x 16 pixel tile of one image for 32 output channels.  For each block of 32
-// input channels it stages the 10 x 18 input halo and the 9 x 32 x 32 weights in
-// LDS, and its four waves (two pixel rows of 16 each) take the operands of all nine
-// taps from there.
-constexpr int LT_H = 8, LT_W = 16, LT_CO = 32;
+// LDS-staged convolution: a workgroup of four waves computes a (4 RW) x 16 pixel tile of
+// one image for CO_B output channels (32, 64 or 96), each wave RW pixel rows of 16 for all
+// CO_B channels.  For each block of 32 input channels it stages the (4 RW + 2) x 18
+// input halo and the 9 x CO_B x 32 weights in LDS; per tap a wave then reads CO_B / 16
+// weight blocks and RW pixel blocks and issues RW x CO_B / 16 MFMAs (2 x 2 for RW = 2,
+// CO_B = 32: one LDS read per MFMA; 4 x 4 for RW = 4, CO_B = 64: one per two).
+constexpr int LT_W = 16;
+template <int RW, int CO_B>
+struct LdsConv {
+    static constexpr int TH = 4 * RW;                      // tile rows
+    static constexpr int XIN = (TH + 2) * (LT_W + 2) * 32;  // halo elements
+    static constexpr int WSH = 9 * CO_B * 32;               // weight elements
+    static constexpr int NB = CO_B / 16;                    // 16-channel blocks per wave
+};
+
+template <int RW, int CO_B>
 __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
-    __shared__ __attribute__((aligned(16))) uint16_t xin[(LT_H + 2) * (LT_W + 2) * 32];
-    __shared__ __attribute__((aligned(16))) uint16_t wsh[9 * LT_CO * 32];
-    const int co_blocks = a.cout_p / LT_CO;
-    const int tiles_x = (a.W + LT_W - 1) / LT_W, tiles_y = (a.H + LT_H - 1) / LT_H;
+    using K = LdsConv<RW, CO_B>;
+    constexpr int TH = K::TH, NB = K::NB;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[K::XIN + K::WSH];
+    uint16_t* xin = lds;
+    uint16_t* wsh = lds + K::XIN;
+    const int co_blocks = a.cout_p / CO_B;
+    const int tiles_x = (a.W + LT_W - 1) / LT_W, tiles_y = (a.H + TH - 1) / TH;
     int b = blockIdx.x;
     const int co_blk = b % co_blocks;
     b /= co_blocks;
@@ -154,20 +167,20 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
     b /= tiles_x;
     const int ty = b % tiles_y;
     const int img = b / tiles_y;
-    const int x0 = tx * LT_W, y0 = ty * LT_H, co_base = co_blk * LT_CO;
+    const int x0 = tx * LT_W, y0 = ty * TH, co_base = co_blk * CO_B;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
 
-    f32x4 acc[2][2];
+    f32x4 acc[RW][NB];
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+    for (int m = 0; m < RW; ++m)
 #pragma unroll
-        for (int n = 0; n < 2; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     for (int ci0 = 0; ci0 < a.cin_p; ci0 += 32) {
-        // input halo: (LT_H + 2) x (LT_W + 2) pixels x 32 channels, zero outside the
+        // input halo: (TH + 2) x (LT_W + 2) pixels x 32 channels, zero outside the
         // image and beyond cin; 8 channels (16 bytes) per load
-        for (int q = threadIdx.x; q < (LT_H + 2) * (LT_W + 2) * 4; q += 256) {
+        for (int q = threadIdx.x; q < (TH + 2) * (LT_W + 2) * 4; q += 256) {
             const int pix = q >> 2, cg = q & 3;
             const int yy = y0 - 1 + pix / (LT_W + 2), xx = x0 - 1 + pix % (LT_W + 2);
             const int ci = ci0 + 8 * cg;
@@ -177,10 +190,10 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
                                                     a.in.co + ci);
             *reinterpret_cast<uint4*>(xin + pix * 32 + 8 * cg) = v;
         }
-        // weights of this block: [tap][32 output channels][32 input channels]
-        for (int q = threadIdx.x; q < 9 * LT_CO * 4; q += 256) {
+        // weights of this block: [tap][CO_B output channels][32 input channels]
+        for (int q = threadIdx.x; q < 9 * CO_B * 4; q += 256) {
             const int row = q >> 2, cg = q & 3;
-            const int tap = row / LT_CO, col = row - tap * LT_CO;
+            const int tap = row / CO_B, col = row - tap * CO_B;
             *reinterpret_cast<uint4*>(wsh + row * 32 + 8 * cg) = *reinterpret_cast<const uint4*>(
                 a.w + ((size_t)(tap * a.cout_p + co_base + col) * a.cin_p + ci0 + 8 * cg));
         }
@@ -188,49 +201,48 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int du = tap / 3 - 1, dv = tap % 3 - 1;
-            bf16x8 av[2], bv[2];
+            bf16x8 bv[NB];
 #pragma unroll
-            for (int m = 0; m < 2; ++m) {
-                const int ly = 2 * wave + m + 1 + du, lx = r + 1 + dv;
-                av[m] = as_bf16x8(*reinterpret_cast<const uint4*>(xin + (ly * (LT_W + 2) + lx) * 32 + 8 * g));
+            for (int n = 0; n < NB; ++n)
+                bv[n] = as_bf16x8(*reinterpret_cast<const uint4*>(wsh + (tap * CO_B + 16 * n + r) * 32 + 8 * g));
+#pragma unroll
+            for (int m = 0; m < RW; ++m) {
+                const int ly = RW * wave + m + 1 + du, lx = r + 1 + dv;
+                const bf16x8 av = as_bf16x8(*reinterpret_cast<const uint4*>(xin + (ly * (LT_W + 2) + lx) * 32 + 8 * g));
+#pragma unroll
+                for (int n = 0; n < NB; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[n], acc[m][n], 0, 0, 0);
             }
-#pragma unroll
-            for (int n = 0; n < 2; ++n)
-                bv[n] = as_bf16x8(*reinterpret_cast<const uint4*>(wsh + (tap * LT_CO + 16 * n + r) * 32 + 8 * g));
-#pragma unroll
-            for (int m = 0; m < 2; ++m)
-#pragma unroll
-                for (int n = 0; n < 2; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv[n], acc[m][n], 0, 0, 0);
         }
         __syncthreads();  // the next block of channels overwrites the LDS
     }
 
-    // BF16 epilogues: bias and ReLU in registers, the 128 x 32 tile through LDS (the
-    // input halo's space, free after the last barrier), then 16-byte stores of 8
-    // channels (the mask of EPI_MASK_BF16 read 16 bytes at a time as well)
+    // BF16 epilogues: bias and ReLU in registers, the TH x 16 x CO_B tile through LDS
+    // (free after the last barrier), then 16-byte stores of 8 channels (the mask of
+    // EPI_MASK_BF16 read 16 bytes at a time as well)
     if (a.epi != EPI_F32) {
-        uint16_t* ost = xin;  // [LT_H * LT_W pixels][LT_CO channels]
+        static_assert(TH * LT_W * CO_B <= K::XIN + K::WSH, "the output tile fits the staging space");
+        uint16_t* ost = lds;  // [TH * LT_W pixels][CO_B channels]
 #pragma unroll
-        for (int n = 0; n < 2; ++n) {
+        for (int n = 0; n < NB; ++n) {
             const int cl = 16 * n + r, co = co_base + cl;
             const float bias = (a.bias != nullptr && co < a.cout) ? a.bias[co] : 0.0f;
 #pragma unroll
-            for (int m = 0; m < 2; ++m)
+            for (int m = 0; m < RW; ++m)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     float v = acc[m][n][i] + bias;
                     if (a.epi == EPI_RELU_BF16) v = v > 0.f ? v : 0.f;
-                    ost[((2 * wave + m) * LT_W + 4 * g + i) * LT_CO + cl] = f2bf(v);
+                    ost[((RW * wave + m) * LT_W + 4 * g + i) * CO_B + cl] = f2bf(v);
                 }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < LT_H * LT_W * (LT_CO / 8); q += 256) {
-            const int pl = q / (LT_CO / 8), cg = q % (LT_CO / 8);
+        for (int q = threadIdx.x; q < TH * LT_W * (CO_B / 8); q += 256) {
+            const int pl = q / (CO_B / 8), cg = q % (CO_B / 8);
             const int y = y0 + pl / LT_W, x = x0 + pl % LT_W, co = co_base + 8 * cg;
             if (y >= a.H || x >= a.W || co >= a.cout) continue;
             const long long p = ((long long)img * a.H + y) * a.W + x;
-            uint4 v = *reinterpret_cast<const uint4*>(ost + pl * LT_CO + 8 * cg);
+            uint4 v = *reinterpret_cast<const uint4*>(ost + pl * CO_B + 8 * cg);
             if (a.epi == EPI_MASK_BF16) {
                 const uint4 mk = *reinterpret_cast<const uint4*>(a.mask.p + p * a.mask.cs + a.mask.co + co);
                 auto keep = [](uint32_t w, uint32_t m) {  // zero each BF16 half whose mask is not > 0
@@ -248,38 +260,172 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
         return;
     }
 
-    // FP32 epilogue: lane holds pixels (y0 + 2 wave + m, x0 + 4 g + i), channel co_base + 16 n + r
+    // FP32 epilogue: lane holds pixels (y0 + RW wave + m, x0 + 4 g + i), channel co_base + 16 n + r
 #pragma unroll
-    for (int n = 0; n < 2; ++n) {
+    for (int n = 0; n < NB; ++n) {
         const int co = co_base + 16 * n + r;
         if (co >= a.cout) continue;
         const float bias = (a.bias != nullptr) ? a.bias[co] : 0.0f;
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            const int y = y0 + 2 * wave + m;
+        for (int m = 0; m < RW; ++m) {
+            const int y = y0 + RW * wave + m;
             if (y >= a.H) continue;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int x = x0 + 4 * g + i;
                 if (x >= a.W) continue;
                 const long long p = ((long long)img * a.H + y) * a.W + x;
-                const float v = acc[m][n][i] + bias;
-                switch (a.epi) {
-                case EPI_RELU_BF16:
-                    a.out.p[p * a.out.cs + a.out.co + co] = f2bf(v > 0.f ? v : 0.f);
-                    break;
-                case EPI_MASK_BF16: {
-                    const float mk = bf2f(a.mask.p[p * a.mask.cs + a.mask.co + co]);
-                    a.out.p[p * a.out.cs + a.out.co + co] = f2bf(mk > 0.f ? v : 0.f);
-                    break;
-                }
-                case EPI_BF16:
-                    a.out.p[p * a.out.cs + a.out.co + co] = f2bf(v);
-                    break;
-                default:  // EPI_F32
-                    a.out_f32[p * a.out_f32_cs + co] = v;
+                a.out_f32[p * a.out_f32_cs + co] = acc[m][n][i] + bias;
+            }
+        }
+    }
+}
+
+// The same convolution for layers of 32 input channels (one channel block), with a
+// workgroup walking a run of pixel tiles: the weights are staged once for the run,
+// the next tile's input halo is loaded into registers while the current tile's
+// MFMAs run, and the output tile goes out through an LDS area of its own, so that the
+// load, MFMA and store phases of consecutive tiles overlap.  The 256^2 layers of 32
+// channels are close to memory-bound, and the one-tile workgroups left these phases
+// back to back.
+template <int RW, int CO_B>
+__global__ __launch_bounds__(256) void conv3x3_lds_run_kernel(ConvArgs a, int tiles_per_run) {
+    using K = LdsConv<RW, CO_B>;
+    constexpr int TH = K::TH, NB = K::NB;
+    constexpr int HALO = (TH + 2) * (LT_W + 2) * 4;  // 16-byte pieces of the input halo
+    constexpr int HR = (HALO + 255) / 256;            // per thread
+    constexpr int OST = TH * LT_W * CO_B;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[K::XIN + K::WSH + OST];
+    uint16_t* xin = lds;
+    uint16_t* wsh = lds + K::XIN;
+    uint16_t* ost = lds + K::XIN + K::WSH;
+    const int co_blocks = a.cout_p / CO_B;
+    const int tiles_x = (a.W + LT_W - 1) / LT_W, tiles_y = (a.H + TH - 1) / TH;
+    const int tiles = a.N * tiles_y * tiles_x;
+    const int co_blk = blockIdx.x % co_blocks, co_base = co_blk * CO_B;
+    const int t_begin = (blockIdx.x / co_blocks) * tiles_per_run;
+    if (t_begin >= tiles) return;  // the whole workgroup
+    const int t_end = min(t_begin + tiles_per_run, tiles);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+
+    // weights of the run: [tap][CO_B output channels][32 input channels]
+    for (int q = threadIdx.x; q < 9 * CO_B * 4; q += 256) {
+        const int row = q >> 2, cg = q & 3;
+        const int tap = row / CO_B, col = row - tap * CO_B;
+        *reinterpret_cast<uint4*>(wsh + row * 32 + 8 * cg) =
+            *reinterpret_cast<const uint4*>(a.w + ((size_t)(tap * a.cout_p + co_base + col) * a.cin_p + 8 * cg));
+    }
+    auto tile_origin = [&](int t, int& img, int& y0, int& x0) {
+        img = t / (tiles_y * tiles_x);
+        const int tt = t - img * tiles_y * tiles_x;
+        y0 = (tt / tiles_x) * TH;
+        x0 = (tt % tiles_x) * LT_W;
+    };
+    // halo piece q of a tile: pixel q / 4 of the (TH + 2) x (LT_W + 2) halo, channels 8 (q % 4) ..
+    auto load_halo = [&](int t, uint4* hr) {
+        int img, y0, x0;
+        tile_origin(t, img, y0, x0);
+#pragma unroll
+        for (int k = 0; k < HR; ++k) {
+            const int q = threadIdx.x + 256 * k;
+            const int pix = q >> 2, cg = q & 3;
+            const int yy = y0 - 1 + pix / (LT_W + 2), xx = x0 - 1 + pix % (LT_W + 2);
+            const int ci = 8 * cg;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (q < HALO && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W && ci < a.cin)
+                v = *reinterpret_cast<const uint4*>(a.in.p + (((long long)img * a.H + yy) * a.W + xx) * a.in.cs +
+                                                    a.in.co + ci);
+            hr[k] = v;
+        }
+    };
+    uint4 hr[HR];
+    load_halo(t_begin, hr);
+    for (int t = t_begin; t < t_end; ++t) {
+#pragma unroll
+        for (int k = 0; k < HR; ++k) {
+            const int q = threadIdx.x + 256 * k;
+            if (q < HALO) *reinterpret_cast<uint4*>(xin + (q >> 2) * 32 + 8 * (q & 3)) = hr[k];
+        }
+        __syncthreads();  // halo (and, on the first tile, weights) in place; the last tile's output stored
+        if (t + 1 < t_end) load_halo(t + 1, hr);  // in flight during the MFMAs
+        f32x4 acc[RW][NB];
+#pragma unroll
+        for (int m = 0; m < RW; ++m)
+#pragma unroll
+            for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int du = tap / 3 - 1, dv = tap % 3 - 1;
+            bf16x8 bv[NB];
+#pragma unroll
+            for (int n = 0; n < NB; ++n)
+                bv[n] = as_bf16x8(*reinterpret_cast<const uint4*>(wsh + (tap * CO_B + 16 * n + r) * 32 + 8 * g));
+#pragma unroll
+            for (int m = 0; m < RW; ++m) {
+                const int ly = RW * wave + m + 1 + du, lx = r + 1 + dv;
+                const bf16x8 av = as_bf16x8(*reinterpret_cast<const uint4*>(xin + (ly * (LT_W + 2) + lx) * 32 + 8 * g));
+#pragma unroll
+                for (int n = 0; n < NB; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[n], acc[m][n], 0, 0, 0);
+            }
+        }
+        int img, y0, x0;
+        tile_origin(t, img, y0, x0);
+        if (a.epi == EPI_F32) {  // lane holds pixels (y0 + RW wave + m, x0 + 4 g + i), channel co_base + 16 n + r
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                const int co = co_base + 16 * n + r;
+                if (co >= a.cout) continue;
+                const float bias = (a.bias != nullptr) ? a.bias[co] : 0.0f;
+#pragma unroll
+                for (int m = 0; m < RW; ++m) {
+                    const int y = y0 + RW * wave + m;
+                    if (y >= a.H) continue;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int x = x0 + 4 * g + i;
+                        if (x >= a.W) continue;
+                        a.out_f32[(((long long)img * a.H + y) * a.W + x) * a.out_f32_cs + co] = acc[m][n][i] + bias;
+                    }
                 }
             }
+            __syncthreads();  // every wave is done with this tile's halo
+            continue;
+        }
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            const int cl = 16 * n + r, co = co_base + cl;
+            const float bias = (a.bias != nullptr && co < a.cout) ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int m = 0; m < RW; ++m)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float v = acc[m][n][i] + bias;
+                    if (a.epi == EPI_RELU_BF16) v = v > 0.f ? v : 0.f;
+                    ost[((RW * wave + m) * LT_W + 4 * g + i) * CO_B + cl] = f2bf(v);
+                }
+        }
+        __syncthreads();  // the output tile is in LDS; every wave is done with the halo
+        for (int q = threadIdx.x; q < TH * LT_W * (CO_B / 8); q += 256) {
+            const int pl = q / (CO_B / 8), cg = q % (CO_B / 8);
+            const int y = y0 + pl / LT_W, x = x0 + pl % LT_W, co = co_base + 8 * cg;
+            if (y >= a.H || x >= a.W || co >= a.cout) continue;
+            const long long p = ((long long)img * a.H + y) * a.W + x;
+            uint4 v = *reinterpret_cast<const uint4*>(ost + pl * CO_B + 8 * cg);
+            if (a.epi == EPI_MASK_BF16) {
+                const uint4 mk = *reinterpret_cast<const uint4*>(a.mask.p + p * a.mask.cs + a.mask.co + co);
+                auto keep = [](uint32_t w, uint32_t mm) {  // zero each BF16 half whose mask is not > 0
+                    const uint32_t lo = bf2f(uint16_t(mm)) > 0.f ? 0x0000ffffu : 0u;
+                    const uint32_t hi = bf2f(uint16_t(mm >> 16)) > 0.f ? 0xffff0000u : 0u;
+                    return w & (lo | hi);
+                };
+                v.x = keep(v.x, mk.x);
+                v.y = keep(v.y, mk.y);
+                v.z = keep(v.z, mk.z);
+                v.w = keep(v.w, mk.w);
+            }
+            *reinterpret_cast<uint4*>(a.out.p + p * a.out.cs + a.out.co + co) = v;
         }
     }
 }
@@ -990,10 +1136,42 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
     (void)hipGetLastError();
     const bool views8 = a.cout % 8 == 0 && a.out.cs % 8 == 0 && a.out.co % 8 == 0 &&
                         (a.epi != EPI_MASK_BF16 || (a.mask.cs % 8 == 0 && a.mask.co % 8 == 0));
-    if (a.cout_p % LT_CO == 0 && (a.epi == EPI_F32 || views8)) {
-        const long long blocks = (long long)a.N * ((a.H + LT_H - 1) / LT_H) * ((a.W + LT_W - 1) / LT_W) *
-                                 (a.cout_p / LT_CO);
-        hipLaunchKernelGGL(conv3x3_lds_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, a);
+    auto blocks_of = [&](int th, int co_b) {
+        return (long long)a.N * ((a.H + th - 1) / th) * ((a.W + LT_W - 1) / LT_W) * (a.cout_p / co_b);
+    };
+    auto lds = [&](auto kernel, int th, int co_b) {
+        hipLaunchKernelGGL(kernel, dim3(unsigned(blocks_of(th, co_b))), dim3(256), 0, s, a);
+    };
+    if (a.cout_p % 32 == 0 && (a.epi == EPI_F32 || views8)) {
+        // the widest channel block (each staged halo then serves more output channels)
+        // that still gives at least 1024 workgroups (64 or 96 channels, 4 rows per wave),
+        // else 32 channels with 4 rows per wave if that gives 512, else with 2 (measured:
+        // a 64^2 layer of 96 channels takes 46 us as one 96-channel block of 256
+        // workgroups, 32 us as three 32-channel blocks of 4 rows per wave, 37 us of 2)
+        constexpr long long ENOUGH = 1024;
+        if (a.cin_p == 32 && a.H >= 16) {
+            // one input-channel block: runs of tiles, two workgroups per CU
+            const int co_blocks = a.cout_p / 32;
+            const long long tiles = blocks_of(LdsConv<4, 32>::TH, 32) / co_blocks;
+            long long runs = std::max<long long>(1, 512 / co_blocks);
+            runs = std::min(runs, tiles);
+            const int per_run = int((tiles + runs - 1) / runs);
+            runs = (tiles + per_run - 1) / per_run;
+            hipLaunchKernelGGL((conv3x3_lds_run_kernel<4, 32>), dim3(unsigned(runs * co_blocks)), dim3(256), 0, s, a,
+                               per_run);
+            return hipGetLastError();
+        }
+        const long long b64 = a.cout_p % 64 == 0 ? blocks_of(LdsConv<4, 64>::TH, 64) : 0;
+        const long long b96 = a.cout_p % 96 == 0 ? blocks_of(LdsConv<4, 96>::TH, 96) : 0;
+        const long long b32 = blocks_of(LdsConv<4, 32>::TH, 32);
+        if (b64 >= ENOUGH)
+            lds(conv3x3_lds_kernel<4, 64>, LdsConv<4, 64>::TH, 64);
+        else if (b96 >= ENOUGH)
+            lds(conv3x3_lds_kernel<4, 96>, LdsConv<4, 96>::TH, 96);
+        else if (b32 >= ENOUGH / 2)
+            lds(conv3x3_lds_kernel<4, 32>, LdsConv<4, 32>::TH, 32);
+        else
+            lds(conv3x3_lds_kernel<2, 32>, LdsConv<2, 32>::TH, 32);
     } else {
         const long long waves = ((npx + 63) / 64) * (a.cout_p / 16);
         hipLaunchKernelGGL((conv3x3_kernel<4, 1>), dim3(int((waves + 3) / 4)), dim3(256), 0, s, a);

@@ -410,10 +410,13 @@ def sub_grid_interface(spec: CaseSpec, pred):
 
 
 def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000, log=None, calibration_arm=False,
-             pinned="cap"):
+             pinned="cap", by_class=False):
     """Cold versus warm start of one batched sweep: per-case steps to the plain
     equilibrium angle, and the sweep's device time until its last case is there
-    (for the warm start plus the network inference and the warm-field set-up)."""
+    (for the warm start plus the network inference and the warm-field set-up).
+    With by_class, the cold and warm sweeps are also run separately over the two
+    classes the prediction tells apart (resolved and sub-grid interfaces), each
+    charged its share of the inference time."""
     cold0 = [initial_density(s) for s in specs]
     steps_cold, dt_cold, dev_cold = time_to_angle(specs, cold0, theta_eq, tol_deg, check_every, max_steps, log=log)
     t0 = time.perf_counter()
@@ -436,6 +439,25 @@ def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000
            "speedup": t_cold / t_warm if done else float("nan"),
            "masked_sweep_s_cold": dev_cold, "masked_sweep_s_warm": dev_warm + t_inf,
            "speedup_masked": dev_cold / (dev_warm + t_inf) if done else float("nan")}
+    if by_class:
+        theta_eq = np.asarray(theta_eq)
+        for cls, m in (("resolved", ~sub_grid), ("sub_grid", sub_grid)):
+            idx = np.flatnonzero(m)
+            if idx.size == 0:
+                continue
+            sp = [specs[i] for i in idx]
+            sc, dtc, devc = time_to_angle(sp, [cold0[i] for i in idx], theta_eq[idx], tol_deg, check_every,
+                                          max_steps, log=log)
+            sw, dtw, devw = time_to_angle(sp, [warm0[i] for i in idx], theta_eq[idx], tol_deg, check_every,
+                                          max_steps, log=log)
+            ok = (sc >= 0).all() and (sw >= 0).all()
+            share = t_inf * idx.size / len(specs)
+            tc = float(sc.max() * dtc) if ok else float("nan")
+            tw = float(sw.max() * dtw + share) if ok else float("nan")
+            out["sweep_" + cls] = {"cases": int(idx.size), "sweep_s_cold": tc, "sweep_s_warm": tw,
+                                   "speedup": tc / tw if ok else float("nan"), "masked_sweep_s_cold": devc,
+                                   "masked_sweep_s_warm": devw + share,
+                                   "speedup_masked": devc / (devw + share) if ok else float("nan")}
     if calibration_arm:
         # the same sweep started from the calibration's angle alone (no network):
         # what the trained network adds over the method without it
@@ -514,7 +536,7 @@ def run_experiment(n_cases=2000, side=256, seed=11, n_val=100, n_test=100, train
     out["val_mse"] = float(np.mean((net.forward(xv) - tv) ** 2))
     tspecs = [specs[i] for i in test]
     res = evaluate(net, tspecs, theta[test], tol_deg=0.5, check_every=200, max_steps=40000, log=log,
-                   calibration_arm=True, pinned=pinned)
+                   calibration_arm=True, pinned=pinned, by_class=True)
     out["theta_calibration_abs_err_median"] = float(np.median(np.abs([s.theta0 for s in tspecs] - theta[test])))
     pred_theta = np.array([read_prediction(s, p)[0] for s, p in zip(tspecs, res["pred"])])
     if debug_path:
@@ -546,6 +568,11 @@ def run_experiment(n_cases=2000, side=256, seed=11, n_val=100, n_test=100, train
     log("masked sweep (settled cases stopped): cold %.3f s, warm %.3f s: %.2fx; calibration angle alone %.2fx" %
         (out["masked_sweep_s_cold"], out["masked_sweep_s_warm"], out["speedup_masked"],
          out.get("speedup_masked_calibration_only", float("nan"))))
+    for cls in ("resolved", "sub_grid"):
+        if "sweep_" + cls in out:
+            c = out["sweep_" + cls]
+            log("%s interfaces (%d cases): sweep %.2fx, masked sweep %.2fx" % (cls, c["cases"], c["speedup"],
+                                                                                c["speedup_masked"]))
     net.close()
     return out
 
