@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 MONITOR_EVERY = 100
 KERNEL_SRC = os.path.join(ROOT, "paper_1611_00907_amd", "csrc", "lbm_kernels.hip")
+KERNEL3_SRC = os.path.join(ROOT, "paper_1611_00907_amd", "csrc", "lbm3d_kernels.hip")
 
 
 def parse():
@@ -52,7 +53,7 @@ def parse():
                     help="also run the learned warm-start experiment live (2000 cases at 256^2: "
                          "equilibria, training, cold vs warm sweep; several minutes)")
     ap.add_argument("--workload", choices=("spinodal4096", "wetting1024", "spinodal4096_f16dev",
-                                           "spinodal4096_bf16dev", "batch256", "batch256_residual"),
+                                           "spinodal4096_bf16dev", "batch256", "batch256_residual", "d3q19"),
                     default="spinodal4096",
                     help="main measurement: the 4096^2 FP32 spinodal lattice (default, HBM-bound); the others "
                          "(the 1024^2 FP32 wetting lattice, the 16-bit storage types, the 256-case batch) "
@@ -211,7 +212,22 @@ def measure_d3q19(lbm, inputs, n=256, steps=50):
     return {"workload": "D3Q19 spinodal %d^3 periodic VdW Tr=0.85, f32 storage (density pass + fused step pass)" % n,
             "mlups": round(nodes / t / 1e6, 1), "ms_per_step": round(t * 1e3, 4),
             "roofline": {"bound": "hbm", "achieved": round(nodes * 152.0 / t / 1e9, 1), "peak": PEAK_HBM_GBS,
-                         "unit": "GB/s", "frac": round(nodes * 152.0 / t / 1e9 / PEAK_HBM_GBS, 4), "traffic": None}}
+                         "unit": "GB/s", "frac": round(nodes * 152.0 / t / 1e9 / PEAK_HBM_GBS, 4),
+                         "traffic": traffic3_for("step3_f32_d3q19_256")}}
+
+
+def traffic3_for(workload: str):
+    """HBM bytes per D3Q19 step (density pass plus step pass) from committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE counts, scaled as for the 2-D step, if they were taken on
+    the current 3-D kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_sha") != hashlib.sha256(open(KERNEL3_SRC, "rb").read()).hexdigest()[:16]:
+        return None
+    return round((d["fetch_kib_per_step"] * d["fetch_factor"] + d["write_kib_per_step"] * d["write_factor"]) * 1024.0,
+                 0)
 
 
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
@@ -421,6 +437,9 @@ def main():
         return
     if args.workload == "batch256_residual":
         print(json.dumps(measure_batch_residual(lbm, inputs)), flush=True)
+        return
+    if args.workload == "d3q19":
+        print(json.dumps({"workload": "d3q19", "aux": [measure_d3q19(lbm, inputs, steps=args.steps)]}), flush=True)
         return
     if args.workload == "spinodal4096":
         p, rho0, mu_w, fluid = spinodal_workload(lbm, inputs, lbm.LBM_F32)

@@ -1,7 +1,8 @@
-"""GPU: every kernel of the surrogate, element by element, at the training size.
+"""GPU: every kernel of the surrogate, element by element, at the training size and
+at a ragged one.
 
-One forward and backward pass of the network at 256^2 (batch 2) runs with the
-library's trace on, so that the BF16 tensors each kernel read and wrote can be
+One forward and backward pass of the network at 256^2 (batch 2) and at 40^2 (batch
+3: every map ends in partial tiles) runs with the library's trace on, so that the BF16 tensors each kernel read and wrote can be
 read back (sur_read).  Each kernel is then recomputed in FP64 by the oracle from
 exactly the BF16 operands that kernel used on the GPU (its input activation or
 output gradient as stored, the BF16-rounded weights), so the only differences left
@@ -28,7 +29,9 @@ pytestmark = pytest.mark.gpu
 
 lbm = pytest.importorskip("paper_1611_00907_amd.lbm")
 
-SIZE, BATCH = 256, 2
+# the training size, and a size whose maps (40, 20, 10, 5) end in ragged tiles of every
+# convolution kernel and take the gather weight-gradient kernel (widths not a multiple of 32)
+SHAPES = [(256, 2), (40, 3)]
 U32 = 2.0 ** -24
 U16 = 2.0 ** -8          # unit roundoff of BF16 (8-bit significand, round to nearest)
 
@@ -37,12 +40,18 @@ def wgrad_terms(n, h, w, cin, cout):
     """FP32 additions behind one weight-gradient element in the library's schedule.
     Layers of 32-128 output channels (the LDS kernel): runs of at least 8 tiles of
     4 x 32 pixels, at most about 512 workgroups over all 32-channel input blocks, one
-    atomic addition per run; counted as every pixel of a run plus the runs.  The one-output-channel layer:
+    atomic addition per run; counted as every pixel of a run plus the runs.  Maps
+    whose width is not a multiple of 32: the gather kernel's pixel runs.  The one-output-channel layer:
     runs of 256-8192 pixels in 16 groups, the reduction across the block, one atomic
     addition per run."""
     px = n * h * w
     if cout == 1:
         run = min(max((px // 2048 + 15) // 16 * 16, 256), 8192)
+        return run + 16 + (px + run - 1) // run
+    if not (cout % 32 == 0 and cout <= 128 and w % 32 == 0 and h % 4 == 0 and cin % 8 == 0):
+        # the gather kernel: pixel runs of 512-8192 sized for about 16384 waves
+        blocks = 9 * ((cout + 31) // 32) * ((cin + 31) // 32)
+        run = min(max(px * blocks // 16384, 512), 8192) // 32 * 32
         return run + 16 + (px + run - 1) // run
     tiles = n * (h // 4) * (w // 32)
     runs = max(min(512 // ((cin + 31) // 32), (tiles + 7) // 8), 1)
@@ -63,8 +72,9 @@ def nchw(t):
     return np.ascontiguousarray(t.transpose(0, 3, 1, 2), dtype=np.float64)
 
 
-@pytest.fixture(scope="module")
-def run():
+@pytest.fixture(scope="module", params=SHAPES, ids=["%dx%d" % s for s in SHAPES])
+def run(request):
+    SIZE, BATCH = request.param
     r = np.random.default_rng(21)
     params = S.init_params(17)
     params = {k: (w, r.normal(0, 0.05, b.shape)) for k, (w, b) in params.items()}
