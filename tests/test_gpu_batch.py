@@ -54,6 +54,26 @@ def test_batch_equals_single_runs_fp32():
         assert np.array_equal(b.get_state(i), f), "case %d" % i
 
 
+def test_batch_beyond_the_caches_equals_single_runs():
+    """A batch whose distributions exceed the 256 MB Infinity Cache stores them with
+    the non-temporal hint (one 2048^2 case brings it to 0.3 GB); every case must still
+    equal its single run bit for bit (the 2048^2 single lattice takes the hint as well,
+    the small ones do not)."""
+    big = Case(2048, 2048, thermo.PR, 0.8, 1.3, omega=0.344, bottom=CPWALL, top=NEUTRAL, drop="sessile",
+               radius=400.0, noise=1e-4, seed=77)
+    big.mu_w_bottom = big.coexistence()[3] + 0.01
+    cases = _cases(3) + [big]
+    b = _batch(cases, lbm.LBM_F32)
+    b.step(24)
+    for i, c in enumerate(cases):
+        lat = _single(c, lbm.LBM_F32)
+        lat.step(24)
+        f, _ = lat.get_state()
+        lat.close()
+        assert np.array_equal(b.get_state(i), f), "case %d" % i
+    b.close()
+
+
 @pytest.mark.parametrize("bpc", [-1, 0, 1, 2])
 def test_batch_schedules_agree(bpc):
     """Every grid of the batched launch (k workgroups per CU, as many as fit, one
