@@ -38,6 +38,14 @@ struct W3 {
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Workgroups are dealt round-robin to the 8 XCDs; renumbered so that each XCD gets a
+// contiguous band of blocks, neighbouring blocks (which pull from each other's
+// planes) share an L2 instead of fetching the same lines through eight of them.
+__device__ __forceinline__ unsigned xcd_band(unsigned b, unsigned nblk) {
+    const unsigned q = nblk >> 3, r = nblk & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // Offset of node (x, y, z) in a plane.
 __device__ __forceinline__ unsigned node(const Args3& A, int x, int y, int z) {
     return (unsigned(z) * unsigned(A.ny) + unsigned(y)) * unsigned(A.pitch) + unsigned(x);
@@ -84,7 +92,7 @@ __device__ __forceinline__ CT sum19(const CT f[19]) {
 template <typename ST, typename CT>
 __global__ __launch_bounds__(256) void density_kernel(Args3 A, const ST* __restrict__ fin, CT* __restrict__ rho) {
     const unsigned n = unsigned(A.nx) * unsigned(A.ny) * unsigned(A.nz);
-    const unsigned c = blockIdx.x * 256u + threadIdx.x;
+    const unsigned c = xcd_band(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
     if (c >= n) return;
     const unsigned x = c % unsigned(A.nx), yz = c / unsigned(A.nx);
     const unsigned y = yz % unsigned(A.ny), z = yz / unsigned(A.ny);
@@ -130,12 +138,13 @@ constexpr int MX = TX + 2, MYX = (TY + 2) * MX;   // strides of ms
 
 // Step pass (MODE 0) or field output (MODE 1: out = [5][nz][ny][nx] doubles rho,
 // vx, vy, vz, mu with v = u + F / (2 rho)).
-template <typename ST, typename CT, int EOS, int MODE>
+// NTS: the stores of f*(t) are non-temporal (boxes larger than the caches).
+template <typename ST, typename CT, int EOS, int MODE, bool NTS = false>
 __global__ __launch_bounds__(NT) void step3_kernel(Args3 A, const ST* __restrict__ fin, const CT* __restrict__ rho_g,
                                                    ST* __restrict__ fout, double* __restrict__ out) {
     __shared__ Lds3<CT> L;
     const int bx = (A.nx + TX - 1) / TX, by = (A.ny + TY - 1) / TY;
-    const int b = blockIdx.x;
+    const int b = int(xcd_band(blockIdx.x, gridDim.x));
     const int x0 = (b % bx) * TX, y0 = ((b / bx) % by) * TY, z0 = (b / (bx * by)) * TZ;
     // 1. density of the block and its two-node ring (periodic wrap)
     for (int q = threadIdx.x; q < (TZ + 4) * RYX; q += NT) {
@@ -199,7 +208,11 @@ __global__ __launch_bounds__(NT) void step3_kernel(Args3 A, const ST* __restrict
             const CT w = i == 0 ? W3<CT>::w0 : (i <= 6 ? W3<CT>::w1 : W3<CT>::w2);
             const CT eu = (CT(CX[i]) * ux + CT(CY[i]) * uy) + CT(CZ[i]) * uz;
             const CT feq = w * rho * (CT(1) + CT(3) * eu + CT(4.5) * eu * eu - usq);
-            fout[i * A.plane + o] = ST(f[i] - (f[i] - feq) * inv_tau);
+            const ST v = ST(f[i] - (f[i] - feq) * inv_tau);
+            if constexpr (NTS)
+                __builtin_nontemporal_store(v, &fout[i * A.plane + o]);
+            else
+                fout[i * A.plane + o] = v;
         }
     }
 }
@@ -251,7 +264,12 @@ hipError_t step_eos(int mode, const Args3& A, const void* fin, void* rho, void* 
     if (e != hipSuccess) return e;
     const unsigned blocks = unsigned((A.nx + TX - 1) / TX) * unsigned((A.ny + TY - 1) / TY) *
                             unsigned((A.nz + TZ - 1) / TZ);
-    if (mode == 0)
+    // non-temporal stores when the two distribution buffers exceed the 256 MB Infinity Cache
+    const bool nt = 2 * 19 * A.plane * (long long)sizeof(ST) > (256LL << 20);
+    if (mode == 0 && nt)
+        hipLaunchKernelGGL((step3_kernel<ST, CT, EOS, 0, true>), dim3(blocks), dim3(NT), 0, s, A, (const ST*)fin,
+                           (const CT*)rho, (ST*)fout, out);
+    else if (mode == 0)
         hipLaunchKernelGGL((step3_kernel<ST, CT, EOS, 0>), dim3(blocks), dim3(NT), 0, s, A, (const ST*)fin,
                            (const CT*)rho, (ST*)fout, out);
     else
