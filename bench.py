@@ -53,7 +53,8 @@ def parse():
                     help="also run the learned warm-start experiment live (2000 cases at 256^2: "
                          "equilibria, training, cold vs warm sweep; several minutes)")
     ap.add_argument("--workload", choices=("spinodal4096", "wetting1024", "spinodal4096_f16dev",
-                                           "spinodal4096_bf16dev", "batch256", "batch256_residual", "d3q19"),
+                                           "spinodal4096_bf16dev", "batch256", "batch256_residual", "d3q19",
+                                           "variants"),
                     default="spinodal4096",
                     help="main measurement: the 4096^2 FP32 spinodal lattice (default, HBM-bound); the others "
                          "(the 1024^2 FP32 wetting lattice, the 16-bit storage types, the 256-case batch) "
@@ -184,7 +185,15 @@ def measure_variants(lbm, inputs, steps=100):
                 ("eq12_mrt", lbm.LBM_COLLIDE_MRT), ("eq5_mrt", lbm.LBM_FORCE_PTENSOR | lbm.LBM_COLLIDE_MRT)]
     p0, rho0, _, fluid = spinodal_workload(lbm, inputs, lbm.LBM_F32)
     out = {"workload": "force and collision variants, spinodal 4096x4096 VdW Tr=0.85, f32 storage, 64x16 tiles",
-           "kernel_us": {}, "achieved_gbs": {}}
+           "kernel_us": {}, "mlups": {}, "achieved_gbs": {}, "hbm_bytes": {}}
+    traffic = {}
+    path = os.path.join(ROOT, "profiles", "traffic_step_f32_variants4096.json")
+    if os.path.exists(path):
+        d = json.load(open(path))
+        if d.get("kernel_sha") == kernel_sha():
+            traffic = {k: round((v["fetch_kib_per_dispatch"] * d["fetch_factor"] +
+                                 v["write_kib_per_dispatch"] * d["write_factor"]) * 1024.0, 0)
+                       for k, v in d.get("variants", {}).items()}
     for name, scheme in variants:
         p = _with_monitor(p0, 0)
         p.scheme = scheme
@@ -194,7 +203,9 @@ def measure_variants(lbm, inputs, steps=100):
         t = lat.step_timed(steps) / 1e3 / steps
         lat.close()
         out["kernel_us"][name] = round(t * 1e6, 2)
+        out["mlups"][name] = round(fluid / t / 1e6, 1)
         out["achieved_gbs"][name] = round(fluid * 72.0 / t / 1e9, 1)
+        out["hbm_bytes"][name] = traffic.get(name)
     return out
 
 
@@ -437,6 +448,10 @@ def main():
         return
     if args.workload == "batch256_residual":
         print(json.dumps(measure_batch_residual(lbm, inputs)), flush=True)
+        return
+    if args.workload == "variants":
+        print(json.dumps({"workload": "variants", "aux": [measure_variants(lbm, inputs, steps=args.steps)]}),
+              flush=True)
         return
     if args.workload == "d3q19":
         print(json.dumps({"workload": "d3q19", "aux": [measure_d3q19(lbm, inputs, steps=args.steps)]}), flush=True)

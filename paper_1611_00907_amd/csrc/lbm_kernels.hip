@@ -1422,30 +1422,40 @@ hipError_t step_launch(const LatticeArgs& A, const void* fin, void* fout, const 
 }
 
 // The variants of the step (force of Eq 5, TRT / MRT collision): 64 x 16 tiles,
-// FP64 and FP32 storage.
+// FP64 and FP32 storage, with the non-temporal stores of the plain step where it
+// takes them (so that the variants compare like with like).
+template <typename ST, int EOS, int MODE, bool NTS>
+hipError_t step_scheme_nt(const LatticeArgs& A, const void* fin, void* fout, const void* mu_w, double* out,
+                          hipStream_t s) {
+    static_assert(SCHEME_TILE_Y == 16, "the variants are instantiated for 64 x 16 tiles");
+    switch (A.scheme) {
+    case FORCE_CP | COLLIDE_TRT:
+        return step_launch<ST, EOS, MODE, 16, 64, 4, false, FORCE_CP, COLLIDE_TRT, NTS>(A, fin, fout, mu_w, out, s);
+    case FORCE_CP | COLLIDE_MRT:
+        return step_launch<ST, EOS, MODE, 16, 64, 4, false, FORCE_CP, COLLIDE_MRT, NTS>(A, fin, fout, mu_w, out, s);
+    case FORCE_PTENSOR | COLLIDE_BGK:
+        return step_launch<ST, EOS, MODE, 16, 64, 4, false, FORCE_PTENSOR, COLLIDE_BGK, NTS>(A, fin, fout, mu_w, out,
+                                                                                             s);
+    case FORCE_PTENSOR | COLLIDE_TRT:
+        return step_launch<ST, EOS, MODE, 16, 64, 4, false, FORCE_PTENSOR, COLLIDE_TRT, NTS>(A, fin, fout, mu_w, out,
+                                                                                             s);
+    case FORCE_PTENSOR | COLLIDE_MRT:
+        return step_launch<ST, EOS, MODE, 16, 64, 4, false, FORCE_PTENSOR, COLLIDE_MRT, NTS>(A, fin, fout, mu_w, out,
+                                                                                             s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename ST, int EOS, int MODE>
 hipError_t step_scheme(const LatticeArgs& A, const void* fin, void* fout, const void* mu_w, double* out,
                        hipStream_t s) {
     if constexpr (sizeof(ST) < 4) {
         return hipErrorInvalidValue;
     } else {
-        static_assert(SCHEME_TILE_Y == 16, "the variants are instantiated for 64 x 16 tiles");
-        switch (A.scheme) {
-        case FORCE_CP | COLLIDE_TRT:
-            return step_launch<ST, EOS, MODE, 16, 64, 4, false, FORCE_CP, COLLIDE_TRT>(A, fin, fout, mu_w, out, s);
-        case FORCE_CP | COLLIDE_MRT:
-            return step_launch<ST, EOS, MODE, 16, 64, 4, false, FORCE_CP, COLLIDE_MRT>(A, fin, fout, mu_w, out, s);
-        case FORCE_PTENSOR | COLLIDE_BGK:
-            return step_launch<ST, EOS, MODE, 16, 64, 4, false, FORCE_PTENSOR, COLLIDE_BGK>(A, fin, fout, mu_w, out,
-                                                                                           s);
-        case FORCE_PTENSOR | COLLIDE_TRT:
-            return step_launch<ST, EOS, MODE, 16, 64, 4, false, FORCE_PTENSOR, COLLIDE_TRT>(A, fin, fout, mu_w, out,
-                                                                                           s);
-        case FORCE_PTENSOR | COLLIDE_MRT:
-            return step_launch<ST, EOS, MODE, 16, 64, 4, false, FORCE_PTENSOR, COLLIDE_MRT>(A, fin, fout, mu_w, out,
-                                                                                           s);
-        default: return hipErrorInvalidValue;
+        if constexpr (MODE == MODE_STEP) {
+            if (A.nt_store) return step_scheme_nt<ST, EOS, MODE, true>(A, fin, fout, mu_w, out, s);
         }
+        return step_scheme_nt<ST, EOS, MODE, false>(A, fin, fout, mu_w, out, s);
     }
 }
 
