@@ -419,6 +419,34 @@ lbm_status lbm_contact_angle(const double* rho, int32_t nx, int32_t ny, int32_t 
                              double surface_y, double rho_mid, double* theta_deg, double* L,
                              double* H);
 
+/* ---------------------------------------------------------------- warm-start host helpers
+ * Host-only (no GPU work, callable from several threads at once) pieces of the
+ * learned warm start: the warm field is a circular cap whose angle and bulk levels
+ * are read off the network's predicted phase.  The paper defines none of these; the
+ * cap's geometry is that of the contact-angle measurement of Sec. V. */
+
+/* out[y][x] (host, nx * ny doubles) = (rho_in + rho_out)/2 - (rho_in - rho_out)/2 *
+ * tanh(2 (r - radius) / width), r the distance of node (x, y) from (cx, cy).
+ * LBM_EINVAL for empty sizes, a null pointer, width <= 0 or non-finite values. */
+lbm_status lbm_warm_cap(int32_t nx, int32_t ny, double rho_in, double rho_out, double radius, double cx,
+                        double cy, double width, double* out);
+
+/* Logarithmic phase out[i] = ln(rho[i] / rho_g) / ln(rho_l / rho_g) (rho floored at 1e-300),
+ * and its inverse rho[i] = rho_g exp(phi[i] ln(rho_l / rho_g)); n host values each.
+ * LBM_EINVAL unless 0 < rho_g < rho_l. */
+lbm_status lbm_warm_phase(int64_t n, const double* rho, double rho_g, double rho_l, float* out);
+lbm_status lbm_warm_density(int64_t n, const float* phi, double rho_g, double rho_l, double* out);
+
+/* One pass of the D2Q9-weighted average (4/9 centre, 1/9 axes, 1/36 diagonals) of the
+ * predicted phase clipped to [lo, hi]; x periodic, rows clamped at the edges; host
+ * [ny][nx] floats in and out (not aliased). */
+lbm_status lbm_warm_smooth(int32_t nx, int32_t ny, const float* pred, float lo, float hi, float* out);
+
+/* Liquid and vapour levels of a phase field: the medians of the nodes whose whole
+ * 5 x 5 neighbourhood (periodic in x and y) lies above / below 1/2; 1 and 0 when no
+ * node qualifies. */
+lbm_status lbm_warm_bulk_phases(int32_t nx, int32_t ny, const float* phi, double* ph_l, double* ph_g);
+
 #ifdef __cplusplus
 }
 #endif

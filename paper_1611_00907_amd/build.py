@@ -23,7 +23,7 @@ OBJ = os.path.join(PKG, "_build")
 KERNEL_SOURCE = "lbm_kernels.hip"
 STORAGE = [("double", "f64"), ("float", "f32"), ("__half", "f16dev"), ("__hip_bfloat16", "bf16dev")]
 HOST_SOURCES = ["lbm_dispatch.cpp", "lbm_host.cpp", "lbm_batch.cpp", "thermo_host.cpp", "sur_kernels.hip",
-                "sur_host.cpp", "lbm3d_kernels.hip", "lbm3d_host.cpp"]
+                "sur_host.cpp", "lbm3d_kernels.hip", "lbm3d_host.cpp", "warm_host.cpp"]
 HEADERS = ["lbm_internal.h", "lbm_common.h", "thermo_host.h", "sur_internal.h", "lbm3d_internal.h",
            "lbm_eos_device.h"]
 SOURCES = [KERNEL_SOURCE] + HOST_SOURCES

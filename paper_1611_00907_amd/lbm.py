@@ -43,7 +43,8 @@ EXPORTED = ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lb
             "sur_set_dataset", "sur_train", "sur_trace", "sur_read", "sur_destroy",
             "lbm_get_monitors", "lbm_monitor_step", "lbm_get_state", "lbm_set_state",
             "lbm_get_temperature", "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_critical_point",
-            "lbm_coexistence", "lbm_spinodal", "lbm_eos_eval", "lbm_contact_angle"]
+            "lbm_coexistence", "lbm_spinodal", "lbm_eos_eval", "lbm_contact_angle", "lbm_warm_cap",
+            "lbm_warm_phase", "lbm_warm_density", "lbm_warm_smooth", "lbm_warm_bulk_phases"]
 
 
 class LbmParams(C.Structure):
@@ -167,6 +168,12 @@ def load_library():
     lib.lbm_eos_eval.argtypes = [P, C.c_int64, vp, vp, vp]
     lib.lbm_contact_angle.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                       dp, dp, dp]
+    d = C.c_double
+    lib.lbm_warm_cap.argtypes = [C.c_int32, C.c_int32, d, d, d, d, d, d, vp]
+    lib.lbm_warm_phase.argtypes = [C.c_int64, vp, d, d, vp]
+    lib.lbm_warm_density.argtypes = [C.c_int64, vp, d, d, vp]
+    lib.lbm_warm_smooth.argtypes = [C.c_int32, C.c_int32, vp, C.c_float, C.c_float, vp]
+    lib.lbm_warm_bulk_phases.argtypes = [C.c_int32, C.c_int32, vp, dp, dp]
     for name in EXPORTED:
         if name not in ("lbm_workspace_bytes", "lbm_destroy", "lbm_strerror", "lbm_last_error",
                         "lbm_batch_workspace_bytes", "lbm_batch_fluid_nodes", "lbm_batch_destroy",
@@ -241,6 +248,50 @@ def lbm_contact_angle(rho, rho_mid: float, base_row: int = 1, surface_y=None):
     _check(lib.lbm_contact_angle(_p(rho), nx, ny, int(base_row), sy, float(rho_mid),
                                  *[C.byref(o) for o in out]), "lbm_contact_angle")
     return tuple(o.value for o in out)
+
+
+def warm_cap(nx: int, ny: int, rho_in: float, rho_out: float, radius: float, cx: float, cy: float,
+             width: float = 4.0):
+    """Drop of rho_in in rho_out with a tanh interface (lbm_warm_cap): [ny][nx] doubles."""
+    out = np.empty((ny, nx))
+    _check(load_library().lbm_warm_cap(int(nx), int(ny), float(rho_in), float(rho_out), float(radius), float(cx),
+                                       float(cy), float(width), _p(out)), "lbm_warm_cap")
+    return out
+
+
+def warm_phase(rho, rho_g: float, rho_l: float):
+    """ln(rho / rho_g) / ln(rho_l / rho_g) as float32 (lbm_warm_phase)."""
+    rho = _f64(rho)
+    out = np.empty(rho.shape, np.float32)
+    _check(load_library().lbm_warm_phase(rho.size, _p(rho), float(rho_g), float(rho_l), _p(out)), "lbm_warm_phase")
+    return out
+
+
+def warm_density(phi, rho_g: float, rho_l: float):
+    """rho_g exp(phi ln(rho_l / rho_g)) as float64 (lbm_warm_density)."""
+    phi = np.ascontiguousarray(phi, dtype=np.float32)
+    out = np.empty(phi.shape)
+    _check(load_library().lbm_warm_density(phi.size, _p(phi), float(rho_g), float(rho_l), _p(out)),
+           "lbm_warm_density")
+    return out
+
+
+def warm_smooth(pred, lo: float = -0.5, hi: float = 1.5):
+    """One D2Q9-weighted smoothing pass of pred clipped to [lo, hi] (lbm_warm_smooth), float32."""
+    pred = np.ascontiguousarray(pred, dtype=np.float32)
+    ny, nx = pred.shape
+    out = np.empty_like(pred)
+    _check(load_library().lbm_warm_smooth(nx, ny, _p(pred), float(lo), float(hi), _p(out)), "lbm_warm_smooth")
+    return out
+
+
+def warm_bulk_phases(phi):
+    """(liquid, vapour) phase levels of a phase field (lbm_warm_bulk_phases)."""
+    phi = np.ascontiguousarray(phi, dtype=np.float32)
+    ny, nx = phi.shape
+    hl, hg = C.c_double(), C.c_double()
+    _check(load_library().lbm_warm_bulk_phases(nx, ny, _p(phi), C.byref(hl), C.byref(hg)), "lbm_warm_bulk_phases")
+    return hl.value, hg.value
 
 
 def lbm_copy_bandwidth(nbytes: int, iters: int = 20) -> float:

@@ -214,7 +214,8 @@ def features(spec: CaseSpec):
     x = np.zeros((4, spec.side, spec.side), np.float32)
     x[0, 0, :] = 1.0
     x[0, -1, :] = 1.0
-    x[1] = phase(spec, cap_field(spec, spec.theta0))
+    rg, rl, _, _ = spec.coexistence()
+    x[1] = lbm.warm_phase(cap_field(spec, spec.theta0), rg, rl)
     x[2] = spec.Tr
     x[3] = spec.frac
     return x
@@ -274,39 +275,6 @@ def time_to_angle(specs, rho_starts, theta_eq, tol_deg=0.5, check_every=200, max
     return first_in, (t_full if t_full is not None else 0.0), t_dev
 
 
-def _smooth(a):
-    """One pass of the D2Q9-weighted average (4/9 centre, 1/9 axes, 1/36 diagonals),
-    periodic in x, rows clamped at the edges; in the input's precision."""
-    h, w = a.shape
-    p = np.empty((h + 2, w + 2), a.dtype)
-    p[1:-1, 1:-1] = a
-    p[0, 1:-1], p[-1, 1:-1] = a[0], a[-1]
-    p[:, 0], p[:, -1] = p[:, -2], p[:, 1]
-    c = p[1:-1, 1:-1]
-    ax = (p[:-2, 1:-1] + p[2:, 1:-1]) + (p[1:-1, :-2] + p[1:-1, 2:])
-    dg = (p[:-2, :-2] + p[:-2, 2:]) + (p[2:, :-2] + p[2:, 2:])
-    return a.dtype.type(4 / 9) * c + a.dtype.type(1 / 9) * ax + a.dtype.type(1 / 36) * dg
-
-
-def bulk_phases(phi):
-    """Liquid and vapour phase levels of a phase field: medians of the nodes whose
-    whole 5 x 5 neighbourhood lies on one side of 1/2 (periodic in x)."""
-    hi = phi > 0.5
-    # 5 x 5 erosions of both sides, separably: rows of 5 first, then columns of 5
-    row_hi, row_lo = hi.copy(), ~hi
-    for dx in (-2, -1, 1, 2):
-        s = np.roll(hi, dx, 1)
-        row_hi &= s
-        row_lo &= ~s
-    all_hi, all_lo = row_hi.copy(), row_lo.copy()
-    for dy in (-2, -1, 1, 2):
-        all_hi &= np.roll(row_hi, dy, 0)
-        all_lo &= np.roll(row_lo, dy, 0)
-    lo = float(np.median(phi[all_lo])) if all_lo.any() else 0.0
-    hi_v = float(np.median(phi[all_hi])) if all_hi.any() else 1.0
-    return hi_v, lo
-
-
 def cap_field(spec: CaseSpec, theta_deg, rho_l=None, rho_g=None):
     """Sessile circular cap of contact angle theta on the first fluid row at the
     bulk densities rho_l, rho_g (default: the coexistence values), holding the cold
@@ -328,7 +296,7 @@ def cap_field(spec: CaseSpec, theta_deg, rho_l=None, rho_g=None):
     A = (M - rg * N) / (rl - rg)
     t = np.radians(float(np.clip(theta_deg, 5.0, 175.0)))
     R = np.sqrt(A / (t - np.sin(t) * np.cos(t)))
-    rho = inputs.tanh_drop(spec.side, spec.side, rl, rg, R, spec.side / 2.0, 1.0 - R * np.cos(t))
+    rho = lbm.warm_cap(spec.side, spec.side, rl, rg, R, spec.side / 2.0, 1.0 - R * np.cos(t))
     excess = rho[fl] - rg
     rho[fl] = rg + excess * ((M - rg * N) / excess.sum())
     rho[0] = rho[1]
@@ -339,13 +307,14 @@ def cap_field(spec: CaseSpec, theta_deg, rho_l=None, rho_g=None):
 def read_prediction(spec: CaseSpec, pred):
     """Contact angle and bulk densities of a predicted phase field (clipped to
     [-0.5, 1.5], which keeps the offsets of the equilibrium phases, and smoothed
-    once): the angle by the Sec. V measure, the bulk phases by bulk_phases.  NaN
-    angle if none can be read."""
-    # FP32 (the prediction's own precision): the angle and the bulk levels read off it
-    # change by far less than the prediction's error, at half the host time
-    phi = _smooth(np.clip(np.asarray(pred, np.float32), -0.5, 1.5))
-    theta = measure_angle(density(spec, phi))
-    ph_l, ph_g = bulk_phases(phi)
+    once, in FP32, the prediction's own precision): the angle by the Sec. V measure,
+    the bulk phases as the medians of the nodes whose 5 x 5 neighbourhood lies on one
+    side of 1/2.  NaN angle if none can be read.  The field work runs in the library's
+    host helpers, which leave the interpreter free for other threads."""
+    rg, rl, _, _ = spec.coexistence()
+    phi = lbm.warm_smooth(pred, -0.5, 1.5)
+    theta = measure_angle(lbm.warm_density(phi, rg, rl))
+    ph_l, ph_g = lbm.warm_bulk_phases(phi)
     return theta, float(density(spec, ph_l)), float(density(spec, ph_g))
 
 
@@ -356,7 +325,8 @@ def predicted_field(spec: CaseSpec, pred, rho_g, rho_max):
     """The predicted density field (phase clipped to [-0.5, 1.5], smoothed once,
     densities capped at rho_max) with its excess over rho_g scaled so that the fluid
     rows hold the cold start's mass."""
-    rho = np.minimum(density(spec, _smooth(np.clip(np.asarray(pred, np.float64), -0.5, 1.5))), rho_max)
+    rg0, rl0, _, _ = spec.coexistence()
+    rho = np.minimum(lbm.warm_density(lbm.warm_smooth(pred, -0.5, 1.5), rg0, rl0), rho_max)
     fl = slice(1, spec.side - 1)
     M, N = float(initial_density(spec)[fl].sum()), rho[fl].size
     excess = np.maximum(rho[fl] - rho_g, 0.0)
@@ -425,7 +395,8 @@ def evaluate(net, specs, theta_eq, tol_deg=0.5, check_every=200, max_steps=60000
     cold0 = [initial_density(s) for s in specs]
     steps_cold, dt_cold, dev_cold = time_to_angle(specs, cold0, theta_eq, tol_deg, check_every, max_steps, log=log)
     t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as pool:  # numpy releases the GIL (more threads contend)
+    # the field work runs in library calls that release the interpreter, so threads scale
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as pool:
         x = np.stack(list(pool.map(features, specs)))
         pred = net.forward(x)
         warm0 = list(pool.map(lambda sp: warm_field(sp[0], sp[1], pinned), zip(specs, pred)))

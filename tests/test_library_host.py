@@ -183,3 +183,41 @@ def test_scheme_validation(lbm):
     L = lbm.load_library()
     arr = (lbm.LbmParams * 1)(_params(lbm, scheme=lbm.LBM_COLLIDE_TRT))
     assert L.lbm_batch_workspace_bytes(arr, 1) == 0
+
+
+def test_warm_start_host_helpers_match_their_definitions(lbm):
+    """The warm start's host helpers against the formulas they implement, written out
+    in numpy: tanh cap, logarithmic phase and its inverse, the D2Q9-weighted smoothing
+    (x periodic, rows clamped) and the 5 x 5-eroded bulk medians."""
+    r = np.random.default_rng(3)
+    ny, nx = 37, 52
+    y, x = np.arange(ny)[:, None], np.arange(nx)[None, :]
+    cap = lbm.warm_cap(nx, ny, 2.5, 0.2, 11.3, 20.5, 1.0, 4.0)
+    ref = 1.35 - 1.15 * np.tanh(2.0 * (np.hypot(x - 20.5, y - 1.0) - 11.3) / 4.0)
+    np.testing.assert_allclose(cap, ref, rtol=1e-14, atol=1e-14)
+    rho = r.uniform(0.1, 3.0, (ny, nx))
+    ph = lbm.warm_phase(rho, 0.2, 2.5)
+    np.testing.assert_allclose(ph, np.log(rho / 0.2) / np.log(12.5), rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(lbm.warm_density(ph, 0.2, 2.5), 0.2 * np.exp(ph.astype(np.float64) * np.log(12.5)),
+                               rtol=1e-14)
+    pred = r.uniform(-0.8, 1.8, (ny, nx)).astype(np.float32)
+    c = np.clip(pred.astype(np.float64), -0.5, 1.5)
+    p = np.pad(c, ((1, 1), (0, 0)), mode="edge")
+    p = np.concatenate([p[:, -1:], p, p[:, :1]], axis=1)
+    ax = p[:-2, 1:-1] + p[2:, 1:-1] + p[1:-1, :-2] + p[1:-1, 2:]
+    dg = p[:-2, :-2] + p[:-2, 2:] + p[2:, :-2] + p[2:, 2:]
+    np.testing.assert_allclose(lbm.warm_smooth(pred, -0.5, 1.5), 4 / 9 * c + ax / 9 + dg / 36, atol=2e-6)
+    # bulk medians: a liquid disc at phase 0.9 +- noise in vapour at 0.1 +- noise
+    phi = np.where(np.hypot(x - 26, y - 18) < 10, 0.9, 0.1) + r.uniform(-0.01, 0.01, (ny, nx))
+    phi = phi.astype(np.float32)
+    hi = phi > 0.5
+    ero_hi = np.ones_like(hi)
+    ero_lo = np.ones_like(hi)
+    for dy in range(-2, 3):
+        for dx in range(-2, 3):
+            s = np.roll(np.roll(hi, dy, 0), dx, 1)
+            ero_hi &= s
+            ero_lo &= ~s
+    pl, pg = lbm.warm_bulk_phases(phi)
+    assert abs(pl - np.median(phi[ero_hi])) < 1e-7 and abs(pg - np.median(phi[ero_lo])) < 1e-7
+    assert lbm.warm_bulk_phases(np.full((8, 8), 0.2, np.float32)) == (1.0, pytest.approx(0.2, abs=1e-7))
