@@ -305,8 +305,10 @@ lbm_status lbm_batch_get_state(lbm_batch* b, int32_t i, double* f);
 lbm_status lbm_batch_tune(lbm_batch* b, int32_t trial_steps, int32_t* tile_y,
                           int32_t* blocks_per_cu, double* best_ms);
 
-/* Sets the tile shape (64-wide tiles of height 8, 16 or 32, or the wide shape codes
- * 12816 and 25608: 128 x 16 and 256 x 8 tiles) and the grid of the batched launch directly:
+/* Sets the tile shape (64-wide tiles of height 8, 16 or 32, the wide shape codes
+ * 12816 and 25608: 128 x 16 and 256 x 8 tiles, or 1: a shape per size class, 64 x 32
+ * tiles for cases narrower than 256 columns and 256 x 8 for the others, in the same
+ * launch) and the grid of the batched launch directly:
  * blocks_per_cu = k > 0 workgroups per compute unit, 0 as many as fit, -1 one
  * workgroup per (case, tile) entry (the schedule of a new batch, with tile height
  * 16).  LBM_EINVAL for other values.  Every schedule computes the same step. */

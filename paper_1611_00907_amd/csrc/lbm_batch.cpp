@@ -131,7 +131,7 @@ lbm_status upload_tiles(lbm_batch* b) {
     for (int i = 0; i < b->n; ++i) {
         begin[i] = (int)tiles.size();
         if (b->state[i] != 0) continue;
-        const int nt = tiles_for(b->p[i], b->tile_y);
+        const int nt = tiles_for(b->p[i], batch_case_code(b->tile_y, b->p[i].nx));
         for (int t = 0; t < nt; ++t) tiles.push_back(make_int2(i, t));
     }
     begin[b->n] = (int)tiles.size();
@@ -148,7 +148,7 @@ lbm_status upload_tiles(lbm_batch* b) {
 }
 
 lbm_status upload_desc(lbm_batch* b) {
-    for (int i = 0; i < b->n; ++i) b->desc[i].A.tile_y = b->tile_y;
+    for (int i = 0; i < b->n; ++i) b->desc[i].A.tile_y = batch_case_code(b->tile_y, b->p[i].nx);
     HIP_TRY(hipMemcpyAsync(b->d_cases, b->desc.data(), b->n * sizeof(CaseDesc), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     return LBM_OK;
@@ -486,10 +486,11 @@ lbm_status lbm_batch_tune(lbm_batch* b, int32_t trial_steps, int32_t* tile_y, in
     HIP_TRY(hipEventCreate(&ev.a));
     HIP_TRY(hipEventCreate(&ev.b));
     hipEvent_t e0 = ev.a, e1 = ev.b;
-    constexpr int NCODES = int(std::size(TILE_Y_CHOICES) + std::size(BATCH_WIDE_CODES));
+    constexpr int NCODES = int(std::size(TILE_Y_CHOICES) + std::size(BATCH_WIDE_CODES)) + 1;
     int codes[NCODES], nc = 0;
     for (int ty : TILE_Y_CHOICES) codes[nc++] = ty;
     for (int code : BATCH_WIDE_CODES) codes[nc++] = code;
+    codes[nc++] = BATCH_MIXED;
     for (int ty : codes) {
         for (int bpc : {0, 1, 2, 4, -1}) {
             lbm_status st = set_schedule(b, ty, bpc);
@@ -526,6 +527,7 @@ lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t tile_y, int32_t blocks_p
     bool ok = false;
     for (int ty : TILE_Y_CHOICES) ok = ok || ty == tile_y;
     for (int code : BATCH_WIDE_CODES) ok = ok || code == tile_y;
+    ok = ok || tile_y == BATCH_MIXED;
     if (!ok) return LBM_EINVAL;
     if (hipSetDevice(b->device) != hipSuccess) return LBM_EHIP;
     return set_schedule(b, tile_y, blocks_per_cu);

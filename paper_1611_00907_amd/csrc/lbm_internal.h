@@ -26,6 +26,13 @@ constexpr int WIDE_TILE_CODES[4] = {12816, 12832, 25608, 25616};
 // Batches take the 64-wide heights of TILE_Y_CHOICES and these wide shape codes
 // (128 x 16 and 256 x 8, 4 rows per thread, 512 threads).
 constexpr int BATCH_WIDE_CODES[2] = {12816, 25608};
+// Batch schedule with a tile shape per size class, in one launch: cases narrower than
+// BATCH_MIXED_WIDE columns take 64 x 32 tiles, the others 256 x 8 (both 512 threads).
+constexpr int BATCH_MIXED = 1;
+constexpr int BATCH_MIXED_WIDE = 256;
+constexpr int batch_case_code(int schedule_code, int nx) {
+    return schedule_code != BATCH_MIXED ? schedule_code : (nx < BATCH_MIXED_WIDE ? 32 : 25608);
+}
 // Columns and rows of a tile with shape code `code` (a 64-wide height or 100 * width + height).
 constexpr int tile_tx(int code) { return code >= 10000 ? code / 100 : TILE_X; }
 constexpr int tile_ty(int code) { return code >= 10000 ? code % 100 : code; }

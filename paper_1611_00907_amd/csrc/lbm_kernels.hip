@@ -744,6 +744,76 @@ __global__ __launch_bounds__(TX * TY / RPT) void step_kernel(LatticeArgs A, cons
                                                               (t / tiles_x) * TY, L);
 }
 
+// The mixed schedule: a case narrower than BATCH_MIXED_WIDE columns runs 64 x 32 tiles,
+// a wider one 256 x 8 tiles (the shape codes its descriptor carries); both shapes have
+// 512 threads of 4 rows, so one launch takes both, with the LDS of the larger.
+template <typename ST, bool NTS>
+__global__ __launch_bounds__(512) void batch_step_mixed_kernel(const CaseDesc* __restrict__ cases,
+                                                               const int2* __restrict__ tiles, int ntiles,
+                                                               int parity) {
+    using CT = typename Codec<ST>::CT;
+    __shared__ union {
+        TileLds<CT, 32, 64> small;
+        TileLds<CT, 8, 256> wide;
+    } L;
+    const int chunk = tile_of_block(blockIdx.x, gridDim.x);
+    const int begin = int((long long)ntiles * chunk / gridDim.x);
+    const int end = int((long long)ntiles * (chunk + 1) / gridDim.x);
+    constexpr int R = ROWS_PER_THREAD;
+    constexpr int F = FORCE_CP, B = COLLIDE_BGK;
+    for (int t = begin; t < end; ++t) {
+        const int2 w = tiles[t];
+        const CaseDesc& C = cases[w.x];
+        const ST* fin = in_global(static_cast<const ST*>(C.f[parity]));
+        ST* fout = in_global(static_cast<ST*>(C.f[parity ^ 1]));
+        const CT* mw = in_global(static_cast<const CT*>(C.mu_w));
+        if (C.A.tile_y == 32) {  // workgroup-uniform
+            const int tiles_x = (C.A.nx + 63) / 64;
+            const int x0 = (w.y % tiles_x) * 64, y0 = (w.y / tiles_x) * 32;
+            switch (C.eos) {
+            case EOS_VDW:
+                step_tile<ST, EOS_VDW, MODE_STEP, 32, 64, R, false, F, B, NTS>(C.A, fin, fout, mw, nullptr, x0, y0,
+                                                                              L.small);
+                break;
+            case EOS_CS:
+                step_tile<ST, EOS_CS, MODE_STEP, 32, 64, R, false, F, B, NTS>(C.A, fin, fout, mw, nullptr, x0, y0,
+                                                                             L.small);
+                break;
+            case EOS_PR:
+                step_tile<ST, EOS_PR, MODE_STEP, 32, 64, R, false, F, B, NTS>(C.A, fin, fout, mw, nullptr, x0, y0,
+                                                                             L.small);
+                break;
+            default:
+                step_tile<ST, EOS_RK, MODE_STEP, 32, 64, R, false, F, B, NTS>(C.A, fin, fout, mw, nullptr, x0, y0,
+                                                                             L.small);
+                break;
+            }
+        } else {
+            const int tiles_x = (C.A.nx + 255) / 256;
+            const int x0 = (w.y % tiles_x) * 256, y0 = (w.y / tiles_x) * 8;
+            switch (C.eos) {
+            case EOS_VDW:
+                step_tile<ST, EOS_VDW, MODE_STEP, 8, 256, R, false, F, B, NTS>(C.A, fin, fout, mw, nullptr, x0, y0,
+                                                                              L.wide);
+                break;
+            case EOS_CS:
+                step_tile<ST, EOS_CS, MODE_STEP, 8, 256, R, false, F, B, NTS>(C.A, fin, fout, mw, nullptr, x0, y0,
+                                                                             L.wide);
+                break;
+            case EOS_PR:
+                step_tile<ST, EOS_PR, MODE_STEP, 8, 256, R, false, F, B, NTS>(C.A, fin, fout, mw, nullptr, x0, y0,
+                                                                             L.wide);
+                break;
+            default:
+                step_tile<ST, EOS_RK, MODE_STEP, 8, 256, R, false, F, B, NTS>(C.A, fin, fout, mw, nullptr, x0, y0,
+                                                                             L.wide);
+                break;
+            }
+        }
+        __syncthreads();  // the next tile reuses the LDS
+    }
+}
+
 // Many lattices in one persistent launch: each workgroup walks a contiguous range
 // of the (case, tile) list; the ranges of the workgroups on one XCD are adjacent.
 template <typename ST, int TY, int TX = TILE_X, bool NTS = false>
@@ -1257,7 +1327,8 @@ __global__ __launch_bounds__(64) void monitor_reduce(const double* __restrict__ 
 
 // Monitors of many lattices: one workgroup per (case, tile); per-tile partials, then
 // one workgroup per case reduces its contiguous tile range in a fixed order.
-template <typename ST, int COMPARE, int TY, int TX = TILE_X>
+// TY == 0: each case's own tile shape, from its shape code (the mixed schedule).
+template <typename ST, int COMPARE, int TY_, int TX_ = TILE_X>
 __global__ __launch_bounds__(MON_THREADS) void batch_monitor_kernel(const CaseDesc* __restrict__ cases,
                                                                     const int2* __restrict__ tiles, int parity,
                                                                     double* __restrict__ partials) {
@@ -1265,6 +1336,7 @@ __global__ __launch_bounds__(MON_THREADS) void batch_monitor_kernel(const CaseDe
     const int2 w = tiles[blockIdx.x];
     const CaseDesc& C = cases[w.x];
     const LatticeArgs& A = C.A;
+    const int TY = TY_ ? TY_ : tile_ty(A.tile_y), TX = TY_ ? TX_ : tile_tx(A.tile_y);
     Planes<ST> F;
     const ST* fin = in_global(static_cast<const ST*>(C.f[parity]));
 #pragma unroll
@@ -1567,6 +1639,14 @@ hipError_t batch_step_prec(int code, int nt, const CaseDesc* cases, const int2* 
                            int grid, hipStream_t s) {
     (void)hipGetLastError();
     switch (code) {
+    case BATCH_MIXED:
+        if (nt)
+            hipLaunchKernelGGL((batch_step_mixed_kernel<ST, true>), dim3(grid), dim3(512), 0, s, cases, tiles, ntiles,
+                               parity);
+        else
+            hipLaunchKernelGGL((batch_step_mixed_kernel<ST, false>), dim3(grid), dim3(512), 0, s, cases, tiles, ntiles,
+                               parity);
+        break;
     case 8: batch_step_one<ST, 8, 64>(grid, nt, cases, tiles, ntiles, parity, s); break;
     case 16: batch_step_one<ST, 16, 64>(grid, nt, cases, tiles, ntiles, parity, s); break;
     case 32: batch_step_one<ST, 32, 64>(grid, nt, cases, tiles, ntiles, parity, s); break;
@@ -1588,6 +1668,7 @@ template <typename ST, int COMPARE>
 hipError_t batch_monitor_ty(int code, const CaseDesc* cases, const int2* tiles, int ntiles, int parity,
                             double* partials, hipStream_t s) {
     switch (code) {
+    case BATCH_MIXED: batch_monitor_one<ST, COMPARE, 0, 0>(ntiles, cases, tiles, parity, partials, s); break;
     case 8: batch_monitor_one<ST, COMPARE, 8, 64>(ntiles, cases, tiles, parity, partials, s); break;
     case 16: batch_monitor_one<ST, COMPARE, 16, 64>(ntiles, cases, tiles, parity, partials, s); break;
     case 32: batch_monitor_one<ST, COMPARE, 32, 64>(ntiles, cases, tiles, parity, partials, s); break;
@@ -1614,9 +1695,10 @@ hipError_t batch_monitor_prec(int compare, int tile_y, const CaseDesc* cases, co
 template <typename ST>
 int batch_occupancy(int code) {
     int n = 0;
-    const int threads = tile_tx(code) * tile_ty(code) / ROWS_PER_THREAD;
+    const int threads = code == BATCH_MIXED ? 512 : tile_tx(code) * tile_ty(code) / ROWS_PER_THREAD;
     const void* k = nullptr;
     switch (code) {
+    case BATCH_MIXED: k = (const void*)batch_step_mixed_kernel<ST, false>; break;
     case 8: k = (const void*)batch_step_kernel<ST, 8, 64>; break;
     case 16: k = (const void*)batch_step_kernel<ST, 16, 64>; break;
     case 32: k = (const void*)batch_step_kernel<ST, 32, 64>; break;

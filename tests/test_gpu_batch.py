@@ -108,6 +108,31 @@ def test_batch_wide_tiles_agree(code, bpc):
         assert abs(st["mass"][i] - rho.sum()) < 1e-9 * rho.sum(), i
 
 
+@pytest.mark.parametrize("bpc", [-1, 0])
+def test_batch_mixed_shapes_agree(bpc):
+    """The schedule with a tile shape per size class (code 1: 64 x 32 tiles below 256
+    columns, 256 x 8 from there) gives each case the single run's FP32 result with its
+    class's shape bit for bit, and the monitors (which decode each case's shape) the
+    same mass."""
+    wide = Case(300, 260, thermo.PR, 0.8, 1.3, omega=0.344, bottom=CPWALL, top=NEUTRAL, drop="sessile",
+                radius=70.0, noise=1e-4, seed=61)
+    wide.mu_w_bottom = wide.coexistence()[3] - 0.03
+    cases = _cases(3) + [wide]
+    b = _batch(cases, lbm.LBM_F32)
+    b.set_schedule(1, bpc)
+    b.run(40, check_every=20, window=1, tol=0.0)
+    st = b.status()
+    for i, c in enumerate(cases):
+        lat = _single(c, lbm.LBM_F32, tile_y=32 if c.nx < 256 else 25608)
+        lat.step(40)
+        f, _ = lat.get_state()
+        assert np.array_equal(b.get_state(i), f), "case %d" % i
+        rho = lat.fields()["rho"][1:-1]
+        assert abs(st["mass"][i] - rho.sum()) < 1e-9 * rho.sum(), i
+        lat.close()
+    b.close()
+
+
 def test_batch_schedule_rejects_bad_values():
     b = _batch(_cases(1), lbm.LBM_F32)
     for ty, bpc in ((12, 0), (16, -2), (16, 65)):
@@ -227,12 +252,13 @@ def test_batch_tune_keeps_state_and_results():
     b.step(20)
     before = [b.get_state(i) for i in range(3)]
     ty, bpc, ms = b.tune(trial_steps=5)
-    assert ty in (8, 16, 32, 12816, 25608) and ms > 0
+    assert ty in (1, 8, 16, 32, 12816, 25608) and ms > 0
     for i in range(3):
         assert np.array_equal(b.get_state(i), before[i])
     b.step(30)
     for i, c in enumerate(cases):
-        lat = _single(c, lbm.LBM_F32, tile_y=ty)
+        # the mixed schedule (1) runs 64 x 32 tiles below 256 columns, 256 x 8 from there
+        lat = _single(c, lbm.LBM_F32, tile_y=ty if ty != 1 else (32 if c.nx < 256 else 25608))
         lat.step(50)
         f, _ = lat.get_state()
         assert np.array_equal(b.get_state(i), f)
