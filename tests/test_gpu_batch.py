@@ -133,6 +133,35 @@ def test_batch_mixed_shapes_agree(bpc):
     b.close()
 
 
+def test_batch_stop_masks_the_listed_cases():
+    """lbm_batch_stop: the listed cases keep their state and step count while the
+    others advance (and still equal their single runs); a stopped case stays stopped;
+    indices outside the batch are rejected."""
+    cases = _cases(4)
+    b = _batch(cases, lbm.LBM_F32)
+    b.step(20)
+    held = {i: b.get_state(i) for i in (1, 3)}
+    b.stop([1, 3])
+    b.stop([3])
+    b.step(30)
+    st = b.status()
+    assert list(st["state"]) == [0, 3, 0, 3]
+    assert list(st["steps"]) == [50, 20, 50, 20]
+    for i, c in enumerate(cases):
+        if i in held:
+            assert np.array_equal(b.get_state(i), held[i]), i
+        else:
+            lat = _single(c, lbm.LBM_F32)
+            lat.step(50)
+            f, _ = lat.get_state()
+            lat.close()
+            assert np.array_equal(b.get_state(i), f), i
+    for bad in ([4], [-1]):
+        with pytest.raises(Exception):
+            b.stop(bad)
+    b.close()
+
+
 def test_batch_schedule_rejects_bad_values():
     b = _batch(_cases(1), lbm.LBM_F32)
     for ty, bpc in ((12, 0), (16, -2), (16, 65)):
