@@ -220,7 +220,7 @@ def measure_d3q19(lbm, inputs, n=256, steps=50):
     t = lat.step_timed(steps) / 1e3 / steps
     lat.close()
     nodes = n ** 3
-    return {"workload": "D3Q19 spinodal %d^3 periodic VdW Tr=0.85, f32 storage (density pass + fused step pass)" % n,
+    return {"workload": "D3Q19 spinodal %d^3 periodic VdW Tr=0.85, f32 storage (one-pass marching step)" % n,
             "mlups": round(nodes / t / 1e6, 1), "ms_per_step": round(t * 1e3, 4),
             "roofline": {"bound": "hbm", "achieved": round(nodes * 152.0 / t / 1e9, 1), "peak": PEAK_HBM_GBS,
                          "unit": "GB/s", "frac": round(nodes * 152.0 / t / 1e9 / PEAK_HBM_GBS, 4),
@@ -228,7 +228,7 @@ def measure_d3q19(lbm, inputs, n=256, steps=50):
 
 
 def traffic3_for(workload: str):
-    """HBM bytes per D3Q19 step (density pass plus step pass) from committed rocprofv3
+    """HBM bytes per D3Q19 step (one launch of the marching kernel) from committed rocprofv3
     FETCH_SIZE / WRITE_SIZE counts, scaled as for the 2-D step, if they were taken on
     the current 3-D kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)

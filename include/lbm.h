@@ -230,13 +230,17 @@ const char* lbm_last_error(void);
 typedef struct lbm3d lbm3d;
 
 /* p gives nx, ny, the EOS, Tr, tau, kappa and the storage (LBM_F64 or LBM_F32);
- * both boundaries must be LBM_BC_PERIODIC and scheme 0; nz >= 1; nx ny nz < 2^31.
+ * both boundaries must be LBM_BC_PERIODIC and scheme 0; nz >= 1; nx ny nz < 2^31,
+ * and one z slice of one direction (ny x nx rounded up to 64, times the storage
+ * size) below 4 GiB.
  * The fluid starts at rest, f = f_eq(rho0, 0).  The library allocates the device
- * memory (two 19-plane buffers and one density plane) and its own stream.
+ * memory (two 19-plane buffers and one density plane, the latter used by
+ * lbm3d_get_fields) and its own stream.
  * Errors: LBM_EINVAL, LBM_EDOMAIN (rho0 outside the EOS domain), LBM_ENOMEM, LBM_EHIP. */
 lbm_status lbm3d_init(const lbm_params* p, int32_t nz, const double* rho0, lbm3d** out);
-/* n steps; each is two launches (a density pass, then the fused chemical
- * potential, force, collision and streaming pass).  Asynchronous. */
+/* n steps; each is one launch that pulls every node once and fuses the density,
+ * the chemical potential of Eq 8, the force of Eq 12, the collision and the
+ * streaming.  Asynchronous. */
 lbm_status lbm3d_step(lbm3d* c, int64_t n);
 /* lbm3d_step between HIP events on the box's stream; *ms is the device time. */
 lbm_status lbm3d_step_timed(lbm3d* c, int64_t n, double* ms);

@@ -36,8 +36,10 @@ lbm_status validate3(const lbm_params* p, int32_t nz) {
     if (p->prec != LBM_F64 && p->prec != LBM_F32) return LBM_EINVAL;
     if (p->scheme != 0) return LBM_EINVAL;
     const long long pitch = ((long long)p->nx + 63) / 64 * 64;
-    // node indices and plane offsets are 32-bit
+    // node indices and plane offsets are 32-bit, and so are the byte offsets in one
+    // z slice of one direction
     if ((long long)p->nx * p->ny * nz >= (1LL << 31) || pitch * p->ny * nz >= (1LL << 31)) return LBM_EINVAL;
+    if (pitch * p->ny * (p->prec == LBM_F64 ? 8 : 4) >= (1LL << 32)) return LBM_EINVAL;
     return LBM_OK;
 }
 

@@ -1,6 +1,7 @@
 """GPU: the D3Q19 step against the D3Q19 oracle, element by element (FP64 within
 1e-10 of the largest distribution, FP32 within 2e-5), on boxes that are ragged
-against the 64 x 4 x 4 blocks of the step pass, for every EOS, and on tiny boxes."""
+against the 64 x 8 columns and the runs of planes of the marching step, for every
+EOS, on tiny boxes, and at the benchmark's 256^3 in the launch it times."""
 import numpy as np
 import pytest
 
@@ -95,3 +96,18 @@ def test_d3q19_rejects_walls_and_16bit():
     p = lbm.make_params(16, 8, 0, 9 / 49, 2 / 21, 0.85, 1.0, 0.01, bc_bottom=1, bc_top=2)
     with pytest.raises(lbm.LbmError):
         lbm.Lattice3(p, 4, np.full((4, 8, 16), 3.0))
+
+
+@pytest.mark.parametrize("n,steps", [(128, 3), (256, 2)])
+def test_d3q19_spinodal_f32_full_size(n, steps):
+    """The benchmark's spinodal box (VdW, Tr 0.85, rho = 2.6 (1 + 0.01 U)) in FP32:
+    at 128^3 (non-temporal stores, 16 runs of 8 planes) and at 256^3 (4 runs of 64
+    planes, the launch the benchmark times), every distribution against the oracle."""
+    rho0 = inputs.with_relative_noise(np.full((n, n, n), 2.6), 0.01, 3)
+    p3 = Params3.from_reduced(n, n, n, thermo.VDW, 9 / 49, 2 / 21, 0.85, 1.0, 0.01)
+    ora = Oracle3(p3, rho0)
+    lat = lbm.Lattice3(lbm.make_params(n, n, 0, 9 / 49, 2 / 21, 0.85, 1.0, 0.01, prec=lbm.LBM_F32), n, rho0)
+    lat.step(steps)
+    ora.step(steps)
+    assert _err(lat, ora) < 2e-5
+    lat.close()
