@@ -218,24 +218,64 @@ __device__ __forceinline__ CT node_rho(const LatticeArgs& A, const Planes<ST>& F
 }
 
 // ---------------------------------------------------------------- thermodynamics
+// FP64 reciprocal and logarithm for psi' inside the spinodal band of the 16-bit
+// storage types, whose result is rounded to FP32: far cheaper than the correctly
+// rounded division and the library logarithm, and accurate to about 1e-13.
+//   rcp_band: the hardware reciprocal estimate and two Newton steps y += y (1 - x y).
+//   log_band: x = m 2^e with m in [sqrt(1/2), sqrt 2), then
+//             ln x = e ln 2 + 2 artanh s = e ln 2 + 2 s (1 + s^2/3 + ... + s^12/13),
+//             s = (m - 1) / (m + 1) (the Taylor series of artanh; |s| <= 0.1716, so the
+//             terms left out are below 2e-12 of the sum).
+__device__ __forceinline__ double rcp_band(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
+__device__ __forceinline__ double log_band(double x) {
+    double m = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1)
+    int e = __builtin_amdgcn_frexp_exp(x);
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) * rcp_band(m + 1.0), t = s * s;
+    double p = 1.0 / 13.0;
+    p = fma(p, t, 1.0 / 11.0);
+    p = fma(p, t, 1.0 / 9.0);
+    p = fma(p, t, 1.0 / 7.0);
+    p = fma(p, t, 1.0 / 5.0);
+    p = fma(p, t, 1.0 / 3.0);
+    p = fma(p, t, 1.0);
+    return fma(double(e), 0.69314718055994530942, 2.0 * s * p);
+}
+
 // Bulk chemical potential psi'(rho): Eq 18 (VdW), Eq 27 (CS), Eq 24 (PR), Eq 21 (RK, RKS).
-template <int EOS, typename CT>
+// BAND: FP64 with rcp_band and log_band (the spinodal band of 16-bit storage).
+template <int EOS, typename CT, bool BAND = false>
 __device__ __forceinline__ CT mu_bulk(const EosConst& E, CT rho) {
     const CT RT = CT(E.RT), a = CT(E.a), b = CT(E.b), c1 = CT(E.c1);
+    const auto L = [](CT v) {
+        if constexpr (BAND) return log_band(v);
+        else return lg(v);
+    };
+    const auto Q = [](CT v) {
+        if constexpr (BAND) return rcp_band(v);
+        else return rcp(v);
+    };
     if constexpr (EOS == EOS_CS) {
         const CT q = c1 * rho, om = CT(1) - q;
-        return RT * ((CT(3) - q) * rcp(om * om * om) + lg(rho) + CT(1)) - CT(2) * a * rho;
+        return RT * ((CT(3) - q) * Q(om * om * om) + L(rho) + CT(1)) - CT(2) * a * rho;
     } else {
-        const CT br = b * rho, ib = rcp(CT(1) - br);
-        const CT rep = RT * (lg(rho * ib) + ib);
+        const CT br = b * rho, ib = Q(CT(1) - br);
+        const CT rep = RT * (L(rho * ib) + ib);
         if constexpr (EOS == EOS_VDW) {
             return rep - CT(2) * a * rho;
         } else if constexpr (EOS == EOS_PR) {
             const CT s2 = CT(1.4142135623730950488);
-            return rep - c1 * lg((s2 - CT(1) + br) * rcp(s2 + CT(1) - br)) -
-                   a * rho * rcp(CT(1) + CT(2) * br - br * br);
+            return rep - c1 * L((s2 - CT(1) + br) * Q(s2 + CT(1) - br)) - a * rho * Q(CT(1) + CT(2) * br - br * br);
         } else {  // RK, RKS
-            return rep - c1 * lg(CT(1) + br) - a * rho * rcp(CT(1) + br);
+            return rep - c1 * L(CT(1) + br) - a * rho * Q(CT(1) + br);
         }
     }
 }
@@ -246,7 +286,7 @@ template <int EOS, typename ST>
 __device__ __forceinline__ typename Codec<ST>::CT mu_node(const LatticeArgs& A, typename Codec<ST>::CT rho) {
     using CT = typename Codec<ST>::CT;
     if constexpr (sizeof(ST) == 2) {
-        if (rho > CT(A.sp_lo) && rho < CT(A.sp_hi)) return CT(mu_bulk<EOS, double>(A.eos, double(rho)));
+        if (rho > CT(A.sp_lo) && rho < CT(A.sp_hi)) return CT(mu_bulk<EOS, double, true>(A.eos, double(rho)));
     }
     return mu_bulk<EOS, CT>(A.eos, rho);
 }
