@@ -102,14 +102,18 @@ class _FakeLbm:
 @pytest.mark.parametrize("steps,warmup", [(20, 5), (1000, 100), (7, 0)])
 def test_measure_times_exactly_the_requested_steps(steps, warmup):
     """The whole-step interval covers exactly --steps steps with monitors every
-    min(100, steps) steps; the kernel interval has no monitors; warm-up runs on every
-    lattice before its timed interval."""
+    min(100, steps) steps and comes right after the kernel interval (no monitors,
+    max(steps, 1000) steps); warm-up runs on every lattice before its timed interval
+    (a zero-step timed call only waits for the warm-up)."""
     _FakeLattice.log = []
     p = lbm.make_params(64, 64, lbm.LBM_EOS_VDW, 9 / 49, 2 / 21, 0.85, 1.0, 0.01)
     res = bench.measure(_FakeLbm, p, None, None, 4096 * 4096, steps, warmup, 72.0, "no_such_workload")
-    timed = [e for e in _FakeLattice.log if e[0] == "timed"]
+    timed = [e for e in _FakeLattice.log if e[0] == "timed" and e[1] > 0]
+    assert len(timed) == 2
     assert timed[-1] == ("timed", steps, min(100, steps))
-    assert timed[0][2] == 0 and timed[0][1] == max(steps, 100)
+    assert timed[0][2] == 0 and timed[0][1] == max(steps, 1000)
+    i_k, i_w = (i for i, e in enumerate(_FakeLattice.log) if e in timed)
+    assert i_w == i_k + 1
     assert res["steps"] == steps and res["monitor_every"] == min(100, steps)
     assert res["ms_per_step"] == pytest.approx(0.25)
     assert res["kernel_us"] == pytest.approx(250.0)
