@@ -260,6 +260,47 @@ def surrogate_step_flops(lbm, size, batch):
     return batch * (3.0 * fwd - first)
 
 
+def surrogate_step_floor(lbm, size, batch):
+    """Roofline floor of one training step of the surrogate: every pass costs at
+    least max(bytes / 8 TB/s, flops / 2.5 PFLOP/s).  Bytes are the pass's own
+    operands, BF16 (2 B per channel and pixel) unless stated: a convolution's forward
+    pass reads its input and writes its output (the one-channel output in FP32), its
+    input gradient reads the output gradient and the ReLU mask (the input) and writes
+    the input gradient, its weight gradient reads the input and the output gradient;
+    each pooling reads its input and writes a quarter of it, each upsampling the
+    reverse; the pooling gradient with the skip share reads three maps and the
+    pooled gradient and writes one, the upsampling gradient reads one map and writes
+    a quarter of it twice over; the loss reads the prediction and target (FP32) and
+    writes the output gradient.  Returns (seconds, bytes)."""
+    lv = {"0": 0, "1": 1, "2": 2, "3": 3, "u": 0}
+    bw, pk = PEAK_HBM_GBS * 1e9, PEAK_BF16_TFLOPS * 1e12
+    t = nbytes = 0.0
+
+    def add(b, f=0.0):
+        nonlocal t, nbytes
+        t += max(b / bw, f / pk)
+        nbytes += b
+
+    first = lbm.Surrogate.LAYERS[0][0]
+    for name, ci, co in lbm.Surrogate.LAYERS:
+        px = batch * (size >> lv[name[1]]) ** 2
+        f = 2.0 * 9 * ci * co * px
+        add(px * (2 * ci + (4 if co == 1 else 2) * co), f)     # forward
+        if name != first:
+            add(px * (2 * co + 4 * ci), f)                       # input gradient
+        add(px * 2 * (ci + co), f)                               # weight gradient
+    for level, c in ((0, 32), (1, 64), (2, 96)):                 # pooling, skip gradient
+        px = batch * (size >> level) ** 2
+        add(px * c * 2 + px // 4 * c * 2)
+        add(px * c * 2 * 3 + px // 4 * c * 2)
+    for level, c in ((2, 128), (1, 96), (0, 64)):                # upsampling and its gradient
+        px = batch * (size >> level) ** 2
+        add(px // 4 * c * 2 + px * c * 2)
+        add(px * c * 2 + px // 4 * c * 2 * 2)
+    add(batch * size * size * (4 + 4 + 2))                       # loss
+    return t, nbytes
+
+
 def measure_surrogate(lbm, size=256, batch=16, steps=40):
     """Training steps of the surrogate (BF16 MFMA convolutions, FP32 accumulation)
     on a device-resident synthetic dataset, timed on the host around sur_train."""
@@ -276,12 +317,16 @@ def measure_surrogate(lbm, size=256, batch=16, steps=40):
     net.train(steps, batch, 1e-4, seed=2)
     dt = (time.perf_counter() - t0) / steps
     flops = surrogate_step_flops(lbm, size, batch)
+    floor_s, floor_bytes = surrogate_step_floor(lbm, size, batch)
     tf = flops / dt / 1e12
     return {"workload": "surrogate training step: batch %d at %d^2, 4-level U-Net (32-128 channels), BF16 MFMA "
                         "convolutions with FP32 accumulation, Adam" % (batch, size),
             "ms_per_step": round(dt * 1e3, 3), "gflop_per_step": round(flops / 1e9, 1),
             "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                         "frac": round(tf / PEAK_BF16_TFLOPS, 5), "traffic": None}}
+                         "frac": round(tf / PEAK_BF16_TFLOPS, 5), "traffic": None},
+            # per pass max(bytes at the HBM peak, flops at the BF16 peak), summed
+            "step_floor": {"ms": round(floor_s * 1e3, 4), "bytes": round(floor_bytes, 0),
+                           "frac": round(floor_s / dt, 4)}}
 
 
 def traffic_for(workload: str, shape: int):

@@ -122,3 +122,42 @@ def test_measure_times_exactly_the_requested_steps(steps, warmup):
     for i, e in enumerate(_FakeLattice.log):
         if e[0] == "timed":
             assert ("step", warmup) in _FakeLattice.log[:i]
+
+
+def test_surrogate_step_floor_by_hand():
+    """The step floor at a small size, pass by pass written out: 2-D maps of
+    side s >> level, BF16 operands, each pass at max(bytes / 8 TB/s, flops / 2.5
+    PFLOP/s); independent of bench.py's layer-name parsing."""
+    size, batch = 32, 2
+    res = {"e0a": 32, "e0b": 32, "e1a": 16, "e1b": 16, "e2a": 8, "e2b": 8, "e3a": 4, "e3b": 4,
+           "d2a": 8, "d2b": 8, "d1a": 16, "d1b": 16, "d0a": 32, "d0b": 32, "out": 32}
+    bw, pk = 8e12, 2.5e15
+    t = b_all = 0.0
+    for name, ci, co in lbm.Surrogate.LAYERS:
+        px = batch * res[name] ** 2
+        f = 18.0 * ci * co * px
+        out_b = 4 * co if name == "out" else 2 * co
+        passes = [px * (2 * ci + out_b), px * 2 * (ci + co)] + ([] if name == "e0a" else [px * (2 * co + 4 * ci)])
+        for b in passes:
+            t += max(b / bw, f / pk)
+            b_all += b
+    for side, c in ((32, 32), (16, 64), (8, 96)):
+        px = batch * side * side
+        for b in (px * c * 2 + px // 4 * c * 2, px * c * 6 + px // 4 * c * 2):
+            t += b / bw
+            b_all += b
+    for side, c in ((8, 128), (16, 96), (32, 64)):
+        px = batch * side * side
+        for b in (px // 4 * c * 2 + px * c * 2, px * c * 2 + px // 4 * c * 4):
+            t += b / bw
+            b_all += b
+    b = batch * 32 * 32 * 10
+    t += b / bw
+    b_all += b
+    got_t, got_b = bench.surrogate_step_floor(lbm, size, batch)
+    assert got_t == pytest.approx(t, rel=1e-12) and got_b == pytest.approx(b_all, rel=1e-12)
+
+
+def test_surrogate_step_floor_at_the_benchmark_size():
+    t, b = bench.surrogate_step_floor(lbm, 256, 16)
+    assert t * 1e3 == pytest.approx(0.658, abs=0.001) and b / 1e9 == pytest.approx(5.03, abs=0.01)
