@@ -260,22 +260,37 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
         return;
     }
 
-    // FP32 epilogue: lane holds pixels (y0 + RW wave + m, x0 + 4 g + i), channel co_base + 16 n + r
+    // FP32 epilogue: 16 channels at a time through the LDS (free after the last
+    // barrier), then out as 16-byte vectors of 4 channels
+    static_assert(TH * LT_W * 16 * 2 <= K::XIN + K::WSH, "16 FP32 channels of the tile fit the staging space");
+    float* of = reinterpret_cast<float*>(lds);
+    const bool vec = (a.out_f32_cs & 3) == 0;
 #pragma unroll
     for (int n = 0; n < NB; ++n) {
-        const int co = co_base + 16 * n + r;
-        if (co >= a.cout) continue;
-        const float bias = (a.bias != nullptr) ? a.bias[co] : 0.0f;
+        if (n > 0) __syncthreads();  // the previous half is stored
+        // lane holds pixels (RW wave + m, 4 g + i) of the tile, channel 16 n + r
 #pragma unroll
-        for (int m = 0; m < RW; ++m) {
-            const int y = y0 + RW * wave + m;
-            if (y >= a.H) continue;
+        for (int m = 0; m < RW; ++m)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int x = x0 + 4 * g + i;
-                if (x >= a.W) continue;
-                const long long p = ((long long)img * a.H + y) * a.W + x;
-                a.out_f32[p * a.out_f32_cs + co] = acc[m][n][i] + bias;
+            for (int i = 0; i < 4; ++i) of[((RW * wave + m) * LT_W + 4 * g + i) * 16 + r] = acc[m][n][i];
+        __syncthreads();
+        for (int q = threadIdx.x; q < TH * LT_W * 4; q += 256) {
+            const int pl = q >> 2, c4 = q & 3;
+            const int y = y0 + pl / LT_W, x = x0 + pl % LT_W, co = co_base + 16 * n + 4 * c4;
+            if (y >= a.H || x >= a.W || co >= a.cout) continue;
+            float4 v = *reinterpret_cast<const float4*>(of + pl * 16 + 4 * c4);
+            if (a.bias != nullptr) {
+                v.x += a.bias[co];
+                if (co + 1 < a.cout) v.y += a.bias[co + 1];
+                if (co + 2 < a.cout) v.z += a.bias[co + 2];
+                if (co + 3 < a.cout) v.w += a.bias[co + 3];
+            }
+            float* dst = a.out_f32 + (((long long)img * a.H + y) * a.W + x) * a.out_f32_cs + co;
+            if (vec && co + 3 < a.cout) {
+                *reinterpret_cast<float4*>(dst) = v;
+            } else {
+                const float e[4] = {v.x, v.y, v.z, v.w};
+                for (int k = 0; k < 4 && co + k < a.cout; ++k) dst[k] = e[k];
             }
         }
     }
@@ -295,6 +310,7 @@ __global__ __launch_bounds__(256) void conv3x3_lds_run_kernel(ConvArgs a, int ti
     constexpr int HALO = (TH + 2) * (LT_W + 2) * 4;  // 16-byte pieces of the input halo
     constexpr int HR = (HALO + 255) / 256;            // per thread
     constexpr int OST = TH * LT_W * CO_B;
+    static_assert(CO_B >= 32, "the FP32 output stages 16 channels per pixel in the output area");
     __shared__ __attribute__((aligned(16))) uint16_t lds[K::XIN + K::WSH + OST];
     uint16_t* xin = lds;
     uint16_t* wsh = lds + K::XIN;
@@ -372,25 +388,41 @@ __global__ __launch_bounds__(256) void conv3x3_lds_run_kernel(ConvArgs a, int ti
         }
         int img, y0, x0;
         tile_origin(t, img, y0, x0);
-        if (a.epi == EPI_F32) {  // lane holds pixels (y0 + RW wave + m, x0 + 4 g + i), channel co_base + 16 n + r
+        if (a.epi == EPI_F32) {
+            // FP32 output, 16 channels at a time through the output area (which holds
+            // TH x LT_W x 16 floats), then out as 16-byte vectors: pixel-major rows of
+            // 64 bytes instead of one float per lane and store
+            float* of = reinterpret_cast<float*>(ost);
+            const bool vec = (a.out_f32_cs & 3) == 0;
 #pragma unroll
             for (int n = 0; n < NB; ++n) {
-                const int co = co_base + 16 * n + r;
-                if (co >= a.cout) continue;
-                const float bias = (a.bias != nullptr) ? a.bias[co] : 0.0f;
+                // lane holds pixels (RW wave + m, 4 g + i) of the tile, channel 16 n + r
 #pragma unroll
-                for (int m = 0; m < RW; ++m) {
-                    const int y = y0 + RW * wave + m;
-                    if (y >= a.H) continue;
+                for (int m = 0; m < RW; ++m)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int x = x0 + 4 * g + i;
-                        if (x >= a.W) continue;
-                        a.out_f32[(((long long)img * a.H + y) * a.W + x) * a.out_f32_cs + co] = acc[m][n][i] + bias;
+                    for (int i = 0; i < 4; ++i) of[((RW * wave + m) * LT_W + 4 * g + i) * 16 + r] = acc[m][n][i];
+                __syncthreads();  // this half is in place (and every wave is done with the halo)
+                for (int q = threadIdx.x; q < TH * LT_W * 4; q += 256) {
+                    const int pl = q >> 2, c4 = q & 3;
+                    const int y = y0 + pl / LT_W, x = x0 + pl % LT_W, co = co_base + 16 * n + 4 * c4;
+                    if (y >= a.H || x >= a.W || co >= a.cout) continue;
+                    float4 v = *reinterpret_cast<const float4*>(of + pl * 16 + 4 * c4);
+                    if (a.bias != nullptr) {
+                        v.x += a.bias[co];
+                        if (co + 1 < a.cout) v.y += a.bias[co + 1];
+                        if (co + 2 < a.cout) v.z += a.bias[co + 2];
+                        if (co + 3 < a.cout) v.w += a.bias[co + 3];
+                    }
+                    float* dst = a.out_f32 + (((long long)img * a.H + y) * a.W + x) * a.out_f32_cs + co;
+                    if (vec && co + 3 < a.cout) {
+                        *reinterpret_cast<float4*>(dst) = v;
+                    } else {
+                        const float e[4] = {v.x, v.y, v.z, v.w};
+                        for (int k = 0; k < 4 && co + k < a.cout; ++k) dst[k] = e[k];
                     }
                 }
+                __syncthreads();  // the area is free for the next half (or the next tile's halo)
             }
-            __syncthreads();  // every wave is done with this tile's halo
             continue;
         }
 #pragma unroll
