@@ -203,8 +203,8 @@ __global__ __launch_bounds__(NT) void fields3_kernel(Args3 A, const ST* __restri
 // registers until its own collision two planes later, and its density goes into
 // an LDS ring of five planes (the column plus a two-node ring in x and y).  The
 // ring nodes' densities come from their own pulls: those nodes belong to the
-// neighbouring columns, which pull the same lines at about the same time, so the
-// re-reads are served by L2.  The chemical potential (Eq 8) of plane z + 1 goes
+// neighbouring columns, which pull the same lines at about the same time, so L2
+// serves most of the re-reads.  The chemical potential (Eq 8) of plane z + 1 goes
 // into an LDS ring of three planes (column plus a one-node ring), and then plane z
 // has all that the force of Eq 12 and the collision need.  Per node and plane: one
 // pull of the distributions, one store, no density pass.
