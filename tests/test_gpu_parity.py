@@ -13,7 +13,7 @@ import pytest
 
 from cases import C1, C1_TAU13, C2, C3, C3_512, WALLED_PR, Case, rel_err
 from oracle import thermo
-from oracle.lattice import CPWALL, NEUTRAL, PERIODIC, OracleLattice
+from oracle.lattice import CPWALL, NEUTRAL, PERIODIC, OracleLattice, eos_c, stencils_c
 
 pytestmark = pytest.mark.gpu
 
@@ -364,3 +364,26 @@ def test_fp32_full_size_4096_sampled(shape):
         got = f[:, (ys[m:m + w])[:, None], xs[m:m + w][None, :]]
         want = ora.f[:, m:m + w, m:m + w]
         assert rel_err(got, want) < 2e-5
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_band_chemical_potential_of_16bit_storage(prec):
+    """Inside the spinodal band the 16-bit formats evaluate psi' in FP64 with a
+    Newton-refined reciprocal and a series logarithm, rounded to FP32.  On the
+    512^2 spinodal start (every node in the band) the output mu must equal
+    psi'(rho) - kappa lap(rho), evaluated by the oracle in FP64 from the same output
+    rho, within FP32 rounding of the terms: 8 u32 (|psi'| + kappa 20 rho)."""
+    p = {"f16": lbm.LBM_F16DEV, "bf16": lbm.LBM_BF16DEV}[prec]
+    lat = lbm.Lattice(C3_512.lbm_params(p, rho_ref=2.6), C3_512.rho0())
+    fd = lat.fields()
+    lat.close()
+    rho, mu = fd["rho"], fd["mu"]
+    op = C3_512.oracle_params()
+    lo, hi = thermo.spinodal(thermo.fluid_at(C3_512.eos, *C3_512.ab, 1.0, C3_512.Tr))
+    assert lo < rho.min() and rho.max() < hi
+    mu_b = eos_c(op, rho)[2].reshape(rho.shape)
+    want = mu_b - op.kappa * stencils_c(op, rho)[0]
+    bound = 8 * 2.0 ** -24 * (np.abs(mu_b) + op.kappa * 20 * rho)
+    excess = np.abs(mu - want) / bound
+    print("%s band mu: max |error| / bound %.3f" % (prec, excess.max()))
+    assert excess.max() <= 1.0
