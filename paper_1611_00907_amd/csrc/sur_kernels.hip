@@ -296,13 +296,13 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
     }
 }
 
-// The same convolution for layers of 32 input channels (one channel block), with a
-// workgroup walking a run of pixel tiles: the weights are staged once for the run,
-// the next tile's input halo is loaded into registers while the current tile's
-// MFMAs run, and the output tile goes out through an LDS area of its own, so that the
-// load, MFMA and store phases of consecutive tiles overlap.  The 256^2 layers of 32
-// channels are close to memory-bound, and the one-tile workgroups left these phases
-// back to back.
+// The same convolution with a workgroup walking a run of pixel tiles, each tile in
+// steps of one 32-channel input block: the next step's input halo (and, with more
+// than one block, its weights) is loaded into registers while the current step's
+// MFMAs run, the weights of a single block are staged once for the run, and the
+// output tile goes out through an LDS area of its own, so that the load, MFMA and
+// store phases of consecutive steps overlap.  The 256^2 layers are close to
+// memory-bound, and the one-tile workgroups left these phases back to back.
 template <int RW, int CO_B>
 __global__ __launch_bounds__(256) void conv3x3_lds_run_kernel(ConvArgs a, int tiles_per_run) {
     using K = LdsConv<RW, CO_B>;
@@ -325,21 +325,46 @@ __global__ __launch_bounds__(256) void conv3x3_lds_run_kernel(ConvArgs a, int ti
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
 
-    // weights of the run: [tap][CO_B output channels][32 input channels]
-    for (int q = threadIdx.x; q < 9 * CO_B * 4; q += 256) {
-        const int row = q >> 2, cg = q & 3;
-        const int tap = row / CO_B, col = row - tap * CO_B;
-        *reinterpret_cast<uint4*>(wsh + row * 32 + 8 * cg) =
-            *reinterpret_cast<const uint4*>(a.w + ((size_t)(tap * a.cout_p + co_base + col) * a.cin_p + 8 * cg));
-    }
+    // The run is a sequence of steps (tile, input-channel block of 32); a tile's
+    // accumulators carry over its blocks.  Weights of a block: [tap][CO_B output
+    // channels][32 input channels]; with one block they are staged once for the run,
+    // with several each step stages its block's weights, prefetched like the halo.
+    const int ncb = a.cin_p / 32;
+    constexpr int WPC = 9 * CO_B * 4;             // 16-byte pieces of one block's weights
+    constexpr int WR = (WPC + 255) / 256;         // per thread
+    auto load_w = [&](int cb, uint4* wr) {
+#pragma unroll
+        for (int k = 0; k < WR; ++k) {
+            const int q = threadIdx.x + 256 * k;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (q < WPC) {
+                const int row = q >> 2, cg = q & 3;
+                const int tap = row / CO_B, col = row - tap * CO_B;
+                v = *reinterpret_cast<const uint4*>(a.w + ((size_t)(tap * a.cout_p + co_base + col) * a.cin_p +
+                                                           32 * cb + 8 * cg));
+            }
+            wr[k] = v;
+        }
+    };
+    auto store_w = [&](const uint4* wr) {
+#pragma unroll
+        for (int k = 0; k < WR; ++k) {
+            const int q = threadIdx.x + 256 * k;
+            if (q < WPC) *reinterpret_cast<uint4*>(wsh + (q >> 2) * 32 + 8 * (q & 3)) = wr[k];
+        }
+    };
+    uint4 wr[WR];
+    load_w(0, wr);
+    if (ncb == 1) store_w(wr);
     auto tile_origin = [&](int t, int& img, int& y0, int& x0) {
         img = t / (tiles_y * tiles_x);
         const int tt = t - img * tiles_y * tiles_x;
         y0 = (tt / tiles_x) * TH;
         x0 = (tt % tiles_x) * LT_W;
     };
-    // halo piece q of a tile: pixel q / 4 of the (TH + 2) x (LT_W + 2) halo, channels 8 (q % 4) ..
-    auto load_halo = [&](int t, uint4* hr) {
+    // halo piece q of a tile: pixel q / 4 of the (TH + 2) x (LT_W + 2) halo, channels
+    // 32 cb + 8 (q % 4) ..
+    auto load_halo = [&](int t, int cb, uint4* hr) {
         int img, y0, x0;
         tile_origin(t, img, y0, x0);
 #pragma unroll
@@ -347,7 +372,7 @@ __global__ __launch_bounds__(256) void conv3x3_lds_run_kernel(ConvArgs a, int ti
             const int q = threadIdx.x + 256 * k;
             const int pix = q >> 2, cg = q & 3;
             const int yy = y0 - 1 + pix / (LT_W + 2), xx = x0 - 1 + pix % (LT_W + 2);
-            const int ci = 8 * cg;
+            const int ci = 32 * cb + 8 * cg;
             uint4 v = make_uint4(0, 0, 0, 0);
             if (q < HALO && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W && ci < a.cin)
                 v = *reinterpret_cast<const uint4*>(a.in.p + (((long long)img * a.H + yy) * a.W + xx) * a.in.cs +
@@ -356,20 +381,27 @@ __global__ __launch_bounds__(256) void conv3x3_lds_run_kernel(ConvArgs a, int ti
         }
     };
     uint4 hr[HR];
-    load_halo(t_begin, hr);
-    for (int t = t_begin; t < t_end; ++t) {
+    load_halo(t_begin, 0, hr);
+    f32x4 acc[RW][NB];
+    for (int st = 0, st_end = (t_end - t_begin) * ncb; st < st_end; ++st) {
+        const int t = t_begin + st / ncb, cb = st % ncb;
 #pragma unroll
         for (int k = 0; k < HR; ++k) {
             const int q = threadIdx.x + 256 * k;
             if (q < HALO) *reinterpret_cast<uint4*>(xin + (q >> 2) * 32 + 8 * (q & 3)) = hr[k];
         }
-        __syncthreads();  // halo (and, on the first tile, weights) in place; the last tile's output stored
-        if (t + 1 < t_end) load_halo(t + 1, hr);  // in flight during the MFMAs
-        f32x4 acc[RW][NB];
+        if (ncb > 1) store_w(wr);
+        __syncthreads();  // halo and weights in place; the last tile's output stored
+        if (st + 1 < st_end) {  // in flight during the MFMAs
+            load_halo(t_begin + (st + 1) / ncb, (st + 1) % ncb, hr);
+            if (ncb > 1) load_w((st + 1) % ncb, wr);
+        }
+        if (cb == 0) {
 #pragma unroll
-        for (int m = 0; m < RW; ++m)
+            for (int m = 0; m < RW; ++m)
 #pragma unroll
-            for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int du = tap / 3 - 1, dv = tap % 3 - 1;
@@ -385,6 +417,10 @@ __global__ __launch_bounds__(256) void conv3x3_lds_run_kernel(ConvArgs a, int ti
                 for (int n = 0; n < NB; ++n)
                     acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[n], acc[m][n], 0, 0, 0);
             }
+        }
+        if (cb + 1 < ncb) {  // the tile's next channel block
+            __syncthreads();    // every wave is done with this block's halo and weights
+            continue;
         }
         int img, y0, x0;
         tile_origin(t, img, y0, x0);
@@ -1181,8 +1217,14 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
         // a 64^2 layer of 96 channels takes 46 us as one 96-channel block of 256
         // workgroups, 32 us as three 32-channel blocks of 4 rows per wave, 37 us of 2)
         constexpr long long ENOUGH = 1024;
-        if (a.cin_p == 32 && a.H >= 16) {
-            // one input-channel block: runs of tiles, two workgroups per CU
+        // runs of tiles for one input block, and for three or more on large maps (or
+        // five or more at any size); two blocks keep the blocked kernel with its wider
+        // output blocks (measured per layer: 256^2 of 96 channels 128 -> 113 us,
+        // 128^2 of 160 channels 94 -> 80 us, but 128^2 of 64 channels 43 -> 47 us and
+        // 64^2 of 96 channels 18 -> 27 us with runs)
+        const int ncb = a.cin_p / 32;
+        if (a.cin_p % 32 == 0 && a.H >= 16 && (ncb == 1 || (ncb >= 3 && a.H >= 128) || ncb >= 5)) {
+            // two workgroups per CU
             const int co_blocks = a.cout_p / 32;
             const long long tiles = blocks_of(LdsConv<4, 32>::TH, 32) / co_blocks;
             long long runs = std::max<long long>(1, 512 / co_blocks);
