@@ -221,3 +221,26 @@ def test_warm_start_host_helpers_match_their_definitions(lbm):
     pl, pg = lbm.warm_bulk_phases(phi)
     assert abs(pl - np.median(phi[ero_hi])) < 1e-7 and abs(pg - np.median(phi[ero_lo])) < 1e-7
     assert lbm.warm_bulk_phases(np.full((8, 8), 0.2, np.float32)) == (1.0, pytest.approx(0.2, abs=1e-7))
+
+
+def test_lbm3d_init_rejects_boxes_the_kernels_cannot_address(lbm):
+    """Checked on the host before any device call: walls and 16-bit storage (D3Q19
+    is periodic, FP64 or FP32), and a box whose slice of one direction and one z
+    plane (ny rows of pitch = nx rounded up to 64) would reach 4 GiB, since the
+    marching kernel's pulls use 32-bit byte offsets within a slice."""
+    import ctypes as C
+    lib = lbm.load_library()
+    rho = np.zeros(1)
+
+    def init(nx, ny, nz, prec=lbm.LBM_F32, **kw):
+        p = lbm.make_params(nx, ny, 0, 9 / 49, 2 / 21, 0.85, 1.0, 0.01, prec=prec, **kw)
+        ctx = C.c_void_p()
+        st = lib.lbm3d_init(C.byref(p), nz, rho.ctypes.data_as(C.c_void_p), C.byref(ctx))
+        assert not ctx.value
+        return st
+
+    assert init(65536, 16384, 1) == lbm.LBM_EINVAL                    # FP32 slice: 2^32 bytes
+    assert init(65536, 8192, 1, prec=lbm.LBM_F64) == lbm.LBM_EINVAL   # FP64 slice: 2^32 bytes
+    assert init(64, 64, 4, prec=lbm.LBM_F16DEV) == lbm.LBM_EINVAL
+    assert init(64, 64, 4, bc_bottom=lbm.LBM_BC_CPWALL, bc_top=lbm.LBM_BC_NEUTRAL) == lbm.LBM_EINVAL
+    assert init(64, 64, 0) == lbm.LBM_EINVAL
