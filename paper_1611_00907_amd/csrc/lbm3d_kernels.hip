@@ -324,11 +324,17 @@ struct March3 {
     __device__ __forceinline__ int wz(int z) const { return ((z % A.nz) + A.nz) % A.nz; }
 
     // Pull plane z (relative index t = z - zs + 2 picks the density slot): own
-    // node into f, densities of the own and the ring node into the ring.
+    // node into f, densities of the own and the ring node into the ring.  On boxes
+    // beyond the caches (NTS) the own pulls go out at a raised wave priority, so that
+    // a wave issuing them wins the SIMD over the other workgroup's arithmetic (256^3
+    // FP32: 661 -> 645 us; the ring's pulls at that priority as well: 652 us).
+    template <bool NTS>
     __device__ __forceinline__ void lead(int z, CT f[19]) {
         const int zc = wz(z), zm = wz(zc - 1), zp = wz(zc + 1);
         CT* r = L.r[(z - zs + 2) % 5];
+        if constexpr (NTS) __builtin_amdgcn_s_setprio(2);
         pull19z<ST, CT>(A, fin, P.own, zc, zm, zp, f);
+        if constexpr (NTS) __builtin_amdgcn_s_setprio(0);
         if (P.rr >= 0) {
             CT h[19];
             pull19z<ST, CT>(A, fin, P.ring, zc, zm, zp, h);
@@ -391,7 +397,7 @@ struct March3 {
     // Plane z: pull z + 2 into fc, chemical potential of z + 1, collide fa (plane z).
     template <int EOS, bool NTS>
     __device__ __forceinline__ void plane(int z, const CT fa[19], CT fc[19]) {
-        lead(z + 2, fc);
+        lead<NTS>(z + 2, fc);
         __syncthreads();
         mu<EOS>(z + 1);
         __syncthreads();
@@ -441,10 +447,10 @@ void march3_kernel(Args3 A, int zrun, const ST* __restrict__ fin, ST* __restrict
     March3<ST, CT> M{A, fin, fout, L, P, zs};
     // prologue: densities of planes zs - 2 .. zs + 1, chemical potentials of zs - 1, zs
     CT f0[19], f1[19], f2[19];
-    M.lead(zs - 2, f2);
-    M.lead(zs - 1, f2);
-    M.lead(zs, f0);
-    M.lead(zs + 1, f1);
+    M.template lead<NTS>(zs - 2, f2);
+    M.template lead<NTS>(zs - 1, f2);
+    M.template lead<NTS>(zs, f0);
+    M.template lead<NTS>(zs + 1, f1);
     __syncthreads();
     M.template mu<EOS>(zs - 1);
     M.template mu<EOS>(zs);
