@@ -142,6 +142,65 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
 // input halo and the 9 x CO_B x 32 weights in LDS; per tap a wave then reads CO_B / 16
 // weight blocks and RW pixel blocks and issues RW x CO_B / 16 MFMAs (2 x 2 for RW = 2,
 // CO_B = 32: one LDS read per MFMA; 4 x 4 for RW = 4, CO_B = 64: one per two).
+// Convolution to one output channel with an FP32 output (the output layer), on the
+// vector ALUs: a matrix-core block would be 1/16 full.  A workgroup stages a 16 x 16
+// pixel tile with its one-pixel ring (32 input channels at a time, pixels padded to
+// 40 channels so that the lanes' 16-byte reads of consecutive pixels fall in
+// distinct LDS banks) and the block's 9 x 32 weights in FP32; each thread sums the
+// 9 x 32 products of its pixel.  Needs input views whose strides and offsets are
+// multiples of 8 channels.
+constexpr int C1_T = 16, C1_HW = C1_T + 2, C1_PX = 40;
+__global__ __launch_bounds__(256) void conv3x3_c1_kernel(ConvArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t xs[C1_HW * C1_HW * C1_PX];
+    __shared__ __attribute__((aligned(16))) float ws[9 * 32];
+    const int tiles_x = (a.W + C1_T - 1) / C1_T, tiles_y = (a.H + C1_T - 1) / C1_T;
+    int b = blockIdx.x;
+    const int x0 = (b % tiles_x) * C1_T;
+    b /= tiles_x;
+    const int y0 = (b % tiles_y) * C1_T, img = b / tiles_y;
+    const int lx = threadIdx.x % C1_T, ly = threadIdx.x / C1_T;
+    float acc = 0.f;
+    for (int ci0 = 0; ci0 < a.cin_p; ci0 += 32) {
+        for (int q = threadIdx.x; q < C1_HW * C1_HW * 4; q += 256) {
+            const int pix = q >> 2, cg = q & 3;
+            const int yy = y0 - 1 + pix / C1_HW, xx = x0 - 1 + pix % C1_HW, ci = ci0 + 8 * cg;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W && ci < a.cin)
+                v = *reinterpret_cast<const uint4*>(a.in.p + (((long long)img * a.H + yy) * a.W + xx) * a.in.cs +
+                                                    a.in.co + ci);
+            *reinterpret_cast<uint4*>(xs + pix * C1_PX + 8 * cg) = v;
+        }
+        for (int q = threadIdx.x; q < 9 * 32; q += 256) {
+            const int tap = q >> 5, ci = ci0 + (q & 31);
+            ws[q] = ci < a.cin ? bf2f(a.w[(size_t)tap * a.cout_p * a.cin_p + ci]) : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const uint16_t* px = xs + ((ly + tap / 3) * C1_HW + (lx + tap % 3)) * C1_PX;
+            const float* w = ws + 32 * tap;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint4 v = *reinterpret_cast<const uint4*>(px + 8 * k);
+                const float4 w0 = *reinterpret_cast<const float4*>(w + 8 * k);
+                const float4 w1 = *reinterpret_cast<const float4*>(w + 8 * k + 4);
+                acc = fmaf(w0.x, __uint_as_float(v.x << 16), acc);
+                acc = fmaf(w0.y, __uint_as_float(v.x & 0xffff0000u), acc);
+                acc = fmaf(w0.z, __uint_as_float(v.y << 16), acc);
+                acc = fmaf(w0.w, __uint_as_float(v.y & 0xffff0000u), acc);
+                acc = fmaf(w1.x, __uint_as_float(v.z << 16), acc);
+                acc = fmaf(w1.y, __uint_as_float(v.z & 0xffff0000u), acc);
+                acc = fmaf(w1.z, __uint_as_float(v.w << 16), acc);
+                acc = fmaf(w1.w, __uint_as_float(v.w & 0xffff0000u), acc);
+            }
+        }
+        __syncthreads();  // the next block overwrites the LDS
+    }
+    const int x = x0 + lx, y = y0 + ly;
+    if (x < a.W && y < a.H)
+        a.out_f32[(((long long)img * a.H + y) * a.W + x) * a.out_f32_cs] = acc + (a.bias != nullptr ? a.bias[0] : 0.f);
+}
+
 constexpr int LT_W = 16;
 template <int RW, int CO_B>
 struct LdsConv {
@@ -1246,6 +1305,9 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
             lds(conv3x3_lds_kernel<4, 32>, LdsConv<4, 32>::TH, 32);
         else
             lds(conv3x3_lds_kernel<2, 32>, LdsConv<2, 32>::TH, 32);
+    } else if (a.cout == 1 && a.epi == EPI_F32 && a.cin % 8 == 0 && a.in.cs % 8 == 0 && a.in.co % 8 == 0) {
+        const long long tiles = (long long)a.N * ((a.H + C1_T - 1) / C1_T) * ((a.W + C1_T - 1) / C1_T);
+        hipLaunchKernelGGL(conv3x3_c1_kernel, dim3(unsigned(tiles)), dim3(256), 0, s, a);
     } else {
         const long long waves = ((npx + 63) / 64) * (a.cout_p / 16);
         hipLaunchKernelGGL((conv3x3_kernel<4, 1>), dim3(int((waves + 3) / 4)), dim3(256), 0, s, a);
