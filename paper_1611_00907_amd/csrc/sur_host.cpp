@@ -161,7 +161,9 @@ hipError_t conv_back(sur_net* n, int li, TView dz, int N, int H, int W, int epi,
     a.N = N;
     a.H = H;
     a.W = W;
-    a.cin = round_up(l.d.cout, 8);
+    // the matrix-core kernels read 8-channel groups; the one-channel output gradient
+    // of the output layer goes to a kernel that reads its one channel
+    a.cin = l.d.cout == 1 ? 1 : round_up(l.d.cout, 8);
     a.cin_p = l.t_cin_p;
     a.cout = l.d.cin;
     a.cout_p = l.t_cout_p;

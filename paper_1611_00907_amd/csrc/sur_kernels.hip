@@ -201,6 +201,83 @@ __global__ __launch_bounds__(256) void conv3x3_c1_kernel(ConvArgs a) {
         a.out_f32[(((long long)img * a.H + y) * a.W + x) * a.out_f32_cs] = acc + (a.bias != nullptr ? a.bias[0] : 0.f);
 }
 
+// Convolution from one input channel to at most 32 (the output layer's input
+// gradient: dX = the flipped convolution of its one-channel output gradient, masked
+// by the ReLU of its input), on the vector ALUs: a 16 x 16 pixel tile of the input
+// channel with its ring and the 9 x 32 weights in LDS, each thread the 32 outputs of
+// one pixel, staged in LDS and stored as BF16 in 16-byte pieces of 8 channels with
+// the mask applied as in the matrix-core kernels (a BF16 output whose mask value is
+// not > 0 is zeroed).
+__global__ __launch_bounds__(256) void conv3x3_from1_kernel(ConvArgs a) {
+    __shared__ float zs[C1_HW * C1_HW];
+    __shared__ __attribute__((aligned(16))) float ws[9 * 32];
+    const int tiles_x = (a.W + C1_T - 1) / C1_T, tiles_y = (a.H + C1_T - 1) / C1_T;
+    int b = blockIdx.x;
+    const int x0 = (b % tiles_x) * C1_T;
+    b /= tiles_x;
+    const int y0 = (b % tiles_y) * C1_T, img = b / tiles_y;
+    const int lx = threadIdx.x % C1_T, ly = threadIdx.x / C1_T;
+    for (int q = threadIdx.x; q < C1_HW * C1_HW; q += 256) {
+        const int yy = y0 - 1 + q / C1_HW, xx = x0 - 1 + q % C1_HW;
+        zs[q] = (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                    ? bf2f(a.in.p[(((long long)img * a.H + yy) * a.W + xx) * a.in.cs + a.in.co])
+                    : 0.f;
+    }
+    for (int q = threadIdx.x; q < 9 * 32; q += 256) {
+        const int tap = q >> 5, co = q & 31;
+        ws[q] = co < a.cout ? bf2f(a.w[((size_t)tap * a.cout_p + co) * a.cin_p]) : 0.f;
+    }
+    __syncthreads();
+    float acc[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) acc[c] = 0.f;
+    // one tap at a time (unrolled, the compiler would hold all 288 weights in registers)
+#pragma unroll 1
+    for (int tap = 0; tap < 9; ++tap) {
+        const float z = zs[(ly + tap / 3) * C1_HW + lx + tap % 3];
+#pragma unroll
+        for (int c4 = 0; c4 < 8; ++c4) {
+            const float4 w = *reinterpret_cast<const float4*>(ws + 32 * tap + 4 * c4);
+            acc[4 * c4] = fmaf(w.x, z, acc[4 * c4]);
+            acc[4 * c4 + 1] = fmaf(w.y, z, acc[4 * c4 + 1]);
+            acc[4 * c4 + 2] = fmaf(w.z, z, acc[4 * c4 + 2]);
+            acc[4 * c4 + 3] = fmaf(w.w, z, acc[4 * c4 + 3]);
+        }
+    }
+    // the tile's outputs through LDS (pixels padded to 40 channels against bank
+    // conflicts), then stored pixel-major in 16-byte pieces with the mask applied
+    __shared__ __attribute__((aligned(16))) uint16_t os[C1_T * C1_T * C1_PX];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        uint32_t d[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            d[k] = uint32_t(f2bf(acc[8 * g + 2 * k])) | (uint32_t(f2bf(acc[8 * g + 2 * k + 1])) << 16);
+        *reinterpret_cast<uint4*>(os + threadIdx.x * C1_PX + 8 * g) = make_uint4(d[0], d[1], d[2], d[3]);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < C1_T * C1_T * 4; q += 256) {
+        const int pl = q >> 2, g = q & 3;
+        const int x = x0 + pl % C1_T, y = y0 + pl / C1_T;
+        if (x >= a.W || y >= a.H || 8 * g >= a.cout) continue;
+        const long long p = ((long long)img * a.H + y) * a.W + x;
+        uint4 v = *reinterpret_cast<const uint4*>(os + pl * C1_PX + 8 * g);
+        if (a.epi == EPI_MASK_BF16) {
+            const uint4 mk = *reinterpret_cast<const uint4*>(a.mask.p + p * a.mask.cs + a.mask.co + 8 * g);
+            auto keep = [](uint32_t w, uint32_t m) {
+                const uint32_t lo = bf2f(uint16_t(m)) > 0.f ? 0x0000ffffu : 0u;
+                const uint32_t hi = bf2f(uint16_t(m >> 16)) > 0.f ? 0xffff0000u : 0u;
+                return w & (lo | hi);
+            };
+            v.x = keep(v.x, mk.x);
+            v.y = keep(v.y, mk.y);
+            v.z = keep(v.z, mk.z);
+            v.w = keep(v.w, mk.w);
+        }
+        *reinterpret_cast<uint4*>(a.out.p + p * a.out.cs + a.out.co + 8 * g) = v;
+    }
+}
+
 constexpr int LT_W = 16;
 template <int RW, int CO_B>
 struct LdsConv {
@@ -1269,6 +1346,11 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
     auto lds = [&](auto kernel, int th, int co_b) {
         hipLaunchKernelGGL(kernel, dim3(unsigned(blocks_of(th, co_b))), dim3(256), 0, s, a);
     };
+    if (a.cin == 1 && a.cout <= 32 && a.cout % 8 == 0 && a.epi == EPI_MASK_BF16 && views8) {
+        const long long tiles = (long long)a.N * ((a.H + C1_T - 1) / C1_T) * ((a.W + C1_T - 1) / C1_T);
+        hipLaunchKernelGGL(conv3x3_from1_kernel, dim3(unsigned(tiles)), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     if (a.cout_p % 32 == 0 && (a.epi == EPI_F32 || views8)) {
         // the widest channel block (each staged halo then serves more output channels)
         // that still gives at least 1024 workgroups (64 or 96 channels, 4 rows per wave),
