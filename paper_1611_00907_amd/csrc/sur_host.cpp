@@ -201,13 +201,15 @@ hipError_t trace_dp(sur_net* n, int k, int N, int H, int W, int C) {
                           n->stream);
 }
 
+// One launch for every layer's flipped weights (they change with every Adam step).
 hipError_t refresh_flipped(sur_net* n) {
-    for (const Layer& l : n->L) {
-        hipError_t e = flip_weights(n->wbf + l.w_off, l.cout_p, l.cin_p, l.d.cin, l.d.cout, n->wflip + l.t_off,
-                                    l.t_cout_p, l.t_cin_p, n->stream);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    static_assert(NL <= FLIP_MAX_JOBS, "one flip job per layer");
+    FlipJob jobs[FLIP_MAX_JOBS];
+    int k = 0;
+    for (const Layer& l : n->L)
+        jobs[k++] = FlipJob{n->wbf + l.w_off, n->wflip + l.t_off, l.cout_p, l.cin_p, l.d.cin, l.d.cout,
+                            l.t_cout_p, l.t_cin_p};
+    return flip_weights(jobs, k, n->stream);
 }
 
 #define SUR_TRY(expr)                                       \

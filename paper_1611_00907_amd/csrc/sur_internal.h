@@ -60,8 +60,16 @@ hipError_t mse(const float* y, const float* t, long long count, TView dz, double
 hipError_t adam(float* p, const float* g, float* m, float* v, uint16_t* p_bf16, long long n, float lr, int step,
                 hipStream_t s);
 hipError_t to_bf16(const float* src, uint16_t* dst, long long n, hipStream_t s);
-hipError_t flip_weights(const uint16_t* w, int cout_p, int cin_p, int cin, int cout, uint16_t* wt, int t_cout_p,
-                        int t_cin_p, hipStream_t s);
+// The weights of one layer for its input gradient: wt[tap][c][k] = w[8 - tap][k][c]
+// (taps mirrored, input and output channels swapped), zero beyond cin / cout.
+struct FlipJob {
+    const uint16_t* w;
+    uint16_t* wt;
+    int cout_p, cin_p, cin, cout, t_cout_p, t_cin_p;
+};
+constexpr int FLIP_MAX_JOBS = 16;
+// All layers' flips in one launch (at most FLIP_MAX_JOBS).
+hipError_t flip_weights(const FlipJob* jobs, int n, hipStream_t s);
 hipError_t gather_rows(const float* src, const int* idx, long long len, int nb, float* dst, hipStream_t s);
 
 }  // namespace sur

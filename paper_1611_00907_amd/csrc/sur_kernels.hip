@@ -1303,17 +1303,26 @@ __global__ void to_bf16_kernel(const float* __restrict__ src, uint16_t* __restri
 
 // Weights for the input gradient: Wt[t'][ci][co] = W[8 - t'][co][ci] (flip the 3 x 3
 // window, swap the channel roles), padded as [9][cin_p16][cout_p32].
-__global__ void flip_weights_kernel(const uint16_t* __restrict__ w, int cout_p, int cin_p, int cin, int cout,
-                                    uint16_t* __restrict__ wt, int t_cout_p, int t_cin_p) {
-    const long long total = 9LL * t_cout_p * t_cin_p;
+struct FlipBatch {
+    FlipJob job[FLIP_MAX_JOBS];
+    long long begin[FLIP_MAX_JOBS + 1];  // prefix sums of the jobs' element counts
+    int n;
+};
+
+__global__ void flip_weights_kernel(FlipBatch b) {
+    const long long total = b.begin[b.n];
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (long long)gridDim.x * blockDim.x) {
-        const int k = int(i % t_cin_p);        // original output channel
-        const int c = int((i / t_cin_p) % t_cout_p);  // original input channel
-        const int tp = int(i / t_cin_p / t_cout_p);
+        int j = 0;
+        while (j + 1 < b.n && i >= b.begin[j + 1]) ++j;
+        const FlipJob& J = b.job[j];
+        const long long li = i - b.begin[j];
+        const int k = int(li % J.t_cin_p);                // original output channel
+        const int c = int((li / J.t_cin_p) % J.t_cout_p);  // original input channel
+        const int tp = int(li / J.t_cin_p / J.t_cout_p);
         uint16_t v = 0;
-        if (c < cin && k < cout) v = w[((size_t)(8 - tp) * cout_p + k) * cin_p + c];
-        wt[i] = v;
+        if (c < J.cin && k < J.cout) v = J.w[((size_t)(8 - tp) * J.cout_p + k) * J.cin_p + c];
+        J.wt[li] = v;
     }
 }
 
@@ -1561,10 +1570,16 @@ hipError_t to_bf16(const float* src, uint16_t* dst, long long n, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t flip_weights(const uint16_t* w, int cout_p, int cin_p, int cin, int cout, uint16_t* wt, int t_cout_p,
-                        int t_cin_p, hipStream_t s) {
-    hipLaunchKernelGGL(flip_weights_kernel, dim3(grid_for(9LL * t_cout_p * t_cin_p)), dim3(256), 0, s, w, cout_p,
-                       cin_p, cin, cout, wt, t_cout_p, t_cin_p);
+hipError_t flip_weights(const FlipJob* jobs, int n, hipStream_t s) {
+    if (n < 1 || n > FLIP_MAX_JOBS) return hipErrorInvalidValue;
+    FlipBatch b{};
+    b.n = n;
+    b.begin[0] = 0;
+    for (int j = 0; j < n; ++j) {
+        b.job[j] = jobs[j];
+        b.begin[j + 1] = b.begin[j] + 9LL * jobs[j].t_cout_p * jobs[j].t_cin_p;
+    }
+    hipLaunchKernelGGL(flip_weights_kernel, dim3(grid_for(b.begin[n])), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 
