@@ -1249,13 +1249,23 @@ __global__ void skip_grad_kernel(const float* __restrict__ dcat, int dcs, int dc
 }
 
 // NCHW FP32 input with 4 channels -> NHWC BF16 with 16 channels (12 zero).
-__global__ void pack_input_kernel(const float* __restrict__ in, int N, int H, int W, TView out) {
+// vec: the 16 channels of a pixel go out as two 16-byte stores (views in multiples of 8)
+__global__ void pack_input_kernel(const float* __restrict__ in, int N, int H, int W, TView out, bool vec) {
     const long long total = (long long)N * H * W;
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
          q += (long long)gridDim.x * blockDim.x) {
         const long long n = q / ((long long)H * W), hw = q % ((long long)H * W);
-        for (int c = 0; c < 16; ++c)
-            out.p[q * out.cs + out.co + c] = c < 4 ? f2bf(in[(n * 4 + c) * H * W + hw]) : 0;
+        uint16_t b[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = f2bf(in[(n * 4 + c) * H * W + hw]);
+        uint16_t* dst = out.p + q * out.cs + out.co;
+        if (vec) {
+            reinterpret_cast<uint4*>(dst)[0] =
+                make_uint4(uint32_t(b[0]) | (uint32_t(b[1]) << 16), uint32_t(b[2]) | (uint32_t(b[3]) << 16), 0u, 0u);
+            reinterpret_cast<uint4*>(dst)[1] = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+            for (int c = 0; c < 16; ++c) dst[c] = c < 4 ? b[c] : 0;
+        }
     }
 }
 
@@ -1546,7 +1556,9 @@ hipError_t skip_grad(const float* dcat, int dcs, int dco, const float* dpool, in
 }
 
 hipError_t pack_input(const float* in, int N, int H, int W, TView out, hipStream_t s) {
-    hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for((long long)N * H * W)), dim3(256), 0, s, in, N, H, W, out);
+    const bool vec = out.cs % 8 == 0 && out.co % 8 == 0 && out.cs >= 16;
+    hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for((long long)N * H * W)), dim3(256), 0, s, in, N, H, W, out,
+                       vec);
     return hipGetLastError();
 }
 
