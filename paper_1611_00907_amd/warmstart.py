@@ -556,6 +556,7 @@ def run_experiment(n_cases=2000, side=256, seed=11, n_val=100, n_test=100, train
 if __name__ == "__main__":
     import argparse
     import json
+    import sys
 
     ap = argparse.ArgumentParser(description="learned warm start: calibration, equilibria, training, evaluation")
     ap.add_argument("--cases", type=int, default=2000)
@@ -573,6 +574,7 @@ if __name__ == "__main__":
     r = run_experiment(a.cases, a.side, a.seed, a.val, a.test, log=lambda m: print(m, flush=True),
                        debug_path=a.debug, pinned=a.pinned,
                        gen_prec=lbm.LBM_F64 if a.gen_storage == "f64" else lbm.LBM_F32)
+    r["command"] = " ".join(["python -m paper_1611_00907_amd.warmstart"] + sys.argv[1:])
     print(json.dumps(r))
     if a.out:
         json.dump(r, open(a.out, "w"), indent=1)

@@ -161,3 +161,13 @@ def test_surrogate_step_floor_by_hand():
 def test_surrogate_step_floor_at_the_benchmark_size():
     t, b = bench.surrogate_step_floor(lbm, 256, 16)
     assert t * 1e3 == pytest.approx(0.658, abs=0.001) and b / 1e9 == pytest.approx(5.03, abs=0.01)
+
+
+def test_warm_start_record_names_the_command_that_made_it():
+    """The bench line cites the committed warm-start record when the experiment is not
+    rerun; the citation carries the record's own command, which reruns it."""
+    out = bench.warmstart_summary(False)
+    assert out is not None and out["measured_in_this_run"] is False
+    cmd = json.load(open(bench.WARMSTART_RECORD))["command"]
+    assert cmd.startswith("python -m paper_1611_00907_amd.warmstart ")
+    assert out["source"].endswith("(%s)" % cmd)
