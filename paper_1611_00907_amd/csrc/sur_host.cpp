@@ -90,7 +90,7 @@ struct sur_net {
 
 namespace {
 
-constexpr int MSE_BLOCKS = 256;
+constexpr int MSE_BLOCKS = 1024;  // four workgroups per compute unit
 
 template <typename T>
 lbm_status dalloc(sur_net* n, T** p, size_t count) {

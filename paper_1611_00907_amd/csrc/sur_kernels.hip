@@ -1273,11 +1273,21 @@ __global__ void pack_input_kernel(const float* __restrict__ in, int N, int H, in
 // per-block partial sums of (y - t)^2.
 __global__ __launch_bounds__(256) void mse_kernel(const float* __restrict__ y, const float* __restrict__ t,
                                                   long long count, TView dz, double* __restrict__ partial) {
+    // The gradient goes to channel 0 of a 16-channel pixel, the other 15 channels zero;
+    // with 8-channel aligned views the pixel is written as two 16-byte stores.
+    const bool vec = dz.cs % 8 == 0 && dz.co % 8 == 0;
     double s = 0.0;
     for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < count; q += (long long)gridDim.x * 256) {
         const float d = y[q] - t[q];
         s += double(d) * d;
-        for (int c = 0; c < 16; ++c) dz.p[q * dz.cs + dz.co + c] = c == 0 ? f2bf(2.0f * d / float(count)) : 0;
+        const uint16_t g = f2bf(2.0f * d / float(count));
+        uint16_t* o = dz.p + q * dz.cs + dz.co;
+        if (vec) {
+            reinterpret_cast<uint4*>(o)[0] = make_uint4(g, 0u, 0u, 0u);
+            reinterpret_cast<uint4*>(o)[1] = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+            for (int c = 0; c < 16; ++c) o[c] = c == 0 ? g : 0;
+        }
     }
     __shared__ double sh[256];
     sh[threadIdx.x] = s;
