@@ -1347,13 +1347,20 @@ __global__ void flip_weights_kernel(FlipBatch b) {
 }
 
 // Gathers minibatch rows of a resident dataset: dst[b] = src[idx[b]] (float rows of len).
+// Grid rows walk the batch rows, so no element index is divided; with vec (16-byte
+// aligned bases, len % 4 == 0) the rows are copied in 16-byte pieces.
 __global__ void gather_rows_kernel(const float* __restrict__ src, const int* __restrict__ idx, long long len, int nb,
-                                   float* __restrict__ dst) {
-    const long long total = len * nb;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int b = int(i / len);
-        dst[i] = src[(long long)idx[b] * len + i % len];
+                                   float* __restrict__ dst, bool vec) {
+    const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x, stride = (long long)gridDim.x * blockDim.x;
+    for (int b = blockIdx.y; b < nb; b += gridDim.y) {
+        const float* s = src + (long long)idx[b] * len;
+        float* d = dst + (long long)b * len;
+        if (vec) {
+            for (long long i = t0; i < len / 4; i += stride)
+                reinterpret_cast<float4*>(d)[i] = reinterpret_cast<const float4*>(s)[i];
+        } else {
+            for (long long i = t0; i < len; i += stride) d[i] = s[i];
+        }
     }
 }
 
@@ -1606,7 +1613,10 @@ hipError_t flip_weights(const FlipJob* jobs, int n, hipStream_t s) {
 }
 
 hipError_t gather_rows(const float* src, const int* idx, long long len, int nb, float* dst, hipStream_t s) {
-    hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_for(len * nb)), dim3(256), 0, s, src, idx, len, nb, dst);
+    const bool vec = len % 4 == 0 && reinterpret_cast<uintptr_t>(src) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(dst) % 16 == 0;
+    const dim3 grid(grid_for(vec ? len / 4 : len), nb < 65535 ? nb : 65535);
+    hipLaunchKernelGGL(gather_rows_kernel, grid, dim3(256), 0, s, src, idx, len, nb, dst, vec);
     return hipGetLastError();
 }
 

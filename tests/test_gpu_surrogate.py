@@ -119,6 +119,40 @@ def test_first_adam_step():
     assert np.max(np.abs(p1 - p0)) <= lr * 1.0001
 
 
+def _splitmix64_indices(seed, count, n):
+    """Minibatch draws of sur_train: SplitMix64 (Steele, Lea, Flood 2014) outputs
+    reduced modulo the dataset size."""
+    m = (1 << 64) - 1
+    state, out = seed, []
+    for _ in range(n):
+        state = (state + 0x9E3779B97F4A7C15) & m
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+        out.append((z ^ (z >> 31)) % count)
+    return out
+
+
+def test_training_gathers_the_drawn_rows():
+    """A training step on a dataset of six distinct images takes its minibatch rows
+    from the drawn indices, in order: its loss is the loss of those images, and the
+    first Adam step follows their gradient."""
+    net, p32, x, t = _setup(n=6, seed=8)
+    x32, t32 = x.astype(np.float32), t.astype(np.float32)
+    idx = _splitmix64_indices(2, 6, 4)      # [4, 2, 3, 0]
+    assert len(set(idx)) == 4 and idx != sorted(idx), idx
+    p0 = net.get_params()
+    g, loss = net.gradients(x32[idx], t32[idx])
+    net.set_dataset(x32, t32)
+    lr = 1e-3
+    got = net.train(1, 4, lr, seed=2)
+    assert abs(float(got[0]) - loss) <= 1e-6 * loss, (float(got[0]), loss)
+    p1 = net.get_params()
+    want = p0 - lr * g / (np.abs(g) + 1e-8)
+    big = np.abs(g) > 1e-4 * np.abs(g).max()
+    assert np.max(np.abs(p1 - want)[big]) < 2e-6
+
+
 def test_training_reduces_loss():
     net, p32, x, t = _setup(size=32, n=4)
     tt = np.tanh(x[:, 1]) * 0.5                    # a learnable target: a pointwise map of one input
