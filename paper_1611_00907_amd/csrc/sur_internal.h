@@ -34,6 +34,7 @@ struct ConvArgs {
     int cin, cin_p;      // input channels read (multiple of 8), padded k extent (multiple of 32)
     int cout, cout_p;    // output channels stored, padded (multiple of 16)
     int epi;
+    TView pool;          // EPI_RELU_BF16: the 2 x 2 average of the output at half size (p null: none)
 };
 
 struct WgradArgs {

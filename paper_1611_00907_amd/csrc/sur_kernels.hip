@@ -631,6 +631,36 @@ __global__ __launch_bounds__(256) void conv3x3_lds_run_kernel(ConvArgs a, int ti
             }
             *reinterpret_cast<uint4*>(a.out.p + p * a.out.cs + a.out.co + co) = v;
         }
+        if (a.pool.p != nullptr) {
+            // The forward pass's 2 x 2 average of this output tile (tiles start at even
+            // pixels, the map sides are even), its four terms added in the order of the
+            // pooling kernel, so the pooled map is the same bit for bit.
+            static_assert(TH % 2 == 0 && LT_W % 2 == 0, "pooled tiles need even sides");
+            for (int q = threadIdx.x; q < (TH / 2) * (LT_W / 2) * (CO_B / 8); q += 256) {
+                const int pp = q / (CO_B / 8), cg = q % (CO_B / 8);
+                const int py = pp / (LT_W / 2), px = pp % (LT_W / 2);
+                const int y = y0 + 2 * py, x = x0 + 2 * px, co = co_base + 8 * cg;
+                if (y >= a.H || x >= a.W || co >= a.cout) continue;
+                float sum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx) {
+                        const uint4 v =
+                            *reinterpret_cast<const uint4*>(ost + ((2 * py + dy) * LT_W + 2 * px + dx) * CO_B + 8 * cg);
+                        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            sum[2 * k] += bf2f(uint16_t(w[k]));
+                            sum[2 * k + 1] += bf2f(uint16_t(w[k] >> 16));
+                        }
+                    }
+                uint32_t o[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    o[k] = uint32_t(f2bf(0.25f * sum[2 * k])) | (uint32_t(f2bf(0.25f * sum[2 * k + 1])) << 16);
+                const long long pq = ((long long)img * (a.H / 2) + y / 2) * (a.W / 2) + x / 2;
+                *reinterpret_cast<uint4*>(a.pool.p + pq * a.pool.cs + a.pool.co + co) = make_uint4(o[0], o[1], o[2], o[3]);
+            }
+        }
     }
 }
 
@@ -1376,6 +1406,23 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
     (void)hipGetLastError();
     const bool views8 = a.cout % 8 == 0 && a.out.cs % 8 == 0 && a.out.co % 8 == 0 &&
                         (a.epi != EPI_MASK_BF16 || (a.mask.cs % 8 == 0 && a.mask.co % 8 == 0));
+    const int ncb = a.cin_p / 32;
+    // the run-of-tiles kernel: one input block, and three or more on large maps (or
+    // five or more at any size); two blocks keep the blocked kernel with its wider
+    // output blocks (measured per layer: 256^2 of 96 channels 128 -> 113 us,
+    // 128^2 of 160 channels 94 -> 80 us, but 128^2 of 64 channels 43 -> 47 us and
+    // 64^2 of 96 channels 18 -> 27 us with runs)
+    const bool run = a.cout_p % 32 == 0 && (a.epi == EPI_F32 || views8) && a.cin_p % 32 == 0 && a.H >= 16 &&
+                     (ncb == 1 || (ncb >= 3 && a.H >= 128) || ncb >= 5);
+    if (a.pool.p != nullptr &&
+        !(run && a.epi == EPI_RELU_BF16 && a.H % 2 == 0 && a.W % 2 == 0 && a.pool.cs % 8 == 0 && a.pool.co % 8 == 0)) {
+        // the run kernel pools in its epilogue; any other layer is pooled afterwards
+        ConvArgs b = a;
+        b.pool = TView{nullptr, 0, 0};
+        const hipError_t e = conv3x3(b, s);
+        if (e != hipSuccess) return e;
+        return avgpool2(a.out, a.pool, a.N, a.H, a.W, a.cout, s);
+    }
     auto blocks_of = [&](int th, int co_b) {
         return (long long)a.N * ((a.H + th - 1) / th) * ((a.W + LT_W - 1) / LT_W) * (a.cout_p / co_b);
     };
@@ -1394,13 +1441,7 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
         // a 64^2 layer of 96 channels takes 46 us as one 96-channel block of 256
         // workgroups, 32 us as three 32-channel blocks of 4 rows per wave, 37 us of 2)
         constexpr long long ENOUGH = 1024;
-        // runs of tiles for one input block, and for three or more on large maps (or
-        // five or more at any size); two blocks keep the blocked kernel with its wider
-        // output blocks (measured per layer: 256^2 of 96 channels 128 -> 113 us,
-        // 128^2 of 160 channels 94 -> 80 us, but 128^2 of 64 channels 43 -> 47 us and
-        // 64^2 of 96 channels 18 -> 27 us with runs)
-        const int ncb = a.cin_p / 32;
-        if (a.cin_p % 32 == 0 && a.H >= 16 && (ncb == 1 || (ncb >= 3 && a.H >= 128) || ncb >= 5)) {
+        if (run) {
             // two workgroups per CU
             const int co_blocks = a.cout_p / 32;
             const long long tiles = blocks_of(LdsConv<4, 32>::TH, 32) / co_blocks;
