@@ -287,6 +287,39 @@ struct LdsConv {
     static constexpr int NB = CO_B / 16;                    // 16-channel blocks per wave
 };
 
+// The forward pass's 2 x 2 average of a BF16 output tile staged in LDS as [TH x LT_W
+// pixels][CO_B channels] (tile origin and map sides even): its four terms are added in
+// the order of the pooling kernel, so that the pooled map is the same bit for bit.
+template <int TH, int CO_B>
+__device__ __forceinline__ void pool_tile(const ConvArgs& a, const uint16_t* ost, int img, int y0, int x0,
+                                          int co_base) {
+    static_assert(TH % 2 == 0 && LT_W % 2 == 0, "pooled tiles need even sides");
+    for (int q = threadIdx.x; q < (TH / 2) * (LT_W / 2) * (CO_B / 8); q += blockDim.x) {
+        const int pp = q / (CO_B / 8), cg = q % (CO_B / 8);
+        const int py = pp / (LT_W / 2), px = pp % (LT_W / 2);
+        const int y = y0 + 2 * py, x = x0 + 2 * px, co = co_base + 8 * cg;
+        if (y >= a.H || x >= a.W || co >= a.cout) continue;
+        float sum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const uint4 v =
+                    *reinterpret_cast<const uint4*>(ost + ((2 * py + dy) * LT_W + 2 * px + dx) * CO_B + 8 * cg);
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    sum[2 * k] += bf2f(uint16_t(w[k]));
+                    sum[2 * k + 1] += bf2f(uint16_t(w[k] >> 16));
+                }
+            }
+        uint32_t o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            o[k] = uint32_t(f2bf(0.25f * sum[2 * k])) | (uint32_t(f2bf(0.25f * sum[2 * k + 1])) << 16);
+        const long long pq = ((long long)img * (a.H / 2) + y / 2) * (a.W / 2) + x / 2;
+        *reinterpret_cast<uint4*>(a.pool.p + pq * a.pool.cs + a.pool.co + co) = make_uint4(o[0], o[1], o[2], o[3]);
+    }
+}
+
 template <int RW, int CO_B>
 __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
     using K = LdsConv<RW, CO_B>;
@@ -393,6 +426,7 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
             }
             *reinterpret_cast<uint4*>(a.out.p + p * a.out.cs + a.out.co + co) = v;
         }
+        if (a.pool.p != nullptr) pool_tile<TH, CO_B>(a, ost, img, y0, x0, co_base);
         return;
     }
 
@@ -631,36 +665,7 @@ __global__ __launch_bounds__(256) void conv3x3_lds_run_kernel(ConvArgs a, int ti
             }
             *reinterpret_cast<uint4*>(a.out.p + p * a.out.cs + a.out.co + co) = v;
         }
-        if (a.pool.p != nullptr) {
-            // The forward pass's 2 x 2 average of this output tile (tiles start at even
-            // pixels, the map sides are even), its four terms added in the order of the
-            // pooling kernel, so the pooled map is the same bit for bit.
-            static_assert(TH % 2 == 0 && LT_W % 2 == 0, "pooled tiles need even sides");
-            for (int q = threadIdx.x; q < (TH / 2) * (LT_W / 2) * (CO_B / 8); q += 256) {
-                const int pp = q / (CO_B / 8), cg = q % (CO_B / 8);
-                const int py = pp / (LT_W / 2), px = pp % (LT_W / 2);
-                const int y = y0 + 2 * py, x = x0 + 2 * px, co = co_base + 8 * cg;
-                if (y >= a.H || x >= a.W || co >= a.cout) continue;
-                float sum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                for (int dy = 0; dy < 2; ++dy)
-                    for (int dx = 0; dx < 2; ++dx) {
-                        const uint4 v =
-                            *reinterpret_cast<const uint4*>(ost + ((2 * py + dy) * LT_W + 2 * px + dx) * CO_B + 8 * cg);
-                        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            sum[2 * k] += bf2f(uint16_t(w[k]));
-                            sum[2 * k + 1] += bf2f(uint16_t(w[k] >> 16));
-                        }
-                    }
-                uint32_t o[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    o[k] = uint32_t(f2bf(0.25f * sum[2 * k])) | (uint32_t(f2bf(0.25f * sum[2 * k + 1])) << 16);
-                const long long pq = ((long long)img * (a.H / 2) + y / 2) * (a.W / 2) + x / 2;
-                *reinterpret_cast<uint4*>(a.pool.p + pq * a.pool.cs + a.pool.co + co) = make_uint4(o[0], o[1], o[2], o[3]);
-            }
-        }
+        if (a.pool.p != nullptr) pool_tile<TH, CO_B>(a, ost, img, y0, x0, co_base);
     }
 }
 
@@ -1414,9 +1419,9 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
     // 64^2 of 96 channels 18 -> 27 us with runs)
     const bool run = a.cout_p % 32 == 0 && (a.epi == EPI_F32 || views8) && a.cin_p % 32 == 0 && a.H >= 16 &&
                      (ncb == 1 || (ncb >= 3 && a.H >= 128) || ncb >= 5);
-    if (a.pool.p != nullptr &&
-        !(run && a.epi == EPI_RELU_BF16 && a.H % 2 == 0 && a.W % 2 == 0 && a.pool.cs % 8 == 0 && a.pool.co % 8 == 0)) {
-        // the run kernel pools in its epilogue; any other layer is pooled afterwards
+    if (a.pool.p != nullptr && !(a.epi == EPI_RELU_BF16 && a.cout_p % 32 == 0 && views8 && a.H % 2 == 0 &&
+                                 a.W % 2 == 0 && a.pool.cs % 8 == 0 && a.pool.co % 8 == 0)) {
+        // the run and blocked kernels pool in their epilogues; other layers are pooled afterwards
         ConvArgs b = a;
         b.pool = TView{nullptr, 0, 0};
         const hipError_t e = conv3x3(b, s);
