@@ -126,7 +126,7 @@ void release(sur_net* n) {
 TView tv(uint16_t* p, int cs, int co = 0) { return TView{p, cs, co}; }
 
 hipError_t conv(sur_net* n, int li, TView in, int N, int H, int W, int epi, TView out, float* out_f32 = nullptr,
-                int out_f32_cs = 0, TView pool = TView{nullptr, 0, 0}) {
+                int out_f32_cs = 0, TView pool = TView{nullptr, 0, 0}, TView up = TView{nullptr, 0, 0}) {
     const Layer& l = n->L[li];
     ConvArgs a{};
     a.in = in;
@@ -144,6 +144,7 @@ hipError_t conv(sur_net* n, int li, TView in, int N, int H, int W, int epi, TVie
     a.cout_p = l.cout_p;
     a.epi = epi;
     a.pool = pool;
+    a.up = up;
     return conv3x3(a, n->stream);
 }
 
@@ -232,14 +233,16 @@ lbm_status forward(sur_net* n, int N) {
     SUR_TRY(conv(n, E2A, tv(n->p1, L1), N, S2, S2, EPI_RELU_BF16, tv(n->e2a, L2)));
     SUR_TRY(conv(n, E2B, tv(n->e2a, L2), N, S2, S2, EPI_RELU_BF16, tv(n->c2, L3 + L2, L3), nullptr, 0, tv(n->p2, L2)));
     SUR_TRY(conv(n, E3A, tv(n->p2, L2), N, S3, S3, EPI_RELU_BF16, tv(n->e3a, L3)));
-    SUR_TRY(conv(n, E3B, tv(n->e3a, L3), N, S3, S3, EPI_RELU_BF16, tv(n->e3, L3)));
-    SUR_TRY(upsample2(tv(n->e3, L3), tv(n->c2, L3 + L2, 0), N, S2, S2, L3, n->stream));
+    // the last encoder and the decoders' second convolutions also write their output
+    // repeated 2 x 2 into the next level's concatenation
+    SUR_TRY(conv(n, E3B, tv(n->e3a, L3), N, S3, S3, EPI_RELU_BF16, tv(n->e3, L3), nullptr, 0, TView{nullptr, 0, 0},
+                 tv(n->c2, L3 + L2, 0)));
     SUR_TRY(conv(n, D2A, tv(n->c2, L3 + L2), N, S2, S2, EPI_RELU_BF16, tv(n->d2a, L2)));
-    SUR_TRY(conv(n, D2B, tv(n->d2a, L2), N, S2, S2, EPI_RELU_BF16, tv(n->d2, L2)));
-    SUR_TRY(upsample2(tv(n->d2, L2), tv(n->c1, L2 + L1, 0), N, S1, S1, L2, n->stream));
+    SUR_TRY(conv(n, D2B, tv(n->d2a, L2), N, S2, S2, EPI_RELU_BF16, tv(n->d2, L2), nullptr, 0, TView{nullptr, 0, 0},
+                 tv(n->c1, L2 + L1, 0)));
     SUR_TRY(conv(n, D1A, tv(n->c1, L2 + L1), N, S1, S1, EPI_RELU_BF16, tv(n->d1a, L1)));
-    SUR_TRY(conv(n, D1B, tv(n->d1a, L1), N, S1, S1, EPI_RELU_BF16, tv(n->d1, L1)));
-    SUR_TRY(upsample2(tv(n->d1, L1), tv(n->c0, L1 + L0, 0), N, S0, S0, L1, n->stream));
+    SUR_TRY(conv(n, D1B, tv(n->d1a, L1), N, S1, S1, EPI_RELU_BF16, tv(n->d1, L1), nullptr, 0, TView{nullptr, 0, 0},
+                 tv(n->c0, L1 + L0, 0)));
     SUR_TRY(conv(n, D0A, tv(n->c0, L1 + L0), N, S0, S0, EPI_RELU_BF16, tv(n->d0a, L0)));
     SUR_TRY(conv(n, D0B, tv(n->d0a, L0), N, S0, S0, EPI_RELU_BF16, tv(n->d0, L0)));
     SUR_TRY(conv(n, OUT, tv(n->d0, L0), N, S0, S0, EPI_F32, tv(nullptr, 0), n->y, 1));

@@ -35,6 +35,7 @@ struct ConvArgs {
     int cout, cout_p;    // output channels stored, padded (multiple of 16)
     int epi;
     TView pool;          // EPI_RELU_BF16: the 2 x 2 average of the output at half size (p null: none)
+    TView up;            // EPI_RELU_BF16: the output repeated 2 x 2 at twice the size (p null: none)
 };
 
 struct WgradArgs {

@@ -320,6 +320,23 @@ __device__ __forceinline__ void pool_tile(const ConvArgs& a, const uint16_t* ost
     }
 }
 
+// The decoder's upsampled copy of a BF16 output tile staged in LDS: each pixel's
+// channels repeated over its 2 x 2 block of the map at twice the size.
+template <int TH, int CO_B>
+__device__ __forceinline__ void upsample_tile(const ConvArgs& a, const uint16_t* ost, int img, int y0, int x0,
+                                              int co_base) {
+    const int H2 = 2 * a.H, W2 = 2 * a.W;
+    for (int q = threadIdx.x; q < TH * LT_W * 4 * (CO_B / 8); q += blockDim.x) {
+        const int cg = q % (CO_B / 8), rest = q / (CO_B / 8);
+        const int d = rest & 3, pl = rest >> 2;
+        const int y = y0 + pl / LT_W, x = x0 + pl % LT_W, co = co_base + 8 * cg;
+        if (y >= a.H || x >= a.W || co >= a.cout) continue;
+        const uint4 v = *reinterpret_cast<const uint4*>(ost + pl * CO_B + 8 * cg);
+        const long long pu = ((long long)img * H2 + 2 * y + (d >> 1)) * W2 + 2 * x + (d & 1);
+        *reinterpret_cast<uint4*>(a.up.p + pu * a.up.cs + a.up.co + co) = v;
+    }
+}
+
 template <int RW, int CO_B>
 __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
     using K = LdsConv<RW, CO_B>;
@@ -427,6 +444,7 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
             *reinterpret_cast<uint4*>(a.out.p + p * a.out.cs + a.out.co + co) = v;
         }
         if (a.pool.p != nullptr) pool_tile<TH, CO_B>(a, ost, img, y0, x0, co_base);
+        if (a.up.p != nullptr) upsample_tile<TH, CO_B>(a, ost, img, y0, x0, co_base);
         return;
     }
 
@@ -666,6 +684,7 @@ __global__ __launch_bounds__(256) void conv3x3_lds_run_kernel(ConvArgs a, int ti
             *reinterpret_cast<uint4*>(a.out.p + p * a.out.cs + a.out.co + co) = v;
         }
         if (a.pool.p != nullptr) pool_tile<TH, CO_B>(a, ost, img, y0, x0, co_base);
+        if (a.up.p != nullptr) upsample_tile<TH, CO_B>(a, ost, img, y0, x0, co_base);
     }
 }
 
@@ -1419,14 +1438,20 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
     // 64^2 of 96 channels 18 -> 27 us with runs)
     const bool run = a.cout_p % 32 == 0 && (a.epi == EPI_F32 || views8) && a.cin_p % 32 == 0 && a.H >= 16 &&
                      (ncb == 1 || (ncb >= 3 && a.H >= 128) || ncb >= 5);
-    if (a.pool.p != nullptr && !(a.epi == EPI_RELU_BF16 && a.cout_p % 32 == 0 && views8 && a.H % 2 == 0 &&
-                                 a.W % 2 == 0 && a.pool.cs % 8 == 0 && a.pool.co % 8 == 0)) {
-        // the run and blocked kernels pool in their epilogues; other layers are pooled afterwards
+    // the run and blocked kernels write the pooled and upsampled copies in their
+    // epilogues; for other layers separate passes follow
+    const bool fuse = a.epi == EPI_RELU_BF16 && a.cout_p % 32 == 0 && views8;
+    const bool pool_ok = a.pool.p == nullptr || (fuse && a.H % 2 == 0 && a.W % 2 == 0 && a.pool.cs % 8 == 0 &&
+                                                 a.pool.co % 8 == 0);
+    const bool up_ok = a.up.p == nullptr || (fuse && a.up.cs % 8 == 0 && a.up.co % 8 == 0);
+    if (!pool_ok || !up_ok) {
         ConvArgs b = a;
-        b.pool = TView{nullptr, 0, 0};
-        const hipError_t e = conv3x3(b, s);
-        if (e != hipSuccess) return e;
-        return avgpool2(a.out, a.pool, a.N, a.H, a.W, a.cout, s);
+        if (!pool_ok) b.pool = TView{nullptr, 0, 0};
+        if (!up_ok) b.up = TView{nullptr, 0, 0};
+        hipError_t e = conv3x3(b, s);
+        if (e == hipSuccess && !pool_ok) e = avgpool2(a.out, a.pool, a.N, a.H, a.W, a.cout, s);
+        if (e == hipSuccess && !up_ok) e = upsample2(a.out, a.up, a.N, 2 * a.H, 2 * a.W, a.cout, s);
+        return e;
     }
     auto blocks_of = [&](int th, int co_b) {
         return (long long)a.N * ((a.H + th - 1) / th) * ((a.W + LT_W - 1) / LT_W) * (a.cout_p / co_b);
