@@ -150,7 +150,8 @@ hipError_t conv(sur_net* n, int li, TView in, int N, int H, int W, int epi, TVie
 
 // Input gradient of layer li: the flipped convolution of dz (its output gradient).
 hipError_t conv_back(sur_net* n, int li, TView dz, int N, int H, int W, int epi, TView out, TView mask,
-                     float* out_f32 = nullptr, int out_f32_cs = 0) {
+                     float* out_f32 = nullptr, int out_f32_cs = 0, TView fold = TView{nullptr, 0, 0},
+                     TView fold_act = TView{nullptr, 0, 0}, int fold_c = 0) {
     const Layer& l = n->L[li];
     ConvArgs a{};
     a.in = dz;
@@ -170,6 +171,9 @@ hipError_t conv_back(sur_net* n, int li, TView dz, int N, int H, int W, int epi,
     a.cout = l.d.cin;
     a.cout_p = l.t_cout_p;
     a.epi = epi;
+    a.fold = fold;
+    a.fold_act = fold_act;
+    a.fold_c = fold_c;
     return conv3x3(a, n->stream);
 }
 
@@ -265,21 +269,24 @@ lbm_status backward(sur_net* n, int N, double* loss) {
     SUR_TRY(wgrad(n, D0B, tv(n->d0a, L0), tv(A, L0), N, S0, S0));
     SUR_TRY(conv_back(n, D0B, tv(A, L0), N, S0, S0, EPI_MASK_BF16, tv(B, L0), tv(n->d0a, L0)));
     SUR_TRY(wgrad(n, D0A, tv(n->c0, L1 + L0), tv(B, L0), N, S0, S0));
-    SUR_TRY(conv_back(n, D0A, tv(B, L0), N, S0, S0, EPI_F32, none, none, n->dc0, L1 + L0));
+    // the input gradients of the decoders' first convolutions also give the upsampling
+    // gradient of the level below (its share of the concatenation summed over 2 x 2
+    // blocks, masked by the ReLU of the upsampled activation)
+    SUR_TRY(conv_back(n, D0A, tv(B, L0), N, S0, S0, EPI_F32, none, none, n->dc0, L1 + L0, tv(A, L1), tv(n->d1, L1),
+                      L1));
     // level 1 decoder
-    SUR_TRY(upsample2_grad(n->dc0, L1 + L0, 0, tv(n->d1, L1), tv(A, L1), N, S1, S1, L1, n->stream));
     SUR_TRY(wgrad(n, D1B, tv(n->d1a, L1), tv(A, L1), N, S1, S1));
     SUR_TRY(conv_back(n, D1B, tv(A, L1), N, S1, S1, EPI_MASK_BF16, tv(B, L1), tv(n->d1a, L1)));
     SUR_TRY(wgrad(n, D1A, tv(n->c1, L2 + L1), tv(B, L1), N, S1, S1));
-    SUR_TRY(conv_back(n, D1A, tv(B, L1), N, S1, S1, EPI_F32, none, none, n->dc1, L2 + L1));
+    SUR_TRY(conv_back(n, D1A, tv(B, L1), N, S1, S1, EPI_F32, none, none, n->dc1, L2 + L1, tv(A, L2), tv(n->d2, L2),
+                      L2));
     // level 2 decoder
-    SUR_TRY(upsample2_grad(n->dc1, L2 + L1, 0, tv(n->d2, L2), tv(A, L2), N, S2, S2, L2, n->stream));
     SUR_TRY(wgrad(n, D2B, tv(n->d2a, L2), tv(A, L2), N, S2, S2));
     SUR_TRY(conv_back(n, D2B, tv(A, L2), N, S2, S2, EPI_MASK_BF16, tv(B, L2), tv(n->d2a, L2)));
     SUR_TRY(wgrad(n, D2A, tv(n->c2, L3 + L2), tv(B, L2), N, S2, S2));
-    SUR_TRY(conv_back(n, D2A, tv(B, L2), N, S2, S2, EPI_F32, none, none, n->dc2, L3 + L2));
+    SUR_TRY(conv_back(n, D2A, tv(B, L2), N, S2, S2, EPI_F32, none, none, n->dc2, L3 + L2, tv(A, L3), tv(n->e3, L3),
+                      L3));
     // bottleneck
-    SUR_TRY(upsample2_grad(n->dc2, L3 + L2, 0, tv(n->e3, L3), tv(A, L3), N, S3, S3, L3, n->stream));
     SUR_TRY(wgrad(n, E3B, tv(n->e3a, L3), tv(A, L3), N, S3, S3));
     SUR_TRY(conv_back(n, E3B, tv(A, L3), N, S3, S3, EPI_MASK_BF16, tv(B, L3), tv(n->e3a, L3)));
     SUR_TRY(wgrad(n, E3A, tv(n->p2, L2), tv(B, L3), N, S3, S3));

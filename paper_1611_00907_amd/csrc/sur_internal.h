@@ -36,6 +36,12 @@ struct ConvArgs {
     int epi;
     TView pool;          // EPI_RELU_BF16: the 2 x 2 average of the output at half size (p null: none)
     TView up;            // EPI_RELU_BF16: the output repeated 2 x 2 at twice the size (p null: none)
+    // EPI_F32 without bias: channels [0, fold_c) of the output summed over 2 x 2 pixel
+    // blocks, zeroed where fold_act is not > 0, into fold (BF16, half size): the
+    // upsampling gradient (p null: none).  A kernel that folds does not store those
+    // channels of out_f32; one that cannot leaves the fold to a separate pass.
+    TView fold, fold_act;
+    int fold_c;
 };
 
 struct WgradArgs {

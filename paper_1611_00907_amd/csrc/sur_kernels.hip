@@ -618,6 +618,8 @@ __global__ __launch_bounds__(256) void conv3x3_lds_run_kernel(ConvArgs a, int ti
             // 64 bytes instead of one float per lane and store
             float* of = reinterpret_cast<float*>(ost);
             const bool vec = (a.out_f32_cs & 3) == 0;
+            // channels folded into the upsampling gradient are not stored themselves
+            const bool fold = a.fold.p != nullptr && co_base + CO_B <= a.fold_c;
 #pragma unroll
             for (int n = 0; n < NB; ++n) {
                 // lane holds pixels (RW wave + m, 4 g + i) of the tile, channel 16 n + r
@@ -626,7 +628,7 @@ __global__ __launch_bounds__(256) void conv3x3_lds_run_kernel(ConvArgs a, int ti
 #pragma unroll
                     for (int i = 0; i < 4; ++i) of[((RW * wave + m) * LT_W + 4 * g + i) * 16 + r] = acc[m][n][i];
                 __syncthreads();  // this half is in place (and every wave is done with the halo)
-                for (int q = threadIdx.x; q < TH * LT_W * 4; q += 256) {
+                for (int q = threadIdx.x; q < (fold ? 0 : TH * LT_W * 4); q += 256) {
                     const int pl = q >> 2, c4 = q & 3;
                     const int y = y0 + pl / LT_W, x = x0 + pl % LT_W, co = co_base + 16 * n + 4 * c4;
                     if (y >= a.H || x >= a.W || co >= a.cout) continue;
@@ -643,6 +645,38 @@ __global__ __launch_bounds__(256) void conv3x3_lds_run_kernel(ConvArgs a, int ti
                     } else {
                         const float e[4] = {v.x, v.y, v.z, v.w};
                         for (int k = 0; k < 4 && co + k < a.cout; ++k) dst[k] = e[k];
+                    }
+                }
+                if (fold) {
+                    // the upsampling gradient of these channels: sums over 2 x 2 pixel
+                    // blocks (no bias; terms in the order of the separate kernel), masked
+                    for (int q = threadIdx.x; q < (TH / 2) * (LT_W / 2) * 4; q += 256) {
+                        const int pp = q >> 2, c4 = q & 3;
+                        const int py = pp / (LT_W / 2), px = pp % (LT_W / 2);
+                        const int y = y0 + 2 * py, x = x0 + 2 * px, co = co_base + 16 * n + 4 * c4;
+                        if (y >= a.H || x >= a.W || co >= a.cout) continue;
+                        float sum[4] = {0.f, 0.f, 0.f, 0.f};
+                        for (int dy = 0; dy < 2; ++dy)
+                            for (int dx = 0; dx < 2; ++dx) {
+                                const float4 v = *reinterpret_cast<const float4*>(
+                                    of + ((2 * py + dy) * LT_W + 2 * px + dx) * 16 + 4 * c4);
+                                sum[0] += v.x;
+                                sum[1] += v.y;
+                                sum[2] += v.z;
+                                sum[3] += v.w;
+                            }
+                        const long long pq = ((long long)img * (a.H / 2) + y / 2) * (a.W / 2) + x / 2;
+                        const uint2 mk =
+                            *reinterpret_cast<const uint2*>(a.fold_act.p + pq * a.fold_act.cs + a.fold_act.co + co);
+                        const uint32_t mw[2] = {mk.x, mk.y};
+                        uint32_t o[2];
+#pragma unroll
+                        for (int k = 0; k < 2; ++k) {
+                            const float lo = bf2f(uint16_t(mw[k])) > 0.f ? sum[2 * k] : 0.f;
+                            const float hi = bf2f(uint16_t(mw[k] >> 16)) > 0.f ? sum[2 * k + 1] : 0.f;
+                            o[k] = uint32_t(f2bf(lo)) | (uint32_t(f2bf(hi)) << 16);
+                        }
+                        *reinterpret_cast<uint2*>(a.fold.p + pq * a.fold.cs + a.fold.co + co) = make_uint2(o[0], o[1]);
                     }
                 }
                 __syncthreads();  // the area is free for the next half (or the next tile's halo)
@@ -1444,13 +1478,21 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
     const bool pool_ok = a.pool.p == nullptr || (fuse && a.H % 2 == 0 && a.W % 2 == 0 && a.pool.cs % 8 == 0 &&
                                                  a.pool.co % 8 == 0);
     const bool up_ok = a.up.p == nullptr || (fuse && a.up.cs % 8 == 0 && a.up.co % 8 == 0);
-    if (!pool_ok || !up_ok) {
+    // the run kernel folds the upsampling gradient into its FP32 epilogue
+    const bool fold_ok = a.fold.p == nullptr ||
+                         (run && a.epi == EPI_F32 && a.bias == nullptr && a.H % 2 == 0 && a.W % 2 == 0 &&
+                          a.fold_c % 32 == 0 && a.fold_c <= a.cout && a.fold.cs % 4 == 0 && a.fold.co % 4 == 0 &&
+                          a.fold_act.cs % 4 == 0 && a.fold_act.co % 4 == 0);
+    if (!pool_ok || !up_ok || !fold_ok) {
         ConvArgs b = a;
         if (!pool_ok) b.pool = TView{nullptr, 0, 0};
         if (!up_ok) b.up = TView{nullptr, 0, 0};
+        if (!fold_ok) b.fold = TView{nullptr, 0, 0};
         hipError_t e = conv3x3(b, s);
         if (e == hipSuccess && !pool_ok) e = avgpool2(a.out, a.pool, a.N, a.H, a.W, a.cout, s);
         if (e == hipSuccess && !up_ok) e = upsample2(a.out, a.up, a.N, 2 * a.H, 2 * a.W, a.cout, s);
+        if (e == hipSuccess && !fold_ok)
+            e = upsample2_grad(a.out_f32, a.out_f32_cs, 0, a.fold_act, a.fold, a.N, a.H / 2, a.W / 2, a.fold_c, s);
         return e;
     }
     auto blocks_of = [&](int th, int co_b) {

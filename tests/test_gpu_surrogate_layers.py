@@ -15,7 +15,8 @@ with 2^-24 and 2^-8 the unit roundoffs of FP32 and of BF16 (8-bit significand),
 S the same sum over absolute values (sum |w| |x| + |b|) and K the number of
 FP32 additions behind the element: 9 c_in (padded) for a convolution, 9 c_out
 (padded) for its input gradient, a workgroup's run of pixels plus the runs' atomic
-additions for a weight gradient, 3 for pooling and the upsampling gradient.  Copies (upsampling
+additions for a weight gradient, 3 for pooling, and for the upsampling gradient (summed from
+the FP32 input gradient inside the kernel that computes it) that input gradient's plus 3.  Copies (upsampling
 into the concatenations) must be exact.  A misplaced tile, halo column, channel
 pair or pixel run changes elements by the size of the values themselves, far
 beyond these bounds.
@@ -171,18 +172,24 @@ def test_input_gradient_through_relu(run, layer, dzn, maskn, dst):
     check("input gradient " + layer, T[dst], ref, scale, 9 * _pad(w.shape[0], 32), bf16_out=True)
 
 
-# input gradients kept in FP32: the concatenations' and the pooled branches'
-F32_BACK = [("d0a", "dz_d0a", "dc0"), ("d1a", "dz_d1a", "dc1"), ("d2a", "dz_d2a", "dc2"),
-            ("e3a", "dz_e3a", "dp_e3a"), ("e2a", "dz_e2a", "dp_e2a"), ("e1a", "dz_e1a", "dp_e1a")]
+# input gradients kept in FP32: the concatenations' and the pooled branches'.  The
+# first decoder level's input gradient stores only its skip share: the kernel that
+# computes it folds the upsampled share into the upsampling gradient at once (checked
+# below from the oracle's own input gradient).
+F32_BACK = [("d0a", "dz_d0a", "dc0", (64, 96)), ("d1a", "dz_d1a", "dc1", None), ("d2a", "dz_d2a", "dc2", None),
+            ("e3a", "dz_e3a", "dp_e3a", None), ("e2a", "dz_e2a", "dp_e2a", None), ("e1a", "dz_e1a", "dp_e1a", None)]
 
 
-@pytest.mark.parametrize("layer,dzn,dst", F32_BACK, ids=[m[0] for m in F32_BACK])
-def test_input_gradient_fp32(run, layer, dzn, dst):
+@pytest.mark.parametrize("layer,dzn,dst,ch", F32_BACK, ids=[m[0] for m in F32_BACK])
+def test_input_gradient_fp32(run, layer, dzn, dst, ch):
     T, (w, _) = run["T"], run["W"][layer]
     dz = T[dzn]
     ref = S.conv3x3_grad_input(dz, w)
     scale = S.conv3x3_grad_input(np.abs(dz), np.abs(w))
-    check("input gradient " + layer, T[dst], ref, scale, 9 * _pad(w.shape[0], 32), bf16_out=False)
+    got = T[dst]
+    if ch is not None:
+        got, ref, scale = got[:, ch[0]:ch[1]], ref[:, ch[0]:ch[1]], scale[:, ch[0]:ch[1]]
+    check("input gradient " + layer, got, ref, scale, 9 * _pad(w.shape[0], 32), bf16_out=False)
 
 
 def test_pooling_and_upsampling(run):
@@ -196,16 +203,21 @@ def test_pooling_and_upsampling(run):
         assert np.array_equal(T[dst][:, :ch], S.upsample2(T[src])), "upsample " + src
 
 
-UP_GRAD = [("dc0", 64, "d1", "dz_d1b"), ("dc1", 96, "d2", "dz_d2b"), ("dc2", 128, "e3", "dz_e3b")]
+UP_GRAD = [("d0a", "dz_d0a", 64, "d1", "dz_d1b"), ("d1a", "dz_d1a", 96, "d2", "dz_d2b"),
+           ("d2a", "dz_d2a", 128, "e3", "dz_e3b")]
 
 
-@pytest.mark.parametrize("dcat,ch,act,dst", UP_GRAD, ids=[u[3] for u in UP_GRAD])
-def test_upsampling_gradient(run, dcat, ch, act, dst):
-    T = run["T"]
-    d = T[dcat][:, :ch]
+@pytest.mark.parametrize("layer,dzn,ch,act,dst", UP_GRAD, ids=[u[4] for u in UP_GRAD])
+def test_upsampling_gradient(run, layer, dzn, ch, act, dst):
+    """The upsampled share of a decoder's FP32 input gradient summed over 2 x 2 blocks
+    and masked, from the oracle's input gradient of the stored BF16 operands: the
+    convolution's additions plus 3."""
+    T, (w, _) = run["T"], run["W"][layer]
+    dz = T[dzn]
     keep = T[act] > 0
-    ref = S.upsample2_grad(d) * keep
-    check("upsampling gradient " + dst, T[dst], ref, S.upsample2_grad(np.abs(d)) * keep, 3, bf16_out=True)
+    ref = S.upsample2_grad(S.conv3x3_grad_input(dz, w)[:, :ch]) * keep
+    scale = S.upsample2_grad(S.conv3x3_grad_input(np.abs(dz), np.abs(w))[:, :ch]) * keep
+    check("upsampling gradient " + dst, T[dst], ref, scale, 9 * _pad(w.shape[0], 32) + 3, bf16_out=True)
 
 
 SKIP_GRAD = [("dc2", (128, 224), "dp_e3a", ("c2", (128, 224)), "dz_e2b"),
