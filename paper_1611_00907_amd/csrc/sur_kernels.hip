@@ -337,6 +337,42 @@ __device__ __forceinline__ void upsample_tile(const ConvArgs& a, const uint16_t*
     }
 }
 
+// The upsampling gradient from one 16-channel half of an FP32 output tile staged in
+// LDS as [TH x LT_W pixels][16] (no bias; output channels co0 ..): sums over 2 x 2
+// pixel blocks, their terms in the order of the separate kernel, zeroed where the
+// upsampled activation is not > 0, rounded to BF16 at half size.
+template <int TH>
+__device__ __forceinline__ void fold_half(const ConvArgs& a, const float* of, int img, int y0, int x0, int co0) {
+    static_assert(TH % 2 == 0 && LT_W % 2 == 0, "folded tiles need even sides");
+    for (int q = threadIdx.x; q < (TH / 2) * (LT_W / 2) * 4; q += blockDim.x) {
+        const int pp = q >> 2, c4 = q & 3;
+        const int py = pp / (LT_W / 2), px = pp % (LT_W / 2);
+        const int y = y0 + 2 * py, x = x0 + 2 * px, co = co0 + 4 * c4;
+        if (y >= a.H || x >= a.W || co >= a.cout) continue;
+        float sum[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const float4 v =
+                    *reinterpret_cast<const float4*>(of + ((2 * py + dy) * LT_W + 2 * px + dx) * 16 + 4 * c4);
+                sum[0] += v.x;
+                sum[1] += v.y;
+                sum[2] += v.z;
+                sum[3] += v.w;
+            }
+        const long long pq = ((long long)img * (a.H / 2) + y / 2) * (a.W / 2) + x / 2;
+        const uint2 mk = *reinterpret_cast<const uint2*>(a.fold_act.p + pq * a.fold_act.cs + a.fold_act.co + co);
+        const uint32_t mw[2] = {mk.x, mk.y};
+        uint32_t o[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const float lo = bf2f(uint16_t(mw[k])) > 0.f ? sum[2 * k] : 0.f;
+            const float hi = bf2f(uint16_t(mw[k] >> 16)) > 0.f ? sum[2 * k + 1] : 0.f;
+            o[k] = uint32_t(f2bf(lo)) | (uint32_t(f2bf(hi)) << 16);
+        }
+        *reinterpret_cast<uint2*>(a.fold.p + pq * a.fold.cs + a.fold.co + co) = make_uint2(o[0], o[1]);
+    }
+}
+
 template <int RW, int CO_B>
 __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
     using K = LdsConv<RW, CO_B>;
@@ -453,6 +489,8 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
     static_assert(TH * LT_W * 16 * 2 <= K::XIN + K::WSH, "16 FP32 channels of the tile fit the staging space");
     float* of = reinterpret_cast<float*>(lds);
     const bool vec = (a.out_f32_cs & 3) == 0;
+    // channels folded into the upsampling gradient are not stored themselves
+    const bool fold = a.fold.p != nullptr && co_base + CO_B <= a.fold_c;
 #pragma unroll
     for (int n = 0; n < NB; ++n) {
         if (n > 0) __syncthreads();  // the previous half is stored
@@ -462,7 +500,8 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) of[((RW * wave + m) * LT_W + 4 * g + i) * 16 + r] = acc[m][n][i];
         __syncthreads();
-        for (int q = threadIdx.x; q < TH * LT_W * 4; q += 256) {
+        if (fold) fold_half<TH>(a, of, img, y0, x0, co_base + 16 * n);
+        for (int q = threadIdx.x; q < (fold ? 0 : TH * LT_W * 4); q += 256) {
             const int pl = q >> 2, c4 = q & 3;
             const int y = y0 + pl / LT_W, x = x0 + pl % LT_W, co = co_base + 16 * n + 4 * c4;
             if (y >= a.H || x >= a.W || co >= a.cout) continue;
@@ -647,38 +686,7 @@ __global__ __launch_bounds__(256) void conv3x3_lds_run_kernel(ConvArgs a, int ti
                         for (int k = 0; k < 4 && co + k < a.cout; ++k) dst[k] = e[k];
                     }
                 }
-                if (fold) {
-                    // the upsampling gradient of these channels: sums over 2 x 2 pixel
-                    // blocks (no bias; terms in the order of the separate kernel), masked
-                    for (int q = threadIdx.x; q < (TH / 2) * (LT_W / 2) * 4; q += 256) {
-                        const int pp = q >> 2, c4 = q & 3;
-                        const int py = pp / (LT_W / 2), px = pp % (LT_W / 2);
-                        const int y = y0 + 2 * py, x = x0 + 2 * px, co = co_base + 16 * n + 4 * c4;
-                        if (y >= a.H || x >= a.W || co >= a.cout) continue;
-                        float sum[4] = {0.f, 0.f, 0.f, 0.f};
-                        for (int dy = 0; dy < 2; ++dy)
-                            for (int dx = 0; dx < 2; ++dx) {
-                                const float4 v = *reinterpret_cast<const float4*>(
-                                    of + ((2 * py + dy) * LT_W + 2 * px + dx) * 16 + 4 * c4);
-                                sum[0] += v.x;
-                                sum[1] += v.y;
-                                sum[2] += v.z;
-                                sum[3] += v.w;
-                            }
-                        const long long pq = ((long long)img * (a.H / 2) + y / 2) * (a.W / 2) + x / 2;
-                        const uint2 mk =
-                            *reinterpret_cast<const uint2*>(a.fold_act.p + pq * a.fold_act.cs + a.fold_act.co + co);
-                        const uint32_t mw[2] = {mk.x, mk.y};
-                        uint32_t o[2];
-#pragma unroll
-                        for (int k = 0; k < 2; ++k) {
-                            const float lo = bf2f(uint16_t(mw[k])) > 0.f ? sum[2 * k] : 0.f;
-                            const float hi = bf2f(uint16_t(mw[k] >> 16)) > 0.f ? sum[2 * k + 1] : 0.f;
-                            o[k] = uint32_t(f2bf(lo)) | (uint32_t(f2bf(hi)) << 16);
-                        }
-                        *reinterpret_cast<uint2*>(a.fold.p + pq * a.fold.cs + a.fold.co + co) = make_uint2(o[0], o[1]);
-                    }
-                }
+                if (fold) fold_half<TH>(a, of, img, y0, x0, co_base + 16 * n);
                 __syncthreads();  // the area is free for the next half (or the next tile's halo)
             }
             continue;
@@ -1470,18 +1478,32 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
     // output blocks (measured per layer: 256^2 of 96 channels 128 -> 113 us,
     // 128^2 of 160 channels 94 -> 80 us, but 128^2 of 64 channels 43 -> 47 us and
     // 64^2 of 96 channels 18 -> 27 us with runs)
-    const bool run = a.cout_p % 32 == 0 && (a.epi == EPI_F32 || views8) && a.cin_p % 32 == 0 && a.H >= 16 &&
-                     (ncb == 1 || (ncb >= 3 && a.H >= 128) || ncb >= 5);
+    const bool big = a.cout_p % 32 == 0 && (a.epi == EPI_F32 || views8);  // the run or a blocked kernel
+    const bool run = big && a.cin_p % 32 == 0 && a.H >= 16 && (ncb == 1 || (ncb >= 3 && a.H >= 128) || ncb >= 5);
+    auto blocks_of = [&](int th, int co_b) {
+        return (long long)a.N * ((a.H + th - 1) / th) * ((a.W + LT_W - 1) / LT_W) * (a.cout_p / co_b);
+    };
+    // the blocked kernel's channel block: the widest (each staged halo then serves more
+    // output channels) that still gives at least 1024 workgroups (64 or 96 channels, 4
+    // rows per wave), else 32 channels with 4 rows per wave if that gives 512, else with
+    // 2 (measured: a 64^2 layer of 96 channels takes 46 us as one 96-channel block of
+    // 256 workgroups, 32 us as three 32-channel blocks of 4 rows per wave, 37 us of 2)
+    constexpr long long ENOUGH = 1024;
+    const long long b64 = a.cout_p % 64 == 0 ? blocks_of(LdsConv<4, 64>::TH, 64) : 0;
+    const long long b96 = a.cout_p % 96 == 0 ? blocks_of(LdsConv<4, 96>::TH, 96) : 0;
+    const long long b32 = blocks_of(LdsConv<4, 32>::TH, 32);
+    const int co_b = run ? 32 : b64 >= ENOUGH ? 64 : b96 >= ENOUGH ? 96 : 32;
     // the run and blocked kernels write the pooled and upsampled copies in their
     // epilogues; for other layers separate passes follow
-    const bool fuse = a.epi == EPI_RELU_BF16 && a.cout_p % 32 == 0 && views8;
+    const bool fuse = a.epi == EPI_RELU_BF16 && big;
     const bool pool_ok = a.pool.p == nullptr || (fuse && a.H % 2 == 0 && a.W % 2 == 0 && a.pool.cs % 8 == 0 &&
                                                  a.pool.co % 8 == 0);
     const bool up_ok = a.up.p == nullptr || (fuse && a.up.cs % 8 == 0 && a.up.co % 8 == 0);
-    // the run kernel folds the upsampling gradient into its FP32 epilogue
+    // and fold the upsampling gradient into their FP32 epilogues when whole channel
+    // blocks are folded
     const bool fold_ok = a.fold.p == nullptr ||
-                         (run && a.epi == EPI_F32 && a.bias == nullptr && a.H % 2 == 0 && a.W % 2 == 0 &&
-                          a.fold_c % 32 == 0 && a.fold_c <= a.cout && a.fold.cs % 4 == 0 && a.fold.co % 4 == 0 &&
+                         (big && a.epi == EPI_F32 && a.bias == nullptr && a.H % 2 == 0 && a.W % 2 == 0 &&
+                          a.fold_c % co_b == 0 && a.fold_c <= a.cout && a.fold.cs % 4 == 0 && a.fold.co % 4 == 0 &&
                           a.fold_act.cs % 4 == 0 && a.fold_act.co % 4 == 0);
     if (!pool_ok || !up_ok || !fold_ok) {
         ConvArgs b = a;
@@ -1495,9 +1517,6 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
             e = upsample2_grad(a.out_f32, a.out_f32_cs, 0, a.fold_act, a.fold, a.N, a.H / 2, a.W / 2, a.fold_c, s);
         return e;
     }
-    auto blocks_of = [&](int th, int co_b) {
-        return (long long)a.N * ((a.H + th - 1) / th) * ((a.W + LT_W - 1) / LT_W) * (a.cout_p / co_b);
-    };
     auto lds = [&](auto kernel, int th, int co_b) {
         hipLaunchKernelGGL(kernel, dim3(unsigned(blocks_of(th, co_b))), dim3(256), 0, s, a);
     };
@@ -1506,13 +1525,7 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
         hipLaunchKernelGGL(conv3x3_from1_kernel, dim3(unsigned(tiles)), dim3(256), 0, s, a);
         return hipGetLastError();
     }
-    if (a.cout_p % 32 == 0 && (a.epi == EPI_F32 || views8)) {
-        // the widest channel block (each staged halo then serves more output channels)
-        // that still gives at least 1024 workgroups (64 or 96 channels, 4 rows per wave),
-        // else 32 channels with 4 rows per wave if that gives 512, else with 2 (measured:
-        // a 64^2 layer of 96 channels takes 46 us as one 96-channel block of 256
-        // workgroups, 32 us as three 32-channel blocks of 4 rows per wave, 37 us of 2)
-        constexpr long long ENOUGH = 1024;
+    if (big) {
         if (run) {
             // two workgroups per CU
             const int co_blocks = a.cout_p / 32;
@@ -1525,9 +1538,6 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s) {
                                per_run);
             return hipGetLastError();
         }
-        const long long b64 = a.cout_p % 64 == 0 ? blocks_of(LdsConv<4, 64>::TH, 64) : 0;
-        const long long b96 = a.cout_p % 96 == 0 ? blocks_of(LdsConv<4, 96>::TH, 96) : 0;
-        const long long b32 = blocks_of(LdsConv<4, 32>::TH, 32);
         if (b64 >= ENOUGH)
             lds(conv3x3_lds_kernel<4, 64>, LdsConv<4, 64>::TH, 64);
         else if (b96 >= ENOUGH)

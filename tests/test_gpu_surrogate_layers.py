@@ -172,11 +172,11 @@ def test_input_gradient_through_relu(run, layer, dzn, maskn, dst):
     check("input gradient " + layer, T[dst], ref, scale, 9 * _pad(w.shape[0], 32), bf16_out=True)
 
 
-# input gradients kept in FP32: the concatenations' and the pooled branches'.  The
-# first decoder level's input gradient stores only its skip share: the kernel that
-# computes it folds the upsampled share into the upsampling gradient at once (checked
-# below from the oracle's own input gradient).
-F32_BACK = [("d0a", "dz_d0a", "dc0", (64, 96)), ("d1a", "dz_d1a", "dc1", None), ("d2a", "dz_d2a", "dc2", None),
+# input gradients kept in FP32: the concatenations' and the pooled branches'.  A
+# decoder's input gradient stores only its skip share: the kernel that computes it
+# folds the upsampled share into the upsampling gradient at once (checked below from
+# the oracle's own input gradient).
+F32_BACK = [("d0a", "dz_d0a", "dc0", (64, 96)), ("d1a", "dz_d1a", "dc1", (96, 160)), ("d2a", "dz_d2a", "dc2", (128, 224)),
             ("e3a", "dz_e3a", "dp_e3a", None), ("e2a", "dz_e2a", "dp_e2a", None), ("e1a", "dz_e1a", "dp_e1a", None)]
 
 
