@@ -376,7 +376,10 @@ lbm_status sur_trace(sur_net* n, int32_t on);
  *   forward: x0 (packed input, 16 ch), e0a, c0 ([up(d1) 64 | e0b 32]), p0, e1a,
  *     c1 ([up(d2) 96 | e1b 64]), p1, e2a, c2 ([up(e3) 128 | e2b 96]), p2, e3a, e3,
  *     d2a, d2, d1a, d1, d0a, d0 (BF16), y (FP32 prediction);
- *   backward: dc0, dc1, dc2 (FP32 gradients of the concatenations), and with tracing
+ *   backward: dc0, dc1, dc2 (FP32 gradients of the concatenations; the convolution
+ *     that computes one sums its upsampled share over 2 x 2 blocks into the upsampling
+ *     gradient at once and stores only the skip share, channels L..L+S-1 of a
+ *     concatenation of L upsampled and S skip channels), and with tracing
  *     dz_<layer> for every layer (BF16; dz_out has 16 channels, channel 0 used) and
  *     dp_e3a, dp_e2a, dp_e1a (FP32 input gradients of the first convolution of
  *     levels 3, 2, 1).
